@@ -1,0 +1,154 @@
+"""Benchmark: multilevel link updates per second on one MI355X.
+
+A step is one multilevel configuration (the body of Algorithm 1 of arXiv
+1309.3859 with the workload's levels: sublattice sweeps of 1 heatbath + 3
+overrelaxation passes, measurements, slab averages, slab products and sums)
+over the whole batch of ensembles, with the links already resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2|c3|c1]
+
+Prints one JSON line.  value = non-frozen link updates of K steps / GPU time of
+K steps.  The roofline entry is for the dominant kernel (the overrelaxation
+phase of a spatial direction inside the inner slabs): algorithmic bytes under
+the streaming model (every distinct link angle the phase reads once, every link
+it writes once) divided by its average launch time from HIP events.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(spec, budget_s: float):
+    """Time the FP64 oracle on the host on a bounded sample of the workload:
+    the first ensembles of the batch, one multilevel configuration each with
+    the inner update count cut down, until about budget_s seconds are spent."""
+    from oracle import oracle as O
+
+    O.build()
+    levels = [list(lv) for lv in spec.levels]
+    levels[-1][1] = 2  # two sublattice updates per level instead of the full count
+    if len(levels) == 2:
+        levels[0][1] = 1
+    ospec = O.MLSpec(levels=[tuple(lv) for lv in levels], r=spec.r, dirs=spec.dirs, probes=spec.probes,
+                     comps=spec.comps, n_or=spec.n_or)
+    done_upd, t_used, n_ens = 0, 0.0, 0
+    for e in spec.ensembles:
+        lat = O.Lattice(4, list(e.ns) + [e.nt], e.beta, seed=e.seed, key_id=e.key_id)
+        lat.init(1)
+        V = e.volume
+        t0 = time.perf_counter()
+        lat.multilevel(ospec)
+        dt = time.perf_counter() - t0
+        # non-frozen updates of this configuration
+        ti, ni, ki = levels[-1]
+        sp = lambda tau: V // 2 // e.nt * (e.nt - e.nt // tau)
+        per_sweep = lambda tau: (1 + spec.n_or) * 2 * (V // 2 + 3 * sp(tau))
+        u = ni * ki * per_sweep(ti)
+        if len(levels) == 2:
+            to, no, ko = levels[0]
+            u = no * (ko * per_sweep(to) + ni * ki * per_sweep(ti))
+        done_upd += u
+        t_used += dt
+        n_ens += 1
+        if t_used > budget_s:
+            break
+    return {"value": done_upd / t_used, "unit": "link updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_ens} of {len(spec.ensembles)} ensembles, one multilevel configuration each with "
+                      f"levels {levels} (tau, n_iter, k_sweeps), FP64, single thread; {t_used:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU decomposition is a design "
+              "note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1309_3859_amd import configs, u1ml
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    make = configs.PRESETS[args.workload]
+    spec, sched = make()
+    spec.max_configs = max(1, args.steps + args.warmup)
+    ctx = u1ml.Context(spec)
+    ctx.init_links(sched["start"])
+    tune = ctx.autotune()
+    ctx.sweeps(20)
+    for _ in range(args.warmup):
+        ctx.multilevel()
+    torch.cuda.synchronize()
+    ctx.results()
+    upd = ctx.plan["updates_per_config"]
+
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(ctx.stream)
+    for _ in range(args.steps):
+        ctx.multilevel()
+    stop.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    res = ctx.results()
+    assert res.shape[0] == args.steps
+    value = upd * args.steps / (ms / 1e3)
+
+    # dominant kernel: spatial overrelaxation phase inside inner slabs
+    tau = spec.levels[-1][0]
+    per_phase = {}
+    for kind, mu in [(1, 0), (0, 0), (1, 3), (0, 3)]:
+        us = ctx.time_phase(kind, mu, 0, tau, 50)
+        b, u = ctx.phase_bytes(kind, mu, 0, tau)
+        per_phase[(kind, mu)] = (us, b, u)
+    us, b, u = per_phase[(1, 0)]
+    achieved = b / (us * 1e-6) / 1e9
+    line = {
+        "metric": "link updates/s (HB+OR, multilevel)",
+        "value": value,
+        "unit": "link updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if spec.precision == u1ml.FP32 else "f64",
+        "data": "synthetic (seeded Monte-Carlo ensembles)",
+        "config": {"workload": make.__name__, "ensembles": len(spec.ensembles),
+                   "lattices": sorted({f"{e.ns[0]}^3x{e.nt}" for e in spec.ensembles}),
+                   "levels": spec.levels, "n_or": spec.n_or, "updates_per_step": upd,
+                   "block": tune["chosen_block"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_update<float,1> (overrelaxation, spatial mu, inner slabs)",
+                     "bytes_per_launch": b, "updates_per_launch": u, "us_per_launch": us},
+        "phases_us": {f"{'OR' if k else 'HB'}_mu{m}": v[0] for (k, m), v in per_phase.items()},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,247 @@
+/*
+ * u1ml.h -- C ABI of libu1ml: the compact U(1) Luscher--Weisz multilevel hot
+ * path on one AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the statement of the problem in Amado, Cardoso, Bicudo,
+ * "Flux tube widening in compact U(1) lattice gauge theory computed at T < T_c
+ * with the multilevel method and GPUs" (arXiv 1309.3859):
+ *   - lattice Ns^3 x Nt with periodic boundaries, links U = exp(i theta),
+ *     Wilson action with coupling beta                           (Sec. II)
+ *   - sweeps of local link updates plus 3 overrelaxation steps    (Sec. II)
+ *   - the multilevel hierarchy: time slabs of thickness tau whose boundary
+ *     spatial links are frozen, n sublattice updates of k sweeps each, one
+ *     or two levels                          (Sec. II.C, Algorithm 1)
+ *   - Polyakov-loop correlators at separations r along a charge axis mu,
+ *     and plaquette insertions (E and B components, O = 2 beta (1 - Re P)
+ *     and sqrt(beta) Im P) at positions relative to the charge (Sec. II.C.3)
+ *
+ * Conventions
+ *   - Nothing throws or aborts across this boundary; every call returns a
+ *     u1ml_status.  One host thread per context at a time.
+ *   - All pointers are owned by the caller except the context itself.  The
+ *     device workspace is provided by the caller (for instance a torch uint8
+ *     tensor) and is only borrowed by the context.
+ *   - Calls marked "async" enqueue work on the context's stream and return;
+ *     HIP errors they cause are reported by the next call that synchronises
+ *     (U1ML_EDEVICE).
+ *   - Results do not depend on the update kernel's tile shape, on how many
+ *     ensembles share a launch, or on their order: every random number is a
+ *     Philox4x32-10 block keyed by (seed, key_id) and countered by
+ *     (link id, heatbath pass, attempt pair, domain), and every reduction runs
+ *     in a fixed order with double-double partial sums.
+ *   - Canonical link view (get/set): angle of link mu at site
+ *     (x, y, z, t) is element mu + 4 * (x + Nx * (y + Ny * (z + Nz * t))),
+ *     mu = 0, 1, 2, 3 = x, y, z, t.
+ */
+#ifndef U1ML_H
+#define U1ML_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    U1ML_OK = 0,
+    U1ML_EINVAL = 1,  /* invalid argument or problem description           */
+    U1ML_ENOMEM = 2,  /* size overflow in the planner, or host allocation   */
+    U1ML_EDEVICE = 3, /* a HIP call failed (message in u1ml_last_error)     */
+    U1ML_ESTATE = 4,  /* call made in the wrong state (e.g. before init)    */
+    U1ML_ENOTSUP = 5  /* option not supported by this build                 */
+} u1ml_status;
+
+enum { U1ML_FP64 = 0, U1ML_FP32 = 1 };         /* link storage / update arithmetic */
+enum { U1ML_COLD = 0, U1ML_HOT = 1 };          /* start of u1ml_init_links         */
+enum { U1ML_HEATBATH = 0, U1ML_OVERRELAX = 1 }; /* update kind of u1ml_phase        */
+
+/* One ensemble: Ns^3 x Nt lattice (Sec. II), coupling beta = 1/g^2 and its
+ * Philox key.  Every extent must be even and >= 2 (checkerboard across the
+ * periodic wrap). */
+typedef struct {
+    int ns[3];
+    int nt;
+    double beta;
+    uint32_t seed;
+    uint32_t key_id;
+} u1ml_ensemble;
+
+/* One multilevel level (Algorithm 1): time slabs of thickness tau, with the
+ * spatial links of the layers t = 0 mod tau frozen; n_iter sublattice updates
+ * of k_sweeps sweeps each. */
+typedef struct {
+    int tau;
+    int n_iter;
+    int k_sweeps;
+} u1ml_level;
+
+/* Insertion position relative to the site x of the charge P^dagger(x), in the
+ * charge frame (e_par = mu, e_perp1 = mu+1, e_perp2 = mu+2 mod 3):
+ *   x0 = x + l_eff e_par + p1 e_perp1 + p2 e_perp2,
+ *   l_eff = l                         if mode == 0,
+ *   l_eff = l + l_mid(r, component)   if mode == 1 (mid-plane between the
+ *           charges, Sec. III.B: floor((r-1)/2) for plaquettes spanning e_par,
+ *           floor(r/2) otherwise). */
+typedef struct {
+    int l;
+    int p1;
+    int p2;
+    int mode;
+} u1ml_probe;
+
+/* Problem description. Arrays are read during u1ml_plan / u1ml_create only.
+ *   comps: frame components 0..5 = E_par, E_perp1, E_perp2 (plaquettes
+ *          P_{i t}) and B_par, B_perp1, B_perp2 (P_{perp1 perp2},
+ *          P_{perp2 par}, P_{par perp1}); for mu = x: E_x, E_y, E_z, B_x, B_y,
+ *          B_z with B_x from P_{yz}, B_y from P_{zx}, B_z from P_{xy}.
+ *   levels: outer first; with two levels the outer tau must be a multiple of
+ *          the inner tau, and Nt a multiple of the outer tau.
+ *   dirs:   charge axes (0, 1, 2) summed over in the estimators (Sec. II.C.3).
+ *   max_configs: capacity of the device results ring (configurations). */
+typedef struct {
+    int n_ens;
+    const u1ml_ensemble* ens;
+    int precision;
+    int n_or;
+    int n_levels;
+    u1ml_level levels[2];
+    int n_dirs;
+    int dirs[3];
+    int n_r;
+    const int* r;
+    int n_probe;
+    const u1ml_probe* probes;
+    int n_comp;
+    const int* comps;
+    int max_configs;
+} u1ml_problem;
+
+/* Planner output (bytes of each workspace section, 256-byte aligned). */
+typedef struct {
+    size_t ws_bytes;          /* total device workspace required             */
+    size_t link_bytes;        /* link angles of every ensemble               */
+    size_t history_bytes;     /* per-measurement slab phases and O sums      */
+    size_t average_bytes;     /* slab averages [T], [TO] of the inner level  */
+    size_t outer_bytes;       /* running sums of the outer level             */
+    size_t result_bytes;      /* device results ring                         */
+    size_t scratch_bytes;     /* reduction partials, tables, counters        */
+    size_t paper_running_bytes; /* the paper's running-accumulator footprint
+                                   2 * 8 * V * (area of the probe plane)/tau
+                                   for comparison (Sec. II.D)                 */
+    long n_doubles_per_config; /* doubles per ensemble per configuration:
+                                  C[r] (re, im), CO[r][probe][comp][kind]
+                                  (re, im), vacuum <O_sq>[6], <O_lin>[6]      */
+    long updates_per_config;  /* non-frozen link updates of one multilevel
+                                 configuration, all ensembles               */
+    long updates_per_sweep;   /* link updates of one full-lattice sweep      */
+} u1ml_plan_info;
+
+typedef struct u1ml_ctx u1ml_ctx;
+
+/* Pure host function: validates the problem (every rule returns U1ML_EINVAL
+ * with a message for u1ml_last_error(NULL)) and sizes the workspace. */
+u1ml_status u1ml_plan(const u1ml_problem* problem, u1ml_plan_info* out);
+
+/* Creates a context on the current HIP device.  d_ws (device memory of at
+ * least the planned ws_bytes, 256-byte aligned) and hip_stream (a hipStream_t,
+ * may be NULL for the null stream) stay owned by the caller.  Uploads the
+ * ensemble tables; links are undefined until u1ml_init_links. */
+u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes, void* hip_stream,
+                        u1ml_ctx** out);
+
+/* Frees host state and graphs; never frees d_ws.  NULL is accepted. */
+u1ml_status u1ml_destroy(u1ml_ctx* ctx);
+
+/* Async.  Cold start (theta = 0) or hot start (theta = pi (2u - 1), u from
+ * the Philox block (link, 0, 0, domain 1)); resets every update counter. */
+u1ml_status u1ml_init_links(u1ml_ctx* ctx, int start);
+
+/* Async.  n full-lattice sweeps (one heatbath pass, then n_or overrelaxation
+ * passes; a pass visits mu = x, y, z, t, each even then odd sites) on every
+ * ensemble (Sec. II). */
+u1ml_status u1ml_sweeps(u1ml_ctx* ctx, int n);
+
+/* Async.  One checkerboard phase: the links of direction mu and the given
+ * parity that are not frozen at slab thickness tau (tau <= 1: none frozen),
+ * updated with kind U1ML_HEATBATH or U1ML_OVERRELAX, using heatbath pass
+ * counter (device counter + pass_offset).  Does not advance the counter. */
+u1ml_status u1ml_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int pass_offset);
+
+/* Async.  One multilevel configuration: the body of Algorithm 1 with the
+ * problem's levels, then the slab products, appending one record of
+ * n_doubles_per_config doubles per ensemble to the device results ring.
+ * ESTATE when the ring is full or the links were never initialised. */
+u1ml_status u1ml_multilevel(u1ml_ctx* ctx);
+
+/* Synchronises.  Copies every record in the ring, configuration-major then
+ * ensemble: host[(c * n_ens + e) * n_doubles_per_config + k]; *n_written is
+ * the number of doubles copied (at most n_doubles).  Empties the ring. */
+u1ml_status u1ml_copy_results(u1ml_ctx* ctx, double* host, size_t n_doubles, size_t* n_written);
+
+/* Synchronise.  Canonical FP64 view of one ensemble's 4*V link angles. */
+u1ml_status u1ml_get_links(u1ml_ctx* ctx, int ens, double* host, size_t n);
+u1ml_status u1ml_set_links(u1ml_ctx* ctx, int ens, const double* host, size_t n);
+
+/* Synchronise.  Heatbath pass counter of one ensemble (checkpoint / replay). */
+u1ml_status u1ml_get_counter(u1ml_ctx* ctx, int ens, uint32_t* counter);
+u1ml_status u1ml_set_counter(u1ml_ctx* ctx, int ens, uint32_t counter);
+
+/* Synchronises.  Mean cos(theta_P) per ensemble and absolute orientation
+ * (E_x, E_y, E_z, B_x, B_y, B_z): out[ens * 6 + o]. */
+u1ml_status u1ml_plaquette(u1ml_ctx* ctx, double* out);
+
+/* Synchronises.  Number of link angles that are not finite or lie outside
+ * [-pi, pi] by more than 2^-20 relative, all ensembles. */
+u1ml_status u1ml_health(u1ml_ctx* ctx, uint64_t* n_bad);
+
+/* Times every candidate work-group size of the update kernels on this
+ * problem (results are bit-identical for all of them) and keeps the fastest.
+ * Synchronises; restores links and counters afterwards. */
+typedef struct {
+    int n_candidates;
+    int block[8];
+    double us_per_sweep[8];
+    int chosen_block;
+} u1ml_tune_report;
+u1ml_status u1ml_autotune(u1ml_ctx* ctx, u1ml_tune_report* report);
+
+/* Sets the update kernels' work-group size (64, 128, 256, 512 or 1024). */
+u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block);
+
+/* 1: capture sweeps and multilevel bodies into HIP graphs (default);
+ * 0: launch every kernel directly. */
+u1ml_status u1ml_set_graphs(u1ml_ctx* ctx, int enable);
+
+/* Synchronises.  Average device time in microseconds of one launch of the
+ * given checkerboard phase over n_rep launches bracketed by HIP events on the
+ * context's stream (links change; counters do not). */
+u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int n_rep, double* us);
+
+/* Algorithmic bytes moved by one launch of that phase under the streaming
+ * model: every distinct link angle the phase reads once, every link it writes
+ * once (heatbath 8 words per update, overrelaxation 9), all ensembles. */
+u1ml_status u1ml_phase_bytes(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, double* bytes,
+                             long* updates);
+
+/* Async, no context.  Philox4x32-10 blocks on the device:
+ * d_out[4 i + w] = word w of the block (c0 + i, c1, c2, c3) under key
+ * (k0, k1), i < n.  d_out holds 4 n uint32. */
+u1ml_status u1ml_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                             size_t n, uint32_t* d_out, void* hip_stream);
+
+/* Async, no context.  n von Mises(0, kappa) draws with the heatbath's sampler
+ * (Best--Fisher 1979) in the given precision; draw i uses Philox counter
+ * words (c0 + i, c1) in domain 3 under key (seed, key_id).  d_out holds n
+ * doubles; d_attempts (may be NULL) receives the attempt count per draw. */
+u1ml_status u1ml_vonmises_fill(double kappa, int precision, uint32_t seed, uint32_t key_id, uint32_t c0,
+                               uint32_t c1, size_t n, double* d_out, int* d_attempts, void* hip_stream);
+
+const char* u1ml_status_str(u1ml_status s);
+/* Last error message of ctx, or of the last context-free call if ctx is NULL. */
+const char* u1ml_last_error(const u1ml_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

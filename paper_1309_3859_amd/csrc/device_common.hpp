@@ -1,0 +1,224 @@
+// device_common.hpp -- device building blocks of libu1ml (gfx950).
+//
+// Link storage: one angle array per (ensemble, direction mu, parity), the
+// sites of one parity packed along x: half index
+//   h = (x >> 1) + (Nx/2) * (y + Ny * (z + Nz * t)),
+// so consecutive work-items touch consecutive words for every neighbour
+// (coalesced), and a checkerboard phase reads and writes whole cache lines.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace u1ml {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// -> 64 bit multiplications by fixed odd constants, with the Weyl-bumped key
+// xored into the high halves.  Counter-based: no generator state in memory.
+// ---------------------------------------------------------------------------
+struct Block4 {
+    uint32_t w[4];
+};
+
+__host__ __device__ inline Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Block4 b;
+    b.w[0] = c0;
+    b.w[1] = c1;
+    b.w[2] = c2;
+    b.w[3] = c3;
+    return b;
+}
+
+enum : uint32_t { DOM_HB = 0, DOM_INIT = 1, DOM_METRO = 2, DOM_TEST = 3 };
+
+// ---------------------------------------------------------------------------
+// Precision traits.  FP64: library math (ocml), same formulas and order as the
+// definitions; FP32: hardware transcendentals where the error budget allows.
+// ---------------------------------------------------------------------------
+template <typename real>
+struct M;
+
+template <>
+struct M<double> {
+    static constexpr double pi = 3.141592653589793;
+    static constexpr double two_pi = 6.283185307179586;
+    __device__ static inline void sincos_(double a, double* s, double* c) { sincos(a, s, c); }
+    __device__ static inline double cos_pi(double u) { return cos(pi * u); }  // cos(pi u)
+    __device__ static inline double atan2_(double y, double x) { return atan2(y, x); }
+    __device__ static inline double acos_(double x) { return acos(x); }
+    __device__ static inline double log_(double x) { return log(x); }
+    __device__ static inline double sqrt_(double x) { return sqrt(x); }
+    __device__ static inline double div_(double a, double b) { return a / b; }
+    __device__ static inline double floor_(double x) { return floor(x); }
+    // U1 from the high 31 bits of word a, U2 from the whole word b, in (0, 1)
+    __device__ static inline double u1(uint32_t a) { return ((double)(a >> 1) + 0.5) * (1.0 / 2147483648.0); }
+    __device__ static inline double u2(uint32_t b) { return ((double)b + 0.5) * (1.0 / 4294967296.0); }
+};
+
+template <>
+struct M<float> {
+    static constexpr float pi = 3.14159265f;
+    static constexpr float two_pi = 6.28318531f;
+    // hardware sin/cos take revolutions; |a| < 4 pi here, well inside their range
+    __device__ static inline void sincos_(float a, float* s, float* c)
+    {
+        const float rev = a * 0.159154943f;
+        *s = __builtin_amdgcn_sinf(rev);
+        *c = __builtin_amdgcn_cosf(rev);
+    }
+    __device__ static inline float cos_pi(float u) { return __builtin_amdgcn_cosf(0.5f * u); }
+    __device__ static inline float atan2_(float y, float x) { return atan2f(y, x); }
+    __device__ static inline float acos_(float x) { return acosf(x); }
+    __device__ static inline float log_(float x) { return __logf(x); }
+    __device__ static inline float sqrt_(float x) { return __builtin_sqrtf(x); }
+    __device__ static inline float div_(float a, float b) { return __fdividef(a, b); }
+    __device__ static inline float floor_(float x) { return floorf(x); }
+    // 23-bit uniforms: exact in FP32, never 0 or 1
+    __device__ static inline float u1(uint32_t a) { return ((float)(a >> 9) + 0.5f) * (1.0f / 8388608.0f); }
+    __device__ static inline float u2(uint32_t b) { return ((float)(b >> 9) + 0.5f) * (1.0f / 8388608.0f); }
+};
+
+// wrap(a) = a - 2 pi floor((a + pi) / (2 pi))
+template <typename real>
+__device__ inline real wrap_angle(real a)
+{
+    return a - M<real>::two_pi * M<real>::floor_((a + M<real>::pi) / M<real>::two_pi);
+}
+
+// ---------------------------------------------------------------------------
+// von Mises(0, kappa) by Best & Fisher (1979): wrapped-Cauchy envelope with
+//   s = sqrt(1 + 4 k^2), tau = 1 + s, rho = 2 k tau / ((s+1)(tau + sqrt(2 tau)))
+//   (the cancellation-free form of (tau - sqrt(2 tau)) / (2 k)),
+//   r = (1 + rho^2) / (2 rho);
+// attempt: z = cos(pi U1), f = (1 + r z)/(r + z), c = k (r - f), accept if
+// c (2 - c) > U2 or ln(c / U2) + 1 - c >= 0; psi = sign * arccos(f).
+// Attempt j reads Philox block (c0, c1, j/2, domain): words (0,1) for even j,
+// (2,3) for odd j; sign = low bit of the first word of the pair.
+// Returns psi and the attempt count (-1 past 65536 attempts).
+// ---------------------------------------------------------------------------
+template <typename real>
+__device__ inline real vonmises_psi(real kappa, uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t domain,
+                                    int* n_att)
+{
+    using m = M<real>;
+    if (kappa == real(0)) {
+        const Block4 b = philox4x32_10(c0, c1, 0u, domain, k0, k1);
+        *n_att = 1;
+        return m::pi * (real(2) * m::u1(b.w[0]) - real(1));
+    }
+    const real s = m::sqrt_(real(1) + real(4) * kappa * kappa);
+    const real tau = real(1) + s;
+    const real rho = m::div_(real(2) * kappa * tau, (s + real(1)) * (tau + m::sqrt_(real(2) * tau)));
+    const real r = m::div_(real(1) + rho * rho, real(2) * rho);
+    Block4 b;
+    for (int j = 0; j < 65536; ++j) {
+        if ((j & 1) == 0) b = philox4x32_10(c0, c1, (uint32_t)(j >> 1), domain, k0, k1);
+        const uint32_t a = (j & 1) ? b.w[2] : b.w[0];
+        const uint32_t bb = (j & 1) ? b.w[3] : b.w[1];
+        const real z = m::cos_pi(m::u1(a));
+        real f = m::div_(real(1) + r * z, r + z);
+        f = f > real(1) ? real(1) : (f < real(-1) ? real(-1) : f);
+        const real c = kappa * (r - f);
+        const real u2 = m::u2(bb);
+        bool acc = (c * (real(2) - c) - u2 > real(0));
+        if (!acc) acc = (m::log_(m::div_(c, u2)) + real(1) - c >= real(0));
+        if (acc) {
+            *n_att = j + 1;
+            const real psi = m::acos_(f);
+            return (a & 1u) ? -psi : psi;
+        }
+    }
+    *n_att = -1;
+    return real(0);
+}
+
+// FP32 form of the same sampler, rewritten so that small |psi| (f near 1) and
+// |psi| near pi (f near -1) keep their relative precision: with
+//   r - 1 = (1 - rho)^2 / (2 rho),  1 - z = 2 sin^2(pi U1 / 2),  1 + z = 2 cos^2(pi U1 / 2),
+//   g = 1 - f = (r - 1)(1 - z) / (r + z),   h = 1 + f = (r + 1)(1 + z) / (r + z),
+//   c = kappa (r - f) = kappa ((r - 1) + g),
+//   psi = 2 asin(sqrt(g / 2)) if g <= 1, else pi - 2 asin(sqrt(h / 2)),
+// which are the same quantities as above, free of the cancellation in 1 - f.
+template <>
+__device__ inline float vonmises_psi<float>(float kappa, uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
+                                            uint32_t domain, int* n_att)
+{
+    using m = M<float>;
+    if (kappa == 0.0f) {
+        const Block4 b = philox4x32_10(c0, c1, 0u, domain, k0, k1);
+        *n_att = 1;
+        return m::pi * (2.0f * m::u1(b.w[0]) - 1.0f);
+    }
+    const float s = m::sqrt_(1.0f + 4.0f * kappa * kappa);
+    const float tau = 1.0f + s;
+    const float rho = m::div_(2.0f * kappa * tau, (s + 1.0f) * (tau + m::sqrt_(2.0f * tau)));
+    const float omr = 1.0f - rho;
+    const float rm1 = m::div_(omr * omr, 2.0f * rho);
+    Block4 b;
+    for (int j = 0; j < 65536; ++j) {
+        if ((j & 1) == 0) b = philox4x32_10(c0, c1, (uint32_t)(j >> 1), domain, k0, k1);
+        const uint32_t a = (j & 1) ? b.w[2] : b.w[0];
+        const uint32_t bb = (j & 1) ? b.w[3] : b.w[1];
+        const float q = 0.25f * m::u1(a);  // pi U1 / 2 in revolutions
+        const float sh = __builtin_amdgcn_sinf(q), ch = __builtin_amdgcn_cosf(q);
+        const float omz = 2.0f * sh * sh, opz = 2.0f * ch * ch;
+        const float inv = m::div_(1.0f, rm1 + opz);
+        const float g = rm1 * omz * inv;
+        const float c = kappa * (rm1 + g);
+        const float u2 = m::u2(bb);
+        bool acc = (c * (2.0f - c) - u2 > 0.0f);
+        if (!acc) acc = (m::log_(m::div_(c, u2)) + 1.0f - c >= 0.0f);
+        if (acc) {
+            *n_att = j + 1;
+            float psi;
+            if (g <= 1.0f) {
+                psi = 2.0f * asinf(m::sqrt_(0.5f * g));
+            } else {
+                const float h = (rm1 + 2.0f) * opz * inv;
+                psi = m::pi - 2.0f * asinf(m::sqrt_(0.5f * h));
+            }
+            return (a & 1u) ? -psi : psi;
+        }
+    }
+    *n_att = -1;
+    return 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry
+// ---------------------------------------------------------------------------
+struct Coord {
+    int x, y, z, t;
+};
+
+__device__ inline int wrap_p(int v, int n) { return v == n ? 0 : v; }
+__device__ inline int wrap_m(int v, int n) { return v < 0 ? n - 1 : v; }
+
+__device__ inline Coord step(Coord c, int dir, int s, int nx, int ny, int nz, int nt)
+{
+    switch (dir) {
+    case 0: c.x = s > 0 ? wrap_p(c.x + 1, nx) : wrap_m(c.x - 1, nx); break;
+    case 1: c.y = s > 0 ? wrap_p(c.y + 1, ny) : wrap_m(c.y - 1, ny); break;
+    case 2: c.z = s > 0 ? wrap_p(c.z + 1, nz) : wrap_m(c.z - 1, nz); break;
+    default: c.t = s > 0 ? wrap_p(c.t + 1, nt) : wrap_m(c.t - 1, nt); break;
+    }
+    return c;
+}
+
+}  // namespace u1ml

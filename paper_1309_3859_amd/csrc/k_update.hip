@@ -1,0 +1,423 @@
+// k_update.hip -- link initialisation and the checkerboard link update.
+//
+// Paper: Amado, Cardoso, Bicudo, arXiv 1309.3859, Sec. II (Wilson action,
+// local updates with 3 overrelaxation steps), Sec. II.C.1 and Algorithm 1
+// (sublattice updates with frozen boundary spatial links), Sec. II.D (links
+// as phases, even then odd sites, in place).
+//
+// One work-item per link of the phase (direction mu, parity p, not frozen),
+// every ensemble of the batch in the same launch: block b belongs to the
+// ensemble e with bstart[e] <= b < bstart[e+1].  The staple of a link reads
+// 18 angles: 12 of the other parity (coalesced, shifted by one site), 6 of the
+// same parity; none of them is written by the phase, so the update is in place.
+#include "device_common.hpp"
+#include "u1ml_internal.hpp"
+
+namespace u1ml {
+
+__device__ inline int find_ens(const int* __restrict__ bstart, int n_ens, int bid)
+{
+    int e = 0;
+    while (e + 1 < n_ens && bid >= bstart[e + 1]) ++e;
+    return e;
+}
+
+template <typename real>
+struct LinkView {
+    const real* base;
+    int vh, nxh, ny, nz;
+    __device__ inline real ld(int dir, int par, Coord c) const
+    {
+        const int h = (c.x >> 1) + nxh * (c.y + ny * (c.z + nz * c.t));
+        return base[(size_t)(dir * 2 + par) * vh + h];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Staple sum A = sum_{nu != mu} exp(i phi_f) + exp(i phi_b), nu ascending,
+// forward before backward:
+//   phi_f = th_nu(x+mu) - th_mu(x+nu) - th_nu(x)
+//   phi_b = th_nu(x-nu) - th_nu(x+mu-nu) - th_mu(x-nu)
+// ---------------------------------------------------------------------------
+template <typename real>
+__device__ inline void staple(const LinkView<real>& L, Coord c, int mu, int p, int nx, int nt, real* ar, real* ai)
+{
+    const int q = p ^ 1;
+    const Coord cpm = step(c, mu, +1, nx, L.ny, L.nz, nt);
+    real sr = real(0), si = real(0);
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        const Coord cpn = step(c, nu, +1, nx, L.ny, L.nz, nt);
+        const Coord cmn = step(c, nu, -1, nx, L.ny, L.nz, nt);
+        const Coord cpmmn = step(cpm, nu, -1, nx, L.ny, L.nz, nt);
+        const real phf = L.ld(nu, q, cpm) - L.ld(mu, q, cpn) - L.ld(nu, p, c);
+        const real phb = L.ld(nu, q, cmn) - L.ld(nu, p, cpmmn) - L.ld(mu, q, cmn);
+        real s, co;
+        M<real>::sincos_(phf, &s, &co);
+        sr += co;
+        si += s;
+        M<real>::sincos_(phb, &s, &co);
+        sr += co;
+        si += s;
+    }
+    *ar = sr;
+    *ai = si;
+}
+
+// kind 0: heatbath theta = wrap(psi - arg A), psi ~ vonMises(0, beta |A|);
+// kind 1: overrelaxation theta = wrap(-theta - 2 arg A) (unchanged if A = 0).
+template <typename real, int KIND>
+__global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
+                                                 int n_ens, real* __restrict__ links, const uint32_t* __restrict__ upd,
+                                                 int pass_offset, int mu, int parity, int tau)
+{
+    const int bid = blockIdx.x;
+    const int e = find_ens(bstart, n_ens, bid);
+    const EnsDesc& E = ens[e];
+    const int nxh = E.nxh, nx = E.nx, ny = E.ny, nz = E.nz, nt = E.nt;
+    const bool masked = (mu < 3) && (tau > 1);
+    const int slice = nxh * ny * nz;
+    const int active_t = masked ? nt - nt / tau : nt;
+    const int item = (bid - bstart[e]) * (int)blockDim.x + (int)threadIdx.x;
+    if (item >= slice * active_t) return;
+    const int j = item / slice;
+    const int rem = item - j * slice;
+    const int t = masked ? (j / (tau - 1)) * tau + 1 + (j % (tau - 1)) : j;
+    const int yz = rem / nxh;
+    const int xh = rem - yz * nxh;
+    const int z = yz / ny;
+    const int y = yz - z * ny;
+    const int x = 2 * xh + ((y + z + t + parity) & 1);
+    const Coord c = {x, y, z, t};
+
+    real* base = links + E.link_off;
+    LinkView<real> L{base, E.vh, nxh, ny, nz};
+    real ar, ai;
+    staple(L, c, mu, parity, nx, nt, &ar, &ai);
+    real* dst = base + (size_t)(mu * 2 + parity) * E.vh + (xh + nxh * (y + ny * (z + nz * t)));
+    if (KIND == 0) {
+        const real R = M<real>::sqrt_(ar * ar + ai * ai);
+        const real phiA = M<real>::atan2_(ai, ar);
+        const real kappa = (real)E.beta * R;
+        const uint32_t lid = (uint32_t)(mu + 4 * (x + nx * (y + ny * (z + nz * t))));
+        int na;
+        const real psi = vonmises_psi<real>(kappa, E.seed, E.key_id, lid, upd[e] + (uint32_t)pass_offset, DOM_HB, &na);
+        if (na < 0) return;
+        *dst = wrap_angle<real>(psi - phiA);
+    } else {
+        if (ar == real(0) && ai == real(0)) return;
+        const real phiA = M<real>::atan2_(ai, ar);
+        *dst = wrap_angle<real>(-(*dst) - real(2) * phiA);
+    }
+}
+
+hipError_t launch_update(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
+                         int precision, void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu,
+                         int parity, int tau, hipStream_t st)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    dim3 g(total_blocks), b(block);
+    if (precision == 0) {
+        if (kind == 0)
+            hipLaunchKernelGGL((k_update<double, 0>), g, b, 0, st, d_ens, d_bstart, n_ens, (double*)links, d_upd,
+                               pass_offset, mu, parity, tau);
+        else
+            hipLaunchKernelGGL((k_update<double, 1>), g, b, 0, st, d_ens, d_bstart, n_ens, (double*)links, d_upd,
+                               pass_offset, mu, parity, tau);
+    } else {
+        if (kind == 0)
+            hipLaunchKernelGGL((k_update<float, 0>), g, b, 0, st, d_ens, d_bstart, n_ens, (float*)links, d_upd,
+                               pass_offset, mu, parity, tau);
+        else
+            hipLaunchKernelGGL((k_update<float, 1>), g, b, 0, st, d_ens, d_bstart, n_ens, (float*)links, d_upd,
+                               pass_offset, mu, parity, tau);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// All-link kernels: one work-item per (direction, parity, half site).
+// ---------------------------------------------------------------------------
+struct LinkItem {
+    int dir, par, h, x, y, z, t;
+};
+
+__device__ inline bool decode_link(const EnsDesc& E, int item, LinkItem* o)
+{
+    if (item >= 8 * E.vh) return false;
+    const int dp = item / E.vh;
+    o->h = item - dp * E.vh;
+    o->dir = dp >> 1;
+    o->par = dp & 1;
+    const int row = o->h / E.nxh;
+    const int xh = o->h - row * E.nxh;
+    const int yz = row;
+    o->t = yz / (E.ny * E.nz);
+    const int r2 = yz - o->t * E.ny * E.nz;
+    o->z = r2 / E.ny;
+    o->y = r2 - o->z * E.ny;
+    o->x = 2 * xh + ((o->y + o->z + o->t + o->par) & 1);
+    return true;
+}
+
+// Cold: theta = 0.  Hot: theta = pi (2u - 1), u = (w0 + 1/2) 2^-32 with w0 the
+// first word of the Philox block (link id, 0, 0, INIT); formed in FP64 and
+// rounded to the storage precision.
+template <typename real>
+__global__ void k_init(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart, int n_ens,
+                       real* __restrict__ links, int start)
+{
+    const int bid = blockIdx.x;
+    const int e = find_ens(bstart, n_ens, bid);
+    const EnsDesc& E = ens[e];
+    LinkItem it;
+    if (!decode_link(E, (bid - bstart[e]) * (int)blockDim.x + (int)threadIdx.x, &it)) return;
+    double th = 0.0;
+    if (start) {
+        const uint32_t lid = (uint32_t)(it.dir + 4 * (it.x + E.nx * (it.y + E.ny * (it.z + E.nz * it.t))));
+        const Block4 b = philox4x32_10(lid, 0u, 0u, DOM_INIT, E.seed, E.key_id);
+        const double u = ((double)b.w[0] + 0.5) * (1.0 / 4294967296.0);
+        th = M<double>::pi * (2.0 * u - 1.0);
+    }
+    links[E.link_off + (size_t)(it.dir * 2 + it.par) * E.vh + it.h] = (real)th;
+}
+
+hipError_t launch_init_links(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
+                             void* links, int start, hipStream_t st)
+{
+    if (precision == 0)
+        hipLaunchKernelGGL(k_init<double>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart_all, n_ens,
+                           (double*)links, start);
+    else
+        hipLaunchKernelGGL(k_init<float>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart_all, n_ens,
+                           (float*)links, start);
+    return hipGetLastError();
+}
+
+template <typename real>
+__global__ void k_health(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart, int n_ens,
+                         const real* __restrict__ links, unsigned long long* __restrict__ count)
+{
+    const int bid = blockIdx.x;
+    const int e = find_ens(bstart, n_ens, bid);
+    const EnsDesc& E = ens[e];
+    LinkItem it;
+    if (!decode_link(E, (bid - bstart[e]) * (int)blockDim.x + (int)threadIdx.x, &it)) return;
+    const double th = (double)links[E.link_off + (size_t)(it.dir * 2 + it.par) * E.vh + it.h];
+    const double lim = M<double>::pi * (1.0 + 1.0 / 1048576.0);
+    if (!(th >= -lim && th <= lim)) atomicAdd(count, 1ull);
+}
+
+hipError_t launch_health(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
+                         const void* links, unsigned long long* d_count, hipStream_t st)
+{
+    if (precision == 0)
+        hipLaunchKernelGGL(k_health<double>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart_all, n_ens,
+                           (const double*)links, d_count);
+    else
+        hipLaunchKernelGGL(k_health<float>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart_all, n_ens,
+                           (const float*)links, d_count);
+    return hipGetLastError();
+}
+
+// Canonical FP64 view <-> even/odd storage, one ensemble at a time.
+template <typename real>
+__global__ void k_gather(const EnsDesc* __restrict__ ens, int e, const real* __restrict__ links,
+                         double* __restrict__ canon, long long n_sites)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sites) return;
+    const EnsDesc& E = ens[e];
+    const int x = (int)(s % E.nx);
+    long long r = s / E.nx;
+    const int y = (int)(r % E.ny);
+    r /= E.ny;
+    const int z = (int)(r % E.nz);
+    const int t = (int)(r / E.nz);
+    const int par = (x + y + z + t) & 1;
+    const int h = (x >> 1) + E.nxh * (y + E.ny * (z + E.nz * t));
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) canon[4 * s + mu] = (double)links[E.link_off + (size_t)(mu * 2 + par) * E.vh + h];
+}
+
+template <typename real>
+__global__ void k_scatter(const EnsDesc* __restrict__ ens, int e, real* __restrict__ links,
+                          const double* __restrict__ canon, long long n_sites)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sites) return;
+    const EnsDesc& E = ens[e];
+    const int x = (int)(s % E.nx);
+    long long r = s / E.nx;
+    const int y = (int)(r % E.ny);
+    r /= E.ny;
+    const int z = (int)(r % E.nz);
+    const int t = (int)(r / E.nz);
+    const int par = (x + y + z + t) & 1;
+    const int h = (x >> 1) + E.nxh * (y + E.ny * (z + E.nz * t));
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) links[E.link_off + (size_t)(mu * 2 + par) * E.vh + h] = (real)canon[4 * s + mu];
+}
+
+hipError_t launch_gather_links(const EnsDesc* d_ens, int ens, int precision, const void* links, double* d_canon,
+                               long long n_sites, hipStream_t st)
+{
+    const int g = (int)((n_sites + 255) / 256);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_gather<double>, dim3(g), dim3(256), 0, st, d_ens, ens, (const double*)links, d_canon,
+                           n_sites);
+    else
+        hipLaunchKernelGGL(k_gather<float>, dim3(g), dim3(256), 0, st, d_ens, ens, (const float*)links, d_canon,
+                           n_sites);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_links(const EnsDesc* d_ens, int ens, int precision, void* links, const double* d_canon,
+                                long long n_sites, hipStream_t st)
+{
+    const int g = (int)((n_sites + 255) / 256);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_scatter<double>, dim3(g), dim3(256), 0, st, d_ens, ens, (double*)links, d_canon,
+                           n_sites);
+    else
+        hipLaunchKernelGGL(k_scatter<float>, dim3(g), dim3(256), 0, st, d_ens, ens, (float*)links, d_canon, n_sites);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Plaquette means per orientation (E_x, E_y, E_z, B_x, B_y, B_z), FP64 sums.
+// Block (e, b) strides over the ensemble's sites; partials are summed in a
+// fixed order by k_plaq_final.
+// ---------------------------------------------------------------------------
+constexpr int kPlaqBlocks = 64;
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_plaq_partial(const EnsDesc* __restrict__ ens, const real* __restrict__ links,
+                                                      double* __restrict__ partials)
+{
+    const int e = blockIdx.x / kPlaqBlocks;
+    const int b = blockIdx.x % kPlaqBlocks;
+    const EnsDesc& E = ens[e];
+    LinkView<real> L{links + E.link_off, E.vh, E.nxh, E.ny, E.nz};
+    const long long V = 2ll * E.vh;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    static const int pa[6] = {0, 1, 2, 1, 2, 0};
+    static const int pb[6] = {3, 3, 3, 2, 0, 1};
+    for (long long s = (long long)b * 256 + threadIdx.x; s < V; s += 256ll * kPlaqBlocks) {
+        const int x = (int)(s % E.nx);
+        long long r = s / E.nx;
+        const int y = (int)(r % E.ny);
+        r /= E.ny;
+        const int z = (int)(r % E.nz);
+        const int t = (int)(r / E.nz);
+        const Coord c = {x, y, z, t};
+        const int p = (x + y + z + t) & 1;
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+            const int a = pa[o], bb = pb[o];
+            const Coord ca = step(c, a, +1, E.nx, E.ny, E.nz, E.nt);
+            const Coord cb = step(c, bb, +1, E.nx, E.ny, E.nz, E.nt);
+            const double th = (double)L.ld(a, p, c) + (double)L.ld(bb, p ^ 1, ca) - (double)L.ld(a, p ^ 1, cb) -
+                              (double)L.ld(bb, p, c);
+            acc[o] += cos(th);
+        }
+    }
+    __shared__ double sh[6][256];
+    for (int o = 0; o < 6; ++o) sh[o][threadIdx.x] = acc[o];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int o = 0; o < 6; ++o) sh[o][threadIdx.x] += sh[o][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partials[(size_t)blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_plaq_final(const EnsDesc* __restrict__ ens, const double* __restrict__ partials, double* __restrict__ out)
+{
+    const int e = blockIdx.x;
+    const int o = threadIdx.x;
+    if (o >= 6) return;
+    double s = 0.0;
+    for (int b = 0; b < kPlaqBlocks; ++b) s += partials[((size_t)e * kPlaqBlocks + b) * 6 + o];
+    out[e * 6 + o] = s / (2.0 * (double)ens[e].vh);
+}
+
+hipError_t launch_plaquette(const EnsDesc* d_ens, int n_ens, int, int precision, const void* links,
+                            double* d_partials, double* d_out, hipStream_t st)
+{
+    if (precision == 0)
+        hipLaunchKernelGGL(k_plaq_partial<double>, dim3(n_ens * kPlaqBlocks), dim3(256), 0, st, d_ens,
+                           (const double*)links, d_partials);
+    else
+        hipLaunchKernelGGL(k_plaq_partial<float>, dim3(n_ens * kPlaqBlocks), dim3(256), 0, st, d_ens,
+                           (const float*)links, d_partials);
+    hipLaunchKernelGGL(k_plaq_final, dim3(n_ens), dim3(64), 0, st, d_ens, d_partials, d_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// RNG and sampler fills (bit-exact and statistical checks of the stream).
+// ---------------------------------------------------------------------------
+__global__ void k_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, size_t n,
+                              uint32_t* __restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Block4 b = philox4x32_10(c0 + (uint32_t)i, c1, c2, c3, k0, k1);
+    uint4 v;
+    v.x = b.w[0];
+    v.y = b.w[1];
+    v.z = b.w[2];
+    v.w = b.w[3];
+    reinterpret_cast<uint4*>(out)[i] = v;
+}
+
+hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, size_t n,
+                              uint32_t* d_out, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k0, k1, c0, c1, c2, c3, n,
+                       d_out);
+    return hipGetLastError();
+}
+
+template <typename real>
+__global__ void k_vonmises_fill(real kappa, uint32_t seed, uint32_t key_id, uint32_t c0, uint32_t c1, size_t n,
+                                double* __restrict__ out, int* __restrict__ att)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int na;
+    const real psi = vonmises_psi<real>(kappa, seed, key_id, c0 + (uint32_t)i, c1, DOM_TEST, &na);
+    out[i] = (double)psi;
+    if (att) att[i] = na;
+}
+
+hipError_t launch_vonmises_fill(double kappa, int precision, uint32_t seed, uint32_t key_id, uint32_t c0, uint32_t c1,
+                                size_t n, double* d_out, int* d_att, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (precision == 0)
+        hipLaunchKernelGGL(k_vonmises_fill<double>, g, dim3(256), 0, st, kappa, seed, key_id, c0, c1, n, d_out, d_att);
+    else
+        hipLaunchKernelGGL(k_vonmises_fill<float>, g, dim3(256), 0, st, (float)kappa, seed, key_id, c0, c1, n, d_out,
+                           d_att);
+    return hipGetLastError();
+}
+
+__global__ void k_advance(uint32_t* __restrict__ upd, int n_ens, int delta)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n_ens) upd[e] += (uint32_t)delta;
+}
+
+hipError_t launch_advance_counters(uint32_t* d_upd, int n_ens, int delta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance, dim3((n_ens + 63) / 64), dim3(64), 0, st, d_upd, n_ens, delta);
+    return hipGetLastError();
+}
+
+}  // namespace u1ml

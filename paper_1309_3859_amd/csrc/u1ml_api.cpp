@@ -1,0 +1,1016 @@
+// u1ml_api.cpp -- host side of libu1ml: planner, workspace layout, the
+// Algorithm-1 scheduler (Amado, Cardoso, Bicudo, arXiv 1309.3859, Sec. II.C)
+// with HIP-graph capture, and the C ABI declared in include/u1ml.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/u1ml.h"
+#include "u1ml_internal.hpp"
+
+using namespace u1ml;
+
+namespace {
+
+thread_local std::string g_err;  // context-free error text
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool mul_ok(size_t a, size_t b, size_t* out) { return !__builtin_mul_overflow(a, b, out); }
+bool add_ok(size_t a, size_t b, size_t* out) { return !__builtin_add_overflow(a, b, out); }
+
+struct Sizes {
+    // per ensemble element counts
+    std::vector<size_t> links, hc, ho, at, ato, ot, oto, vac;
+};
+
+struct Layout {
+    size_t off_links, off_hc, off_ho, off_at, off_ato, off_ot, off_oto, off_res, off_scr;
+    size_t sz_links, sz_hc, sz_ho, sz_at, sz_ato, sz_ot, sz_oto, sz_res, sz_scr;
+    // scratch sub-offsets (bytes from off_scr)
+    size_t s_ens, s_obs, s_r, s_probe, s_comp, s_bstart, s_upd, s_ring, s_vpart, s_vacc, s_ppart, s_pout, s_count,
+        s_stage;
+    int n_bstart_tables;
+};
+
+constexpr int kTabUpd = 0;    // 4 update classes
+constexpr int kTabAll = 4;    // all links (init, health)
+constexpr int kTabMeas = 5;   // spatial sites
+constexpr int kTabCon = 6;    // contraction items
+constexpr int kTabComb = 7;   // combine items
+constexpr int kNumTabs = 8;
+
+struct Problem {
+    int n_ens = 0;
+    std::vector<u1ml_ensemble> ens;
+    int precision = 0, n_or = 3, n_levels = 1;
+    u1ml_level lv[2] = {};
+    int n_dirs = 1;
+    int dirs[3] = {0, 0, 0};
+    std::vector<int> r;
+    std::vector<u1ml_probe> probes;
+    std::vector<int> comps;
+    int max_configs = 1;
+    // derived
+    int tau_i = 2, n_i = 1, k_i = 1, tau_o = 2, n_o = 1, k_o = 0;
+    bool two = false;
+    long long nd_cfg = 0;
+};
+
+bool fail(std::string* err, const std::string& msg)
+{
+    if (err) *err = msg;
+    return false;
+}
+
+bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
+{
+    if (!p) return fail(err, "problem is NULL");
+    if (p->n_ens < 1 || !p->ens) return fail(err, "n_ens must be >= 1 with a non-NULL ensemble array");
+    if (p->precision != U1ML_FP64 && p->precision != U1ML_FP32) return fail(err, "precision must be 0 (FP64) or 1 (FP32)");
+    if (p->n_or < 0) return fail(err, "n_or must be >= 0");
+    if (p->n_levels < 1 || p->n_levels > 2) return fail(err, "n_levels must be 1 or 2");
+    if (p->max_configs < 1) return fail(err, "max_configs must be >= 1");
+    P->n_ens = p->n_ens;
+    P->ens.assign(p->ens, p->ens + p->n_ens);
+    P->precision = p->precision;
+    P->n_or = p->n_or;
+    P->n_levels = p->n_levels;
+    P->lv[0] = p->levels[0];
+    P->lv[1] = p->levels[1];
+    P->max_configs = p->max_configs;
+    for (int k = 0; k < p->n_levels; ++k) {
+        const u1ml_level& L = p->levels[k];
+        if (L.tau < 2) return fail(err, "level tau must be >= 2 (a slab needs a frozen boundary layer)");
+        if (L.n_iter < 1) return fail(err, "level n_iter must be >= 1");
+        if (L.k_sweeps < 0) return fail(err, "level k_sweeps must be >= 0");
+    }
+    P->two = (p->n_levels == 2);
+    if (P->two) {
+        P->tau_o = p->levels[0].tau;
+        P->n_o = p->levels[0].n_iter;
+        P->k_o = p->levels[0].k_sweeps;
+        P->tau_i = p->levels[1].tau;
+        P->n_i = p->levels[1].n_iter;
+        P->k_i = p->levels[1].k_sweeps;
+        if (P->tau_o % P->tau_i != 0) return fail(err, "outer tau must be a multiple of the inner tau");
+        if (P->tau_o / P->tau_i > 8) return fail(err, "at most 8 inner slabs per outer slab");
+    } else {
+        P->tau_i = P->tau_o = p->levels[0].tau;
+        P->n_i = p->levels[0].n_iter;
+        P->k_i = p->levels[0].k_sweeps;
+        P->n_o = 1;
+        P->k_o = 0;
+    }
+    if (p->n_dirs < 1 || p->n_dirs > 3) return fail(err, "n_dirs must be 1..3");
+    P->n_dirs = p->n_dirs;
+    for (int i = 0; i < p->n_dirs; ++i) {
+        if (p->dirs[i] < 0 || p->dirs[i] > 2) return fail(err, "charge axes must be 0, 1 or 2");
+        for (int j = 0; j < i; ++j)
+            if (p->dirs[j] == p->dirs[i]) return fail(err, "charge axes must be distinct");
+        P->dirs[i] = p->dirs[i];
+    }
+    if (p->n_r < 1 || !p->r) return fail(err, "n_r must be >= 1 with a non-NULL r array");
+    P->r.assign(p->r, p->r + p->n_r);
+    if (p->n_probe < 0 || (p->n_probe > 0 && !p->probes)) return fail(err, "bad probe array");
+    if (p->n_probe > 0) P->probes.assign(p->probes, p->probes + p->n_probe);
+    if (p->n_comp < 0 || p->n_comp > 6 || (p->n_comp > 0 && !p->comps)) return fail(err, "n_comp must be 0..6");
+    if (p->n_comp > 0) P->comps.assign(p->comps, p->comps + p->n_comp);
+    for (int c : P->comps)
+        if (c < 0 || c > 5) return fail(err, "components must be 0..5");
+    if (P->probes.empty() != P->comps.empty()) return fail(err, "probes and components must both be given or both be empty");
+    for (int e = 0; e < P->n_ens; ++e) {
+        const u1ml_ensemble& E = P->ens[e];
+        const int ext[4] = {E.ns[0], E.ns[1], E.ns[2], E.nt};
+        for (int k = 0; k < 4; ++k)
+            if (ext[k] < 2 || ext[k] % 2 != 0) return fail(err, "every extent must be even and >= 2 (ensemble " + std::to_string(e) + ")");
+        if (!std::isfinite(E.beta) || E.beta < 0) return fail(err, "beta must be finite and >= 0");
+        if (E.nt % P->tau_o != 0) return fail(err, "Nt must be a multiple of the outer tau");
+        if (E.nt % P->tau_i != 0) return fail(err, "Nt must be a multiple of the inner tau");
+        const double V = (double)E.ns[0] * E.ns[1] * E.ns[2] * E.nt;
+        if (4.0 * V >= 4294967296.0) return fail(err, "4 V must fit in 32 bits (link ids)");
+        for (int i = 0; i < P->n_dirs; ++i) {
+            const int d = P->dirs[i];
+            for (int rv : P->r)
+                if (rv < 1 || rv >= E.ns[d]) return fail(err, "every r must satisfy 1 <= r < Ns along the charge axis");
+            for (const u1ml_probe& pr : P->probes) {
+                const int n1 = E.ns[(d + 1) % 3], n2 = E.ns[(d + 2) % 3];
+                if (std::abs(pr.p1) * 2 >= n1) return fail(err, "probe |p1| must be < Ns/2");
+                if (std::abs(pr.p2) * 2 >= n2) return fail(err, "probe |p2| must be < Ns/2");
+                if (std::abs(pr.l) >= E.ns[d]) return fail(err, "probe |l| must be < Ns along the charge axis");
+                if (pr.mode != 0 && pr.mode != 1) return fail(err, "probe mode must be 0 or 1");
+            }
+        }
+    }
+    P->nd_cfg = 2ll * P->r.size() + 4ll * P->r.size() * P->probes.size() * P->comps.size() + 12;
+    return true;
+}
+
+bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::string* err)
+{
+    const size_t word = P.precision == U1ML_FP64 ? 8 : 4;
+    const bool store_o = !P.probes.empty();
+    const size_t R = P.r.size(), Np = P.probes.size(), Nc = P.comps.size(), nd = (size_t)P.n_dirs;
+    size_t L = 0, HC = 0, HO = 0, AT = 0, ATO = 0, OT = 0, OTO = 0, VAC = 0;
+    size_t maxV = 0, paper = 0, upd_cfg = 0, upd_sweep = 0;
+    S->links.clear();
+    S->hc.clear();
+    S->ho.clear();
+    S->at.clear();
+    S->ato.clear();
+    S->ot.clear();
+    S->oto.clear();
+    S->vac.clear();
+    for (const u1ml_ensemble& E : P.ens) {
+        const size_t nsig = (size_t)E.ns[0] * E.ns[1] * E.ns[2];
+        const size_t V = nsig * E.nt;
+        maxV = std::max(maxV, V);
+        const size_t si = E.nt / P.tau_i, so = E.nt / P.tau_o;
+        size_t v, t;
+        // links: 4 V words, padded to 256 bytes
+        if (!mul_ok(4 * V, word, &v)) return fail(err, "size overflow (links)");
+        S->links.push_back(L / word);
+        L = align_up(L + v);
+        S->hc.push_back(HC);
+        if (!mul_ok((size_t)P.n_i * si, nsig, &t) || !add_ok(HC, t, &HC)) return fail(err, "size overflow (history)");
+        HC = align_up(HC * 16) / 16;
+        S->ho.push_back(HO);
+        if (store_o) {
+            if (!mul_ok((size_t)P.n_i * si * 12, nsig, &t) || !add_ok(HO, t, &HO)) return fail(err, "size overflow (history)");
+            HO = align_up(HO * 8) / 8;
+        }
+        S->at.push_back(AT);
+        AT = align_up((AT + nd * R * si * nsig) * 16) / 16;
+        S->ato.push_back(ATO);
+        if (store_o) {
+            if (!mul_ok(nd * R * Np * Nc * 2 * si, nsig, &t) || !add_ok(ATO, t, &ATO)) return fail(err, "size overflow (averages)");
+            ATO = align_up(ATO * 16) / 16;
+        }
+        S->ot.push_back(OT);
+        S->oto.push_back(OTO);
+        if (P.two) {
+            OT = align_up((OT + nd * R * so * nsig) * 16) / 16;
+            if (store_o) {
+                if (!mul_ok(nd * R * Np * Nc * 2 * so, nsig, &t) || !add_ok(OTO, t, &OTO)) return fail(err, "size overflow (outer)");
+                OTO = align_up(OTO * 16) / 16;
+            }
+        }
+        S->vac.push_back(VAC);
+        VAC += ((nsig + 255) / 256) * 12;
+        // the paper's running accumulators: 2 doubles per site and per point of
+        // the transverse plane, per slab of the inner level (Sec. II.D)
+        const size_t area = (size_t)E.ns[(P.dirs[0] + 1) % 3] * E.ns[(P.dirs[0] + 2) % 3];
+        paper += 2 * 8 * V * area / P.tau_i;
+        // link updates
+        const size_t vh = V / 2;
+        const size_t sp_i = vh / E.nt * (E.nt - E.nt / P.tau_i);  // spatial links of one parity, one direction
+        const size_t sp_o = vh / E.nt * (E.nt - E.nt / P.tau_o);
+        const size_t per_sweep_i = (1 + P.n_or) * 2 * (vh + 3 * sp_i);
+        const size_t per_sweep_o = (1 + P.n_or) * 2 * (vh + 3 * sp_o);
+        upd_cfg += (size_t)P.n_o * ((size_t)P.k_o * per_sweep_o + (size_t)P.n_i * P.k_i * per_sweep_i);
+        upd_sweep += (1 + P.n_or) * 4 * V;
+    }
+    Lo->sz_links = align_up(L);
+    Lo->sz_hc = align_up(HC * 16);
+    Lo->sz_ho = align_up(HO * 8);
+    Lo->sz_at = align_up(AT * 16);
+    Lo->sz_ato = align_up(ATO * 16);
+    Lo->sz_ot = align_up(OT * 16);
+    Lo->sz_oto = align_up(OTO * 16);
+    size_t res;
+    if (!mul_ok((size_t)P.max_configs * P.n_ens, (size_t)P.nd_cfg * 8, &res)) return fail(err, "size overflow (results)");
+    Lo->sz_res = align_up(res);
+    // scratch
+    size_t s = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = s;
+        s = align_up(s + bytes);
+        return o;
+    };
+    const int n = P.n_ens;
+    Lo->s_ens = take(sizeof(EnsDesc) * n);
+    Lo->s_obs = take(sizeof(ObsDesc));
+    Lo->s_r = take(sizeof(int) * R);
+    Lo->s_probe = take(sizeof(int) * 4 * std::max<size_t>(Np, 1));
+    Lo->s_comp = take(sizeof(int) * std::max<size_t>(Nc, 1));
+    Lo->n_bstart_tables = kNumTabs;
+    Lo->s_bstart = take(sizeof(int) * (n + 1) * kNumTabs);
+    Lo->s_upd = take(sizeof(uint32_t) * n);
+    Lo->s_ring = take(sizeof(int) * 4);
+    Lo->s_vpart = take(sizeof(double) * VAC);
+    Lo->s_vacc = take(sizeof(double) * 24 * n);
+    Lo->s_ppart = take(sizeof(double) * 6 * 64 * n);
+    Lo->s_pout = take(sizeof(double) * 6 * n);
+    Lo->s_count = take(sizeof(unsigned long long) * 2);
+    Lo->s_stage = take(sizeof(double) * 4 * maxV);
+    Lo->sz_scr = s;
+    size_t off = 0;
+    Lo->off_links = off;
+    off += Lo->sz_links;
+    Lo->off_hc = off;
+    off += Lo->sz_hc;
+    Lo->off_ho = off;
+    off += Lo->sz_ho;
+    Lo->off_at = off;
+    off += Lo->sz_at;
+    Lo->off_ato = off;
+    off += Lo->sz_ato;
+    Lo->off_ot = off;
+    off += Lo->sz_ot;
+    Lo->off_oto = off;
+    off += Lo->sz_oto;
+    Lo->off_res = off;
+    off += Lo->sz_res;
+    Lo->off_scr = off;
+    off += Lo->sz_scr;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->ws_bytes = off;
+        info->link_bytes = Lo->sz_links;
+        info->history_bytes = Lo->sz_hc + Lo->sz_ho;
+        info->average_bytes = Lo->sz_at + Lo->sz_ato;
+        info->outer_bytes = Lo->sz_ot + Lo->sz_oto;
+        info->result_bytes = Lo->sz_res;
+        info->scratch_bytes = Lo->sz_scr;
+        info->paper_running_bytes = paper;
+        info->n_doubles_per_config = P.nd_cfg;
+        info->updates_per_config = (long)upd_cfg;
+        info->updates_per_sweep = (long)upd_sweep;
+    }
+    return true;
+}
+
+}  // namespace
+
+struct u1ml_ctx {
+    Problem P;
+    Sizes S;
+    Layout Lo;
+    u1ml_plan_info plan;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    int device = 0;
+    // device pointers
+    void* links = nullptr;
+    double2 *hc = nullptr, *at = nullptr, *ato = nullptr, *ot = nullptr, *oto = nullptr;
+    double *ho = nullptr, *res = nullptr, *vpart = nullptr, *vacc = nullptr, *ppart = nullptr, *pout = nullptr,
+           *stage = nullptr;
+    EnsDesc* d_ens = nullptr;
+    ObsDesc* d_obs = nullptr;
+    int *d_r = nullptr, *d_probe = nullptr, *d_comp = nullptr, *d_bstart = nullptr, *d_ring = nullptr;
+    uint32_t* d_upd = nullptr;
+    unsigned long long* d_count = nullptr;
+    // host mirrors
+    std::vector<EnsDesc> h_ens;
+    std::vector<int> h_bstart;  // kNumTabs x (n_ens + 1)
+    int block = 256;
+    bool initialised = false;
+    int ring_count = 0;
+    bool use_graphs = true;
+    hipGraphExec_t g_sweep = nullptr, g_ml = nullptr;
+    std::string err;
+
+    int tab_total(int tab) const { return h_bstart[(size_t)tab * (P.n_ens + 1) + P.n_ens]; }
+    const int* tab_dev(int tab) const { return d_bstart + (size_t)tab * (P.n_ens + 1); }
+};
+
+namespace {
+
+u1ml_status set_err(u1ml_ctx* c, u1ml_status s, const std::string& m)
+{
+    if (c)
+        c->err = m;
+    else
+        g_err = m;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                                    \
+    do {                                                                                                     \
+        hipError_t _e = (expr);                                                                              \
+        if (_e != hipSuccess)                                                                                \
+            return set_err((ctx), U1ML_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));          \
+    } while (0)
+
+void build_tab(u1ml_ctx* c, int tab, const std::vector<long long>& items, int block)
+{
+    const int n = c->P.n_ens;
+    int* b = &c->h_bstart[(size_t)tab * (n + 1)];
+    b[0] = 0;
+    for (int e = 0; e < n; ++e) b[e + 1] = b[e] + (int)((items[e] + block - 1) / block);
+}
+
+void build_update_tabs(u1ml_ctx* c)
+{
+    const Problem& P = c->P;
+    const int n = P.n_ens;
+    std::vector<long long> it0(n), it1(n), it2(n), it3(n);
+    for (int e = 0; e < n; ++e) {
+        const EnsDesc& E = c->h_ens[e];
+        const long long slice = (long long)E.nxh * E.ny * E.nz;
+        it0[e] = (long long)E.vh;
+        it1[e] = (long long)E.vh;
+        it2[e] = slice * (P.tau_i > 1 ? E.nt - E.nt / P.tau_i : E.nt);
+        it3[e] = slice * (P.tau_o > 1 ? E.nt - E.nt / P.tau_o : E.nt);
+    }
+    build_tab(c, kTabUpd + 0, it0, c->block);
+    build_tab(c, kTabUpd + 1, it1, c->block);
+    build_tab(c, kTabUpd + 2, it2, c->block);
+    build_tab(c, kTabUpd + 3, it3, c->block);
+}
+
+int update_class(const u1ml_ctx* c, int mu, int tau, bool* ok)
+{
+    *ok = true;
+    if (mu == 3) return 0;
+    if (tau <= 1) return 1;
+    if (tau == c->P.tau_i) return 2;
+    if (tau == c->P.tau_o) return 3;
+    *ok = false;
+    return -1;
+}
+
+hipError_t enq_phase(u1ml_ctx* c, hipStream_t st, int kind, int mu, int parity, int tau, int pass_offset)
+{
+    bool ok;
+    const int cls = update_class(c, mu, tau, &ok);
+    if (!ok) return hipErrorInvalidValue;
+    const int tab = kTabUpd + cls;
+    return launch_update(c->d_ens, c->tab_dev(tab), c->P.n_ens, c->tab_total(tab), c->block, c->P.precision, c->links,
+                         c->d_upd, pass_offset, kind, mu, parity, (mu < 3 && tau > 1) ? tau : 0, st);
+}
+
+hipError_t enq_pass(u1ml_ctx* c, hipStream_t st, int kind, int tau, int pass_offset)
+{
+    for (int mu = 0; mu < 4; ++mu)
+        for (int p = 0; p < 2; ++p) {
+            hipError_t e = enq_phase(c, st, kind, mu, p, tau, pass_offset);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+// one sweep: heatbath pass with counter offset hb, then n_or overrelaxation passes
+hipError_t enq_sweep(u1ml_ctx* c, hipStream_t st, int tau, int hb)
+{
+    hipError_t e = enq_pass(c, st, U1ML_HEATBATH, tau, hb);
+    for (int k = 0; e == hipSuccess && k < c->P.n_or; ++k) e = enq_pass(c, st, U1ML_OVERRELAX, tau, hb);
+    return e;
+}
+
+// Body of Algorithm 1 for one outer configuration.
+hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
+{
+    const Problem& P = c->P;
+    const int n = P.n_ens;
+    const int store_o = P.probes.empty() ? 0 : 1;
+    hipError_t e = launch_fill_zero(c->vacc, sizeof(double) * 24 * n, st);
+    if (e == hipSuccess && P.two) {
+        e = launch_fill_zero(c->ot, c->Lo.sz_ot, st);
+        if (e == hipSuccess && c->Lo.sz_oto) e = launch_fill_zero(c->oto, c->Lo.sz_oto, st);
+    }
+    int hb = 0;
+    for (int ko = 0; e == hipSuccess && ko < P.n_o; ++ko) {
+        if (P.two)
+            for (int k = 0; e == hipSuccess && k < P.k_o; ++k) e = enq_sweep(c, st, P.tau_o, hb++);
+        for (int m = 0; e == hipSuccess && m < P.n_i; ++m) {
+            for (int k = 0; e == hipSuccess && k < P.k_i; ++k) e = enq_sweep(c, st, P.tau_i, hb++);
+            if (e == hipSuccess)
+                e = launch_measure(c->d_ens, c->tab_dev(kTabMeas), n, c->tab_total(kTabMeas), P.precision, c->links,
+                                   c->hc, c->ho, c->vpart, m, P.tau_i, store_o, st);
+            if (e == hipSuccess) e = launch_vac_accum(c->d_ens, n, c->vpart, c->vacc, st);
+        }
+        if (e == hipSuccess)
+            e = launch_contract(c->d_ens, c->tab_dev(kTabCon), n, c->tab_total(kTabCon), c->d_obs, c->d_r, c->d_probe,
+                                c->d_comp, c->hc, c->ho, c->at, c->ato, P.n_i, st);
+        if (e == hipSuccess && P.two)
+            e = launch_combine(c->d_ens, c->tab_dev(kTabComb), n, c->tab_total(kTabComb), c->d_obs, c->at, c->ato,
+                               c->ot, c->oto, P.tau_o / P.tau_i, st);
+    }
+    const int npg = std::max<int>(1, (int)P.probes.size());
+    if (e == hipSuccess) {
+        if (P.two)
+            e = launch_product(c->d_ens, n, c->d_obs, (int)P.r.size(), npg, c->ot, c->oto, 1, 1.0 / P.n_o, c->res,
+                               c->d_ring, st);
+        else
+            e = launch_product(c->d_ens, n, c->d_obs, (int)P.r.size(), npg, c->at, c->ato, 0, 1.0, c->res, c->d_ring,
+                               st);
+    }
+    if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vacc, P.n_o * P.n_i, c->res, c->d_ring, st);
+    if (e == hipSuccess) e = launch_ring_advance(c->d_ring, st);
+    if (e == hipSuccess && hb > 0) e = launch_advance_counters(c->d_upd, n, hb, st);
+    return e;
+}
+
+hipError_t enq_sweep_with_counter(u1ml_ctx* c, hipStream_t st)
+{
+    hipError_t e = enq_sweep(c, st, 0, 0);
+    if (e == hipSuccess) e = launch_advance_counters(c->d_upd, c->P.n_ens, 1, st);
+    return e;
+}
+
+void drop_graphs(u1ml_ctx* c)
+{
+    if (c->g_sweep) (void)hipGraphExecDestroy(c->g_sweep);
+    if (c->g_ml) (void)hipGraphExecDestroy(c->g_ml);
+    c->g_sweep = c->g_ml = nullptr;
+}
+
+template <typename F>
+u1ml_status capture(u1ml_ctx* c, F&& body, hipGraphExec_t* out)
+{
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    hipError_t e = body(c->cap);
+    hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return set_err(c, U1ML_EDEVICE, std::string("kernel launch during capture: ") + hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return set_err(c, U1ML_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    hipError_t e3 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) return set_err(c, U1ML_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    return U1ML_OK;
+}
+
+// Streaming-model byte count of one phase: distinct words read + words written.
+void phase_words(const u1ml_ensemble& E, int kind, int mu, int parity, int tau, long long* words, long long* updates)
+{
+    const int n[4] = {E.ns[0], E.ns[1], E.ns[2], E.nt};
+    const long long V = (long long)n[0] * n[1] * n[2] * n[3];
+    std::vector<unsigned char> rd((size_t)(4 * V), 0);
+    long long w = 0, u = 0;
+    auto sid = [&](int c[4]) { return (long long)c[0] + n[0] * ((long long)c[1] + n[1] * ((long long)c[2] + (long long)n[2] * c[3])); };
+    for (int t = 0; t < n[3]; ++t)
+        for (int z = 0; z < n[2]; ++z)
+            for (int y = 0; y < n[1]; ++y)
+                for (int x = 0; x < n[0]; ++x) {
+                    if (((x + y + z + t) & 1) != parity) continue;
+                    if (mu < 3 && tau > 1 && t % tau == 0) continue;
+                    ++u;
+                    int c[4] = {x, y, z, t};
+                    if (kind == 1) rd[(size_t)(mu + 4 * sid(c))] = 1;
+                    for (int nu = 0; nu < 4; ++nu) {
+                        if (nu == mu) continue;
+                        int a[4], b[4], d[4], f[4];
+                        std::memcpy(a, c, sizeof a);
+                        a[mu] = (a[mu] + 1) % n[mu];  // x + mu
+                        std::memcpy(b, c, sizeof b);
+                        b[nu] = (b[nu] + 1) % n[nu];  // x + nu
+                        std::memcpy(d, c, sizeof d);
+                        d[nu] = (d[nu] - 1 + n[nu]) % n[nu];  // x - nu
+                        std::memcpy(f, a, sizeof f);
+                        f[nu] = (f[nu] - 1 + n[nu]) % n[nu];  // x + mu - nu
+                        rd[(size_t)(nu + 4 * sid(a))] = 1;
+                        rd[(size_t)(mu + 4 * sid(b))] = 1;
+                        rd[(size_t)(nu + 4 * sid(c))] = 1;
+                        rd[(size_t)(nu + 4 * sid(d))] = 1;
+                        rd[(size_t)(nu + 4 * sid(f))] = 1;
+                        rd[(size_t)(mu + 4 * sid(d))] = 1;
+                    }
+                }
+    for (unsigned char v : rd) w += v;
+    *words = w + u;
+    *updates = u;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* u1ml_status_str(u1ml_status s)
+{
+    switch (s) {
+    case U1ML_OK: return "ok";
+    case U1ML_EINVAL: return "invalid argument";
+    case U1ML_ENOMEM: return "size overflow or out of host memory";
+    case U1ML_EDEVICE: return "HIP device error";
+    case U1ML_ESTATE: return "call made in the wrong state";
+    case U1ML_ENOTSUP: return "not supported";
+    }
+    return "unknown status";
+}
+
+const char* u1ml_last_error(const u1ml_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+u1ml_status u1ml_plan(const u1ml_problem* problem, u1ml_plan_info* out)
+{
+    if (!out) return set_err(nullptr, U1ML_EINVAL, "plan output is NULL");
+    Problem P;
+    std::string err;
+    if (!read_problem(problem, &P, &err)) return set_err(nullptr, U1ML_EINVAL, err);
+    Sizes S;
+    Layout Lo;
+    if (!compute_sizes(P, &S, out, &Lo, &err)) return set_err(nullptr, U1ML_ENOMEM, err);
+    g_err.clear();
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes, void* hip_stream, u1ml_ctx** out)
+{
+    if (!out) return set_err(nullptr, U1ML_EINVAL, "output pointer is NULL");
+    *out = nullptr;
+    u1ml_ctx* c = new (std::nothrow) u1ml_ctx();
+    if (!c) return set_err(nullptr, U1ML_ENOMEM, "host allocation failed");
+    std::string err;
+    if (!read_problem(problem, &c->P, &err)) {
+        delete c;
+        return set_err(nullptr, U1ML_EINVAL, err);
+    }
+    if (!compute_sizes(c->P, &c->S, &c->plan, &c->Lo, &err)) {
+        delete c;
+        return set_err(nullptr, U1ML_ENOMEM, err);
+    }
+    if (!d_ws || ws_bytes < c->plan.ws_bytes) {
+        const size_t need = c->plan.ws_bytes;
+        delete c;
+        return set_err(nullptr, U1ML_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    }
+    if (((uintptr_t)d_ws) % kAlign != 0) {
+        delete c;
+        return set_err(nullptr, U1ML_EINVAL, "workspace must be 256-byte aligned");
+    }
+    c->ws = (char*)d_ws;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t he = hipGetDevice(&c->device);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (he != hipSuccess) {
+        delete c;
+        return set_err(nullptr, U1ML_EDEVICE, std::string("stream creation: ") + hipGetErrorString(he));
+    }
+    const Layout& Lo = c->Lo;
+    char* w = c->ws;
+    c->links = w + Lo.off_links;
+    c->hc = (double2*)(w + Lo.off_hc);
+    c->ho = (double*)(w + Lo.off_ho);
+    c->at = (double2*)(w + Lo.off_at);
+    c->ato = (double2*)(w + Lo.off_ato);
+    c->ot = (double2*)(w + Lo.off_ot);
+    c->oto = (double2*)(w + Lo.off_oto);
+    c->res = (double*)(w + Lo.off_res);
+    char* s = w + Lo.off_scr;
+    c->d_ens = (EnsDesc*)(s + Lo.s_ens);
+    c->d_obs = (ObsDesc*)(s + Lo.s_obs);
+    c->d_r = (int*)(s + Lo.s_r);
+    c->d_probe = (int*)(s + Lo.s_probe);
+    c->d_comp = (int*)(s + Lo.s_comp);
+    c->d_bstart = (int*)(s + Lo.s_bstart);
+    c->d_upd = (uint32_t*)(s + Lo.s_upd);
+    c->d_ring = (int*)(s + Lo.s_ring);
+    c->vpart = (double*)(s + Lo.s_vpart);
+    c->vacc = (double*)(s + Lo.s_vacc);
+    c->ppart = (double*)(s + Lo.s_ppart);
+    c->pout = (double*)(s + Lo.s_pout);
+    c->d_count = (unsigned long long*)(s + Lo.s_count);
+    c->stage = (double*)(s + Lo.s_stage);
+
+    const Problem& P = c->P;
+    const int n = P.n_ens;
+    c->h_ens.resize(n);
+    for (int e = 0; e < n; ++e) {
+        const u1ml_ensemble& U = P.ens[e];
+        EnsDesc& E = c->h_ens[e];
+        std::memset(&E, 0, sizeof E);
+        E.nx = U.ns[0];
+        E.ny = U.ns[1];
+        E.nz = U.ns[2];
+        E.nt = U.nt;
+        E.nxh = E.nx / 2;
+        E.nsig = E.nx * E.ny * E.nz;
+        E.vh = E.nsig * E.nt / 2;
+        E.s_in = E.nt / P.tau_i;
+        E.s_out = P.two ? E.nt / P.tau_o : E.s_in;
+        E.n_vac_blocks = (E.nsig + 255) / 256;
+        E.beta = U.beta;
+        E.sqrt_beta = std::sqrt(U.beta);
+        E.seed = U.seed;
+        E.key_id = U.key_id;
+        E.link_off = (long long)c->S.links[e];
+        E.hc_off = (long long)c->S.hc[e];
+        E.ho_off = (long long)c->S.ho[e];
+        E.at_off = (long long)c->S.at[e];
+        E.ato_off = (long long)c->S.ato[e];
+        E.ot_off = (long long)c->S.ot[e];
+        E.oto_off = (long long)c->S.oto[e];
+        E.vac_part_off = (long long)c->S.vac[e];
+    }
+    ObsDesc O;
+    std::memset(&O, 0, sizeof O);
+    O.n_dirs = P.n_dirs;
+    for (int i = 0; i < 3; ++i) O.dirs[i] = P.dirs[i];
+    O.n_r = (int)P.r.size();
+    O.n_probe = (int)P.probes.size();
+    O.n_comp = (int)P.comps.size();
+    O.store_o = P.probes.empty() ? 0 : 1;
+    O.n_doubles_per_config = P.nd_cfg;
+    std::vector<int> probe_flat;
+    for (const u1ml_probe& p : P.probes) {
+        probe_flat.push_back(p.l);
+        probe_flat.push_back(p.p1);
+        probe_flat.push_back(p.p2);
+        probe_flat.push_back(p.mode);
+    }
+    // tables
+    c->h_bstart.assign((size_t)kNumTabs * (n + 1), 0);
+    build_update_tabs(c);
+    std::vector<long long> all(n), meas(n), con(n), comb(n);
+    for (int e = 0; e < n; ++e) {
+        const EnsDesc& E = c->h_ens[e];
+        all[e] = 8ll * E.vh;
+        meas[e] = E.nsig;
+        con[e] = (long long)P.n_dirs * P.r.size() * E.s_in * E.nsig;
+        comb[e] = (long long)P.n_dirs * P.r.size() * E.s_out * E.nsig;
+    }
+    build_tab(c, kTabAll, all, 256);
+    build_tab(c, kTabMeas, meas, 256);
+    build_tab(c, kTabCon, con, 256);
+    build_tab(c, kTabComb, comb, 256);
+    std::vector<uint32_t> zeros(n, 0u);
+    int ring0[4] = {0, 0, 0, 0};
+    u1ml_status st = U1ML_OK;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (st != U1ML_OK || bytes == 0) return;
+        hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) st = set_err(nullptr, U1ML_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+    };
+    up(c->d_ens, c->h_ens.data(), sizeof(EnsDesc) * n);
+    up(c->d_obs, &O, sizeof O);
+    up(c->d_r, P.r.data(), sizeof(int) * P.r.size());
+    up(c->d_probe, probe_flat.data(), sizeof(int) * probe_flat.size());
+    up(c->d_comp, P.comps.data(), sizeof(int) * P.comps.size());
+    up(c->d_bstart, c->h_bstart.data(), sizeof(int) * c->h_bstart.size());
+    up(c->d_upd, zeros.data(), sizeof(uint32_t) * n);
+    up(c->d_ring, ring0, sizeof ring0);
+    if (st != U1ML_OK) {
+        (void)hipStreamDestroy(c->cap);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_destroy(u1ml_ctx* ctx)
+{
+    if (!ctx) return U1ML_OK;
+    drop_graphs(ctx);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    delete ctx;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_init_links(u1ml_ctx* ctx, int start)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (start != U1ML_COLD && start != U1ML_HOT) return set_err(ctx, U1ML_EINVAL, "start must be 0 (cold) or 1 (hot)");
+    HIPCHK(ctx, launch_init_links(ctx->d_ens, ctx->tab_dev(kTabAll), ctx->P.n_ens, ctx->tab_total(kTabAll),
+                                  ctx->P.precision, ctx->links, start, ctx->stream));
+    HIPCHK(ctx, launch_fill_zero(ctx->d_upd, align_up(sizeof(uint32_t) * ctx->P.n_ens), ctx->stream));
+    ctx->initialised = true;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_sweeps(u1ml_ctx* ctx, int n)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (n < 0) return set_err(ctx, U1ML_EINVAL, "n must be >= 0");
+    if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
+    if (n == 0) return U1ML_OK;
+    if (ctx->use_graphs) {
+        if (!ctx->g_sweep) {
+            u1ml_status s = capture(ctx, [&](hipStream_t st) { return enq_sweep_with_counter(ctx, st); }, &ctx->g_sweep);
+            if (s != U1ML_OK) return s;
+        }
+        for (int i = 0; i < n; ++i) HIPCHK(ctx, hipGraphLaunch(ctx->g_sweep, ctx->stream));
+    } else {
+        for (int i = 0; i < n; ++i) HIPCHK(ctx, enq_sweep_with_counter(ctx, ctx->stream));
+    }
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int pass_offset)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
+    if ((kind != 0 && kind != 1) || mu < 0 || mu > 3 || (parity != 0 && parity != 1) || pass_offset < 0)
+        return set_err(ctx, U1ML_EINVAL, "bad phase arguments");
+    bool ok;
+    update_class(ctx, mu, tau, &ok);
+    if (!ok) return set_err(ctx, U1ML_EINVAL, "tau must be <= 1 or one of the problem's level thicknesses");
+    HIPCHK(ctx, enq_phase(ctx, ctx->stream, kind, mu, parity, tau, pass_offset));
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_multilevel(u1ml_ctx* ctx)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
+    if (ctx->ring_count >= ctx->P.max_configs)
+        return set_err(ctx, U1ML_ESTATE, "results ring is full: call u1ml_copy_results");
+    if (ctx->use_graphs) {
+        if (!ctx->g_ml) {
+            u1ml_status s = capture(ctx, [&](hipStream_t st) { return enq_multilevel(ctx, st); }, &ctx->g_ml);
+            if (s != U1ML_OK) return s;
+        }
+        HIPCHK(ctx, hipGraphLaunch(ctx->g_ml, ctx->stream));
+    } else {
+        HIPCHK(ctx, enq_multilevel(ctx, ctx->stream));
+    }
+    ctx->ring_count++;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_copy_results(u1ml_ctx* ctx, double* host, size_t n_doubles, size_t* n_written)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (!host && n_doubles) return set_err(ctx, U1ML_EINVAL, "host is NULL");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const size_t avail = (size_t)ctx->ring_count * ctx->P.n_ens * (size_t)ctx->P.nd_cfg;
+    const size_t nw = std::min(avail, n_doubles);
+    if (nw) HIPCHK(ctx, hipMemcpy(host, ctx->res, nw * sizeof(double), hipMemcpyDeviceToHost));
+    int zero[4] = {0, 0, 0, 0};
+    HIPCHK(ctx, hipMemcpy(ctx->d_ring, zero, sizeof zero, hipMemcpyHostToDevice));
+    ctx->ring_count = 0;
+    if (n_written) *n_written = nw;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_get_links(u1ml_ctx* ctx, int ens, double* host, size_t n)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (ens < 0 || ens >= ctx->P.n_ens) return set_err(ctx, U1ML_EINVAL, "ensemble index out of range");
+    const long long V = 2ll * ctx->h_ens[ens].vh;
+    if (!host || n != (size_t)(4 * V)) return set_err(ctx, U1ML_EINVAL, "host buffer must hold exactly 4 V doubles");
+    HIPCHK(ctx, launch_gather_links(ctx->d_ens, ens, ctx->P.precision, ctx->links, ctx->stage, V, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(host, ctx->stage, sizeof(double) * 4 * V, hipMemcpyDeviceToHost));
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_set_links(u1ml_ctx* ctx, int ens, const double* host, size_t n)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (ens < 0 || ens >= ctx->P.n_ens) return set_err(ctx, U1ML_EINVAL, "ensemble index out of range");
+    const long long V = 2ll * ctx->h_ens[ens].vh;
+    if (!host || n != (size_t)(4 * V)) return set_err(ctx, U1ML_EINVAL, "host buffer must hold exactly 4 V doubles");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(ctx->stage, host, sizeof(double) * 4 * V, hipMemcpyHostToDevice));
+    HIPCHK(ctx, launch_scatter_links(ctx->d_ens, ens, ctx->P.precision, ctx->links, ctx->stage, V, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->initialised = true;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_get_counter(u1ml_ctx* ctx, int ens, uint32_t* counter)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (ens < 0 || ens >= ctx->P.n_ens || !counter) return set_err(ctx, U1ML_EINVAL, "bad arguments");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(counter, ctx->d_upd + ens, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_set_counter(u1ml_ctx* ctx, int ens, uint32_t counter)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (ens < 0 || ens >= ctx->P.n_ens) return set_err(ctx, U1ML_EINVAL, "bad arguments");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(ctx->d_upd + ens, &counter, sizeof(uint32_t), hipMemcpyHostToDevice));
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_plaquette(u1ml_ctx* ctx, double* out)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (!out) return set_err(ctx, U1ML_EINVAL, "out is NULL");
+    if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
+    HIPCHK(ctx, launch_plaquette(ctx->d_ens, ctx->P.n_ens, 0, ctx->P.precision, ctx->links, ctx->ppart, ctx->pout,
+                                 ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(out, ctx->pout, sizeof(double) * 6 * ctx->P.n_ens, hipMemcpyDeviceToHost));
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_health(u1ml_ctx* ctx, uint64_t* n_bad)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (!n_bad) return set_err(ctx, U1ML_EINVAL, "n_bad is NULL");
+    HIPCHK(ctx, launch_fill_zero(ctx->d_count, 16, ctx->stream));
+    HIPCHK(ctx, launch_health(ctx->d_ens, ctx->tab_dev(kTabAll), ctx->P.n_ens, ctx->tab_total(kTabAll),
+                              ctx->P.precision, ctx->links, ctx->d_count, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    unsigned long long v = 0;
+    HIPCHK(ctx, hipMemcpy(&v, ctx->d_count, sizeof v, hipMemcpyDeviceToHost));
+    *n_bad = v;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+        return set_err(ctx, U1ML_EINVAL, "block must be 64, 128, 256, 512 or 1024");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->block = block;
+    build_update_tabs(ctx);
+    HIPCHK(ctx, hipMemcpy(ctx->d_bstart, ctx->h_bstart.data(), sizeof(int) * 4 * (ctx->P.n_ens + 1),
+                          hipMemcpyHostToDevice));
+    drop_graphs(ctx);
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_set_graphs(u1ml_ctx* ctx, int enable)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    ctx->use_graphs = enable != 0;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int n_rep, double* us)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (!us || n_rep < 1) return set_err(ctx, U1ML_EINVAL, "bad arguments");
+    if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
+    bool ok;
+    update_class(ctx, mu, tau, &ok);
+    if (!ok) return set_err(ctx, U1ML_EINVAL, "tau must be <= 1 or one of the problem's level thicknesses");
+    hipEvent_t a, b;
+    HIPCHK(ctx, hipEventCreate(&a));
+    HIPCHK(ctx, hipEventCreate(&b));
+    HIPCHK(ctx, hipEventRecord(a, ctx->stream));
+    for (int i = 0; i < n_rep; ++i) HIPCHK(ctx, enq_phase(ctx, ctx->stream, kind, mu, parity, tau, 0));
+    HIPCHK(ctx, hipEventRecord(b, ctx->stream));
+    HIPCHK(ctx, hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *us = 1000.0 * ms / n_rep;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_phase_bytes(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, double* bytes, long* updates)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (!bytes || !updates || mu < 0 || mu > 3 || (parity & ~1) || (kind & ~1))
+        return set_err(ctx, U1ML_EINVAL, "bad arguments");
+    const double word = ctx->P.precision == U1ML_FP64 ? 8.0 : 4.0;
+    double b = 0;
+    long u = 0;
+    for (const u1ml_ensemble& E : ctx->P.ens) {
+        long long w, uu;
+        phase_words(E, kind, mu, parity, tau, &w, &uu);
+        b += w * word;
+        u += (long)uu;
+    }
+    *bytes = b;
+    *updates = u;
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_autotune(u1ml_ctx* ctx, u1ml_tune_report* report)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
+    const int cand[5] = {64, 128, 256, 512, 1024};
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    // save links and counters so tuning leaves no trace
+    const size_t lbytes = ctx->Lo.sz_links;
+    void* saved = nullptr;
+    HIPCHK(ctx, hipMalloc(&saved, lbytes));
+    hipError_t he = hipMemcpy(saved, ctx->links, lbytes, hipMemcpyDeviceToDevice);
+    std::vector<uint32_t> upd(ctx->P.n_ens);
+    if (he == hipSuccess) he = hipMemcpy(upd.data(), ctx->d_upd, sizeof(uint32_t) * upd.size(), hipMemcpyDeviceToHost);
+    if (he != hipSuccess) {
+        (void)hipFree(saved);
+        return set_err(ctx, U1ML_EDEVICE, std::string("autotune save: ") + hipGetErrorString(he));
+    }
+    const int old_block = ctx->block;
+    const bool old_graphs = ctx->use_graphs;
+    ctx->use_graphs = false;
+    double best = 1e300;
+    int best_b = old_block;
+    u1ml_tune_report rep;
+    std::memset(&rep, 0, sizeof rep);
+    u1ml_status st = U1ML_OK;
+    const int tau = ctx->P.tau_i;
+    for (int i = 0; i < 5 && st == U1ML_OK; ++i) {
+        st = u1ml_set_block(ctx, cand[i]);
+        if (st != U1ML_OK) break;
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            st = set_err(ctx, U1ML_EDEVICE, "event creation failed");
+            break;
+        }
+        hipError_t e = enq_sweep(ctx, ctx->stream, tau, 0);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+        for (int k = 0; k < 5 && e == hipSuccess; ++k) e = enq_sweep(ctx, ctx->stream, tau, 0);
+        if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (e != hipSuccess) {
+            st = set_err(ctx, U1ML_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+            break;
+        }
+        rep.block[i] = cand[i];
+        rep.us_per_sweep[i] = 1000.0 * ms / 5;
+        rep.n_candidates = i + 1;
+        if (rep.us_per_sweep[i] < best) {
+            best = rep.us_per_sweep[i];
+            best_b = cand[i];
+        }
+    }
+    hipError_t e1 = hipMemcpy(ctx->links, saved, lbytes, hipMemcpyDeviceToDevice);
+    hipError_t e2 = hipMemcpy(ctx->d_upd, upd.data(), sizeof(uint32_t) * upd.size(), hipMemcpyHostToDevice);
+    (void)hipFree(saved);
+    ctx->use_graphs = old_graphs;
+    if (st != U1ML_OK) {
+        u1ml_set_block(ctx, old_block);
+        return st;
+    }
+    if (e1 != hipSuccess || e2 != hipSuccess) return set_err(ctx, U1ML_EDEVICE, "autotune restore failed");
+    st = u1ml_set_block(ctx, best_b);
+    rep.chosen_block = best_b;
+    if (report) *report = rep;
+    return st;
+}
+
+u1ml_status u1ml_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, size_t n,
+                             uint32_t* d_out, void* hip_stream)
+{
+    if (!d_out && n) return set_err(nullptr, U1ML_EINVAL, "d_out is NULL");
+    if (n > 0xFFFFFFFFull) return set_err(nullptr, U1ML_EINVAL, "n must be < 2^32");
+    hipError_t e = launch_philox_fill(k0, k1, c0, c1, c2, c3, n, d_out, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return set_err(nullptr, U1ML_EDEVICE, hipGetErrorString(e));
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_vonmises_fill(double kappa, int precision, uint32_t seed, uint32_t key_id, uint32_t c0, uint32_t c1,
+                               size_t n, double* d_out, int* d_attempts, void* hip_stream)
+{
+    if (!d_out && n) return set_err(nullptr, U1ML_EINVAL, "d_out is NULL");
+    if (!(kappa >= 0) || !std::isfinite(kappa)) return set_err(nullptr, U1ML_EINVAL, "kappa must be finite and >= 0");
+    if (precision != U1ML_FP64 && precision != U1ML_FP32) return set_err(nullptr, U1ML_EINVAL, "bad precision");
+    if (n > 0xFFFFFFFFull) return set_err(nullptr, U1ML_EINVAL, "n must be < 2^32");
+    hipError_t e = launch_vonmises_fill(kappa, precision, seed, key_id, c0, c1, n, d_out, d_attempts,
+                                        (hipStream_t)hip_stream);
+    if (e != hipSuccess) return set_err(nullptr, U1ML_EDEVICE, hipGetErrorString(e));
+    return U1ML_OK;
+}
+
+}  // extern "C"

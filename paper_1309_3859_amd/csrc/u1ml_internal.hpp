@@ -1,0 +1,76 @@
+// u1ml_internal.hpp -- data shared by the host scheduler and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace u1ml {
+
+// Per-ensemble descriptor, resident in device memory.  Offsets are element
+// offsets into the workspace sections (links: real; history phases, slab
+// averages and outer sums: double2; history O sums: double).
+struct EnsDesc {
+    int nx, ny, nz, nt;
+    int nxh, nsig, vh, s_in;  // s_in: slabs of the innermost level
+    int s_out, n_vac_blocks, pad0, pad1;
+    double beta, sqrt_beta;
+    uint32_t seed, key_id;
+    long long link_off;
+    long long hc_off, ho_off;
+    long long at_off, ato_off;
+    long long ot_off, oto_off;
+    long long vac_part_off;  // double, [n_vac_blocks][12]
+};
+
+// Observable tables in device memory.
+struct ObsDesc {
+    int n_dirs;
+    int dirs[3];
+    int n_r, n_probe, n_comp;
+    int store_o;  // 1 if insertions are requested (history keeps O sums)
+    long long n_doubles_per_config;
+};
+
+constexpr int kUpdateClasses = 4;  // temporal, spatial full, spatial inner tau, spatial outer tau
+
+// --- launchers (k_update.hip) ---
+hipError_t launch_init_links(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
+                             void* links, int start, hipStream_t st);
+hipError_t launch_update(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
+                         int precision, void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu,
+                         int parity, int tau, hipStream_t st);
+hipError_t launch_health(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
+                         const void* links, unsigned long long* d_count, hipStream_t st);
+hipError_t launch_plaquette(const EnsDesc* d_ens, int n_ens, int max_blocks_per_ens, int precision, const void* links,
+                            double* d_partials, double* d_out, hipStream_t st);
+hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, size_t n,
+                              uint32_t* d_out, hipStream_t st);
+hipError_t launch_vonmises_fill(double kappa, int precision, uint32_t seed, uint32_t key_id, uint32_t c0, uint32_t c1,
+                                size_t n, double* d_out, int* d_att, hipStream_t st);
+hipError_t launch_advance_counters(uint32_t* d_upd, int n_ens, int delta, hipStream_t st);
+hipError_t launch_gather_links(const EnsDesc* d_ens, int ens, int precision, const void* links, double* d_canon,
+                               long long n_sites, hipStream_t st);
+hipError_t launch_scatter_links(const EnsDesc* d_ens, int ens, int precision, void* links, const double* d_canon,
+                                long long n_sites, hipStream_t st);
+
+// --- launchers (k_measure.hip) ---
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_measure(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int precision,
+                          const void* links, double2* hist_c, double* hist_o, double* vac_part, int m, int tau,
+                          int store_o, hipStream_t st);
+hipError_t launch_vac_accum(const EnsDesc* d_ens, int n_ens, const double* vac_part, double* vac_acc,
+                            hipStream_t st);
+hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
+                           const int* d_r, const int* d_probe, const int* d_comp, const double2* hist_c,
+                           const double* hist_o, double2* avg_t, double2* avg_to, int n_meas, hipStream_t st);
+hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
+                          const double2* avg_t, const double2* avg_to, double2* out_t, double2* out_to, int q,
+                          hipStream_t st);
+hipError_t launch_product(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, int n_r, int n_pgroups,
+                          const double2* src_t, const double2* src_to, int use_outer, double scale, double* results,
+                          const int* d_ring, hipStream_t st);
+hipError_t launch_vac_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, const double* vac_acc,
+                            int n_meas, double* results, const int* d_ring, hipStream_t st);
+hipError_t launch_ring_advance(int* d_ring, hipStream_t st);
+
+}  // namespace u1ml

@@ -1,0 +1,112 @@
+"""Host-side checks of libu1ml that need no GPU: the shared library loads and
+exports every call include/u1ml.h declares, and the pure-host planner
+validates problems and sizes the workspace (including the paper's worked
+memory example)."""
+import json
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def u1():
+    from paper_1309_3859_amd import build, u1ml
+
+    if not os.path.exists(u1ml.LIB_PATH):
+        build.build()
+    u1ml.lib()
+    return u1ml
+
+
+def test_library_exports_every_declared_call(u1):
+    hdr = open(os.path.join(ROOT, "include", "u1ml.h")).read()
+    declared = set(re.findall(r"\b(u1ml_[a-z_0-9]+)\s*\(", hdr))
+    lib = u1.lib()
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", u1.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (u1ml_[a-z_0-9]+)", out))
+    assert declared == exported
+
+
+def _spec(u1, **kw):
+    base = dict(ensembles=[u1.Ens((4, 4, 4), 4, 1.0)], levels=[(2, 10, 1)], r=[1, 2], dirs=[0],
+                probes=[(0, 0, 0, 1)], comps=[0])
+    base.update(kw)
+    return u1.Spec(**base)
+
+
+BAD = [
+    ("odd extent", dict(ens=((5, 4, 4), 4, 1.0))),
+    ("extent 0", dict(ens=((0, 4, 4), 4, 1.0))),
+    ("nt not multiple of tau", dict(ens=((4, 4, 4), 6, 1.0), levels=[(4, 2, 1)])),
+    ("nan beta", dict(ens=((4, 4, 4), 4, float("nan")))),
+    ("negative beta", dict(ens=((4, 4, 4), 4, -1.0))),
+    ("r >= Ns", dict(r=[4])),
+    ("r = 0", dict(r=[0])),
+    ("tau 1", dict(levels=[(1, 2, 1)])),
+    ("outer not multiple", dict(ens=((4, 4, 4), 12, 1.0), levels=[(6, 2, 1), (4, 2, 1)])),
+    ("n_iter 0", dict(levels=[(2, 0, 1)])),
+    ("k negative", dict(levels=[(2, 2, -1)])),
+    ("probe too far", dict(probes=[(0, 2, 0, 1)])),
+    ("bad component", dict(comps=[6])),
+    ("bad axis", dict(dirs=[3])),
+    ("repeated axis", dict(dirs=[0, 0])),
+    ("probes without comps", dict(comps=[])),
+]
+
+
+@pytest.mark.parametrize("name,kw", BAD, ids=[b[0] for b in BAD])
+def test_planner_rejects_invalid_problems(u1, name, kw):
+    kw = dict(kw)
+    if "ens" in kw:
+        ns, nt, beta = kw.pop("ens")
+        kw["ensembles"] = [u1.Ens(ns, nt, beta)]
+    with pytest.raises(u1.U1MLError) as ei:
+        u1.plan(_spec(u1, **kw))
+    assert ei.value.status == 1  # EINVAL
+    assert str(ei.value).strip() != "EINVAL:"
+
+
+def test_planner_accepts_presets_and_counts_updates(u1):
+    from paper_1309_3859_amd import configs
+
+    spec, _ = configs.c1_plain_fp64()
+    p = u1.plan(spec)
+    # C1 by brute force: per sweep (1 + 3 passes), each pass updates every
+    # temporal link and the spatial links off the frozen layers t = 0 mod 2
+    L = 4
+    per_pass = sum(1 for t in range(L) for _ in range(L ** 3)) + 3 * sum(
+        1 for t in range(L) if t % 2 for _ in range(L ** 3))
+    assert p["updates_per_config"] == 10 * 4 * per_pass == 25600
+    assert p["updates_per_sweep"] == 4 * 4 * L ** 4
+    assert p["n_doubles_per_config"] == spec.n_doubles_per_config()
+    for name in ("c2", "c3", "c4"):
+        s, _ = configs.PRESETS[name]()
+        assert u1.plan(s)["ws_bytes"] < 16 * 2**30
+
+
+def test_paper_memory_example(u1):
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_memory_example.json")))
+    spec = u1.Spec(ensembles=[u1.Ens(tuple(g["ns"]), g["nt"], 1.0)], levels=[(g["tau"], 1, 1)], r=[1], dirs=[0])
+    p = u1.plan(spec)
+    assert p["paper_running_bytes"] == g["bytes"]
+    assert round(g["bytes"] / 2**20) == g["paper_states_MB"]
+    # the paper's "1.7 MB" is one link direction in FP64; the library stores all four
+    spec64 = u1.Spec(ensembles=[u1.Ens(tuple(g["ns"]), g["nt"], 1.0)], levels=[(2, 1, 1)], r=[1], precision=u1.FP64)
+    assert u1.plan(spec64)["link_bytes"] == 4 * g["link_bytes_one_direction"]
+
+
+def test_workspace_too_small_is_rejected_before_any_device_call(u1):
+    import ctypes as C
+
+    spec = _spec(u1)
+    h = C.c_void_p()
+    st = u1.lib().u1ml_create(C.byref(spec.struct()), C.c_void_p(256), 16, None, C.byref(h))
+    assert st == 1 and not h.value
+    assert b"workspace too small" in u1.lib().u1ml_last_error(None)

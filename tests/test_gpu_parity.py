@@ -1,0 +1,348 @@
+"""GPU path (libu1ml through its C ABI) against the FP64 CPU oracle.
+
+Element-wise parity on identical inputs wherever the two follow the same
+arithmetic: Philox blocks bit-exact, von Mises draws, every checkerboard
+phase (both update kinds, every direction and parity, frozen masks),
+plaquettes, the multilevel measurement and estimator chain.  Overrelaxation
+amplifies rounding-level differences (about 30x per pass, measured on the
+oracle itself), so whole trajectories are compared with heatbath-only sweeps,
+and the full dynamics statistically.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from helpers.inputs import random_links, random_links_fp32
+from helpers.stats import batch_mean_err, circ_dist
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as O
+    from paper_1309_3859_amd import u1ml
+
+    u1ml.lib()
+    O.build()
+    return u1ml, O, torch
+
+
+def _ctx(u1, ns, nt, beta=1.0, levels=((4, 1, 1), (2, 1, 1)), precision=0, n_or=3, seed=1, key_id=0, **kw):
+    spec = u1.Spec(ensembles=[u1.Ens(tuple(ns), nt, beta, seed=seed, key_id=key_id)], levels=list(levels),
+                   r=kw.pop("r", [1]), dirs=kw.pop("dirs", [0]), probes=kw.pop("probes", ()),
+                   comps=kw.pop("comps", ()), precision=precision, n_or=n_or, max_configs=kw.pop("max_configs", 4))
+    return spec, u1.Context(spec)
+
+
+def test_philox_bit_exact(env):
+    u1, O, torch = env
+    for key in [(0, 0), (1, 2), (0xDEADBEEF, 0x12345678)]:
+        for ctr in [(0, 0, 0, 0), (123456, 7, 3, 0), (0xFFFFFFF0, 1, 2, 3)]:
+            say("philox", key, ctr)
+            dev = u1.philox_fill(key, ctr, 2048).cpu().numpy().view(np.uint32)
+            ref = np.array([O.philox(((ctr[0] + i) & 0xFFFFFFFF, ctr[1], ctr[2], ctr[3]), key) for i in range(2048)])
+            assert np.array_equal(dev, ref)
+
+
+@pytest.mark.parametrize("kappa", [0.0, 1e-8, 0.5, 3.0, 6.0, 20.0])
+def test_vonmises_fp64_draws_match_oracle(env, kappa):
+    u1, O, torch = env
+    say("vonmises fp64", kappa)
+    n = 20000
+    psi, att = u1.vonmises_fill(kappa, n, precision=u1.FP64, seed=17, key_id=5, c0=100, c1=3)
+    ref, _ = O.vonmises_many(kappa, n, seed=17, key_id=5, c0_start=100, c1=3, domain=O.DOM_TEST)
+    psi = psi.cpu().numpy()
+    att = att.cpu().numpy()
+    # psi = arccos(f) amplifies a 1-ulp difference in f by 1/|sin psi|, so the
+    # well-conditioned comparison is on cos(psi) (= f) and on the sign
+    same = np.abs(np.cos(psi) - np.cos(ref)) < 1e-14
+    same &= (np.sign(psi) == np.sign(ref)) | (np.abs(psi) < 1e-6)
+    assert np.count_nonzero(~same) <= 2  # an accept/reject decision may flip at rounding level
+    assert np.all(att > 0)
+
+
+@pytest.mark.parametrize("kappa", [0.5, 3.0, 20.0])
+def test_vonmises_fp32_statistics(env, kappa):
+    from scipy import special
+
+    u1, O, torch = env
+    say("vonmises fp32", kappa)
+    n = 400_000
+    psi, att = u1.vonmises_fill(kappa, n, precision=u1.FP32, seed=3, key_id=9)
+    psi = psi.cpu().numpy()
+    assert np.all(np.abs(psi) <= np.pi + 1e-6)
+    for m in (1, 2):
+        c = np.cos(m * psi)
+        exact = special.iv(m, kappa) / special.iv(0, kappa)
+        assert abs(c.mean() - exact) < 5 * c.std() / np.sqrt(n) + 1e-6
+    assert att.float().mean().item() < 1.6
+
+
+def test_init_matches_oracle(env):
+    u1, O, torch = env
+    for ns, nt in [((4, 4, 4), 4), ((6, 4, 2), 8)]:
+        spec, ctx = _ctx(u1, ns, nt, seed=11, key_id=2)
+        ref = O.Lattice(4, list(ns) + [nt], 1.0, seed=11, key_id=2)
+        for start in (0, 1):
+            say("init", ns, nt, start)
+            ctx.init_links(start)
+            ref.init(start)
+            assert np.array_equal(ctx.links(0), ref.links())
+            assert ctx.counter(0) == 0
+
+
+GEOMS = [((4, 4, 4), 4), ((6, 4, 2), 8)]
+
+
+@pytest.mark.parametrize("ns,nt", GEOMS)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_phase_matches_oracle(env, ns, nt, precision):
+    """Each checkerboard phase from identical links and counter: FP64 within
+    1e-12 on the circle; FP32 storage within 2e-5 (hardware sin/cos), with
+    heatbath accept/reject flips counted apart (at most a few)."""
+    u1, O, torch = env
+    V = int(np.prod(ns)) * nt
+    spec, ctx = _ctx(u1, ns, nt, beta=1.1, precision=precision, seed=7, key_id=1)
+    ref = O.Lattice(4, list(ns) + [nt], 1.1, seed=7, key_id=1)
+    th0 = random_links_fp32(V, 5) if precision else random_links(V, 5)
+    worst = 0.0
+    flips = 0
+    for kind, mu, p, tau in itertools.product((0, 1), range(4), (0, 1), (0, 2, 4)):
+        say("phase", precision, ns, nt, kind, mu, p, tau)
+        ctx.set_links(th0)
+        ctx.set_counter(9)
+        ref.set_links(th0)
+        ref.counter = 9
+        ctx.phase(kind, mu, p, tau)
+        ref.phase(kind, mu, p, tau)
+        d = circ_dist(ctx.links(0), ref.links())
+        if precision == 0:
+            assert d.max() < 1e-12, (kind, mu, p, tau, d.max())
+        else:
+            big = d > 2e-5
+            flips += int(big.sum())
+            worst = max(worst, float(d[~big].max()))
+    if precision:
+        say("fp32 phases: worst", worst, "flips", flips)
+        assert flips <= 3
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plaquette_matches_oracle(env, precision):
+    u1, O, torch = env
+    ns, nt = (6, 4, 2), 8
+    V = int(np.prod(ns)) * nt
+    spec, ctx = _ctx(u1, ns, nt, precision=precision)
+    ref = O.Lattice(4, list(ns) + [nt], 1.0)
+    th = random_links_fp32(V, 8)
+    ctx.set_links(th)
+    ref.set_links(th)
+    say("plaquette", precision)
+    assert np.max(np.abs(ctx.plaquette()[0] - ref.plaquette_means())) < 1e-13
+
+
+def test_sweep_parity_per_pass_fp64(env):
+    """One full sweep (1 heatbath + 3 overrelaxation passes) from identical
+    links.  The heatbath pass agrees within 1e-12.  Overrelaxation amplifies
+    any rounding-level difference (arg A moves by delta/|A|), so after each
+    pass the GPU-vs-oracle deviation is bounded by 10x the deviation between
+    the oracle and itself started from links perturbed by 1e-15."""
+    u1, O, torch = env
+    ns, nt = (4, 4, 4), 4
+    spec, ctx = _ctx(u1, ns, nt, beta=1.0, levels=[(2, 1, 1)])
+    ref = O.Lattice(4, [4, 4, 4, 4], 1.0, seed=1)
+    pert = O.Lattice(4, [4, 4, 4, 4], 1.0, seed=1)
+    th = random_links(256, 12)
+    ctx.set_links(th)
+    ref.set_links(th)
+    pert.set_links(th + np.random.default_rng(0).uniform(-1e-15, 1e-15, th.size))
+    devs, own = [], []
+    for k in range(4):
+        for mu in range(4):
+            for p in range(2):
+                ctx.phase(0 if k == 0 else 1, mu, p, 0, 0)
+        ref.pass_(0 if k == 0 else 1, 0)
+        pert.pass_(0 if k == 0 else 1, 0)
+        devs.append(float(circ_dist(ctx.links(0), ref.links()).max()))
+        own.append(float(circ_dist(pert.links(), ref.links()).max()))
+    say("per-pass max deviation gpu-oracle", devs, "oracle-perturbed oracle", own)
+    assert devs[0] < 1e-12
+    for d, o in zip(devs, own):
+        assert d <= 10 * o + 1e-13
+
+
+def _multilevel_pair(env, ns, nt, levels, n_or, r, dirs, probes, comps, beta=1.0, seed=3, precision=0, start_seed=21):
+    u1, O, torch = env
+    V = int(np.prod(ns)) * nt
+    spec, ctx = _ctx(u1, ns, nt, beta=beta, levels=levels, n_or=n_or, r=r, dirs=dirs, probes=probes, comps=comps,
+                     seed=seed, precision=precision)
+    ref = O.Lattice(4, list(ns) + [nt], beta, seed=seed)
+    th = random_links_fp32(V, start_seed) if precision else random_links(V, start_seed)
+    ctx.set_links(th)
+    ctx.set_counter(4)
+    ref.set_links(th)
+    ref.counter = 4
+    ctx.multilevel()
+    got = spec.unpack(ctx.results()[0, 0])
+    ospec = O.MLSpec(levels=levels, r=r, dirs=dirs, probes=probes, comps=comps, n_or=n_or)
+    want = ospec.unpack(ref.multilevel(ospec))
+    return got, want, ctx, ref
+
+
+PROBES = [(0, 0, 0, 1), (1, 1, -1, 1), (-1, 2, 1, 0)]
+
+
+@pytest.mark.parametrize("levels", [[(2, 3, 0)], [(4, 2, 0), (2, 3, 0)], [(4, 3, 0)]])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_measurement_and_estimators_match_oracle(env, levels, precision):
+    """k = 0: no updates, so both sides measure the same links; the whole
+    measurement -> slab average -> combine -> product -> sum chain is compared."""
+    say("measurement parity", levels, precision)
+    got, want, _, _ = _multilevel_pair(env, (6, 6, 8), 8, levels, 3, [1, 2, 3], [0, 1, 2], PROBES, list(range(6)),
+                                       precision=precision)
+    tol_c = 1e-12
+    tol_o = 1e-12 if precision == 0 else 1e-5
+    assert np.max(np.abs(got["C"] - want["C"])) < tol_c
+    assert np.max(np.abs(got["CO"] - want["CO"])) < tol_o * max(1.0, np.abs(want["CO"]).max())
+    assert np.max(np.abs(got["vac_sq"] - want["vac_sq"])) < (1e-12 if precision == 0 else 1e-6)
+    assert np.max(np.abs(got["vac_lin"] - want["vac_lin"])) < (1e-12 if precision == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("levels", [[(2, 4, 1)], [(4, 2, 1), (2, 3, 1)]])
+def test_multilevel_trajectory_parity_heatbath_only(env, levels):
+    """Whole multilevel configurations (updates included) with heatbath-only
+    sweeps, where rounding differences stay at the 1e-13 level."""
+    say("trajectory parity", levels)
+    got, want, ctx, ref = _multilevel_pair(env, (4, 4, 4), 8, levels, 0, [1, 2], [0, 1], PROBES[:2], [0, 3, 4])
+    # the heatbath's arccos amplifies rounding differences near psi = 0 a little
+    assert np.max(circ_dist(ctx.links(0), ref.links())) < 1e-9
+    assert ctx.counter(0) == ref.counter
+    assert np.max(np.abs(got["C"] - want["C"])) < 1e-10
+    assert np.max(np.abs(got["CO"] - want["CO"])) < 1e-9
+
+
+def _chain(u1, spec, start, therm, n_conf, between=1):
+    ctx = u1.Context(spec)
+    ctx.init_links(start)
+    ctx.sweeps(therm)
+    out = []
+    for _ in range(n_conf):
+        ctx.multilevel()
+        ctx.sweeps(between)
+        out.append(spec.unpack(ctx.results()[0, 0]))
+    return out, ctx
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c1_statistical_parity_with_overrelaxation(env, precision):
+    """The C1 workload (1 heatbath + 3 overrelaxation) on the GPU and on the
+    oracle as independent chains: correlators and insertions agree within 4
+    combined standard errors."""
+    u1, O, torch = env
+    from paper_1309_3859_amd import configs
+
+    spec, sched = configs.c1_plain_fp64()
+    spec.precision = precision
+    n = 400
+    say("c1 statistical", precision)
+    g, _ = _chain(u1, spec, sched["start"], sched["therm"], n)
+    ref = O.Lattice(4, [4, 4, 4, 4], 1.0, seed=1)
+    ref.init(sched["start"])
+    ref.sweeps(sched["therm"])
+    ospec = O.MLSpec(levels=spec.levels, r=spec.r, dirs=spec.dirs, probes=spec.probes, comps=spec.comps)
+    w = []
+    for _ in range(n):
+        w.append(ospec.unpack(ref.multilevel(ospec)))
+        ref.sweeps(1)
+    for key, f in [("C", lambda x: x["C"].real), ("COsq", lambda x: x["CO"][:, 0, 0, 0].real),
+                   ("COlin", lambda x: x["CO"][:, 0, 0, 1].imag), ("vac", lambda x: x["vac_sq"][:3])]:
+        mg, eg = batch_mean_err(np.array([f(x) for x in g]))
+        mw, ew = batch_mean_err(np.array([f(x) for x in w]))
+        say(key, mg, eg, mw, ew)
+        assert np.all(np.abs(mg - mw) < 4 * np.sqrt(eg**2 + ew**2) + 1e-12), key
+
+
+def test_results_independent_of_tile_batch_and_graphs(env):
+    """Same ensemble alone or inside a batch of uneven ensembles, any work-group
+    size, graphs on or off: bit-identical links and estimates."""
+    u1, O, torch = env
+    A = u1.Ens((6, 4, 4), 8, 1.0, seed=3, key_id=7)
+    B = u1.Ens((4, 4, 8), 4, 0.9, seed=3, key_id=1)
+    Cc = u1.Ens((8, 8, 4), 4, 1.05, seed=9, key_id=2)
+    kw = dict(levels=[(4, 2, 1), (2, 2, 1)], r=[1, 2, 3], dirs=[0], probes=[(0, 0, 0, 1), (0, 1, 1, 1)],
+              comps=[0, 1, 5], precision=1, n_or=3, max_configs=2)
+    runs = []
+    for ens_list, idx, block, graphs in [([A], 0, 256, True), ([B, A, Cc], 1, 64, False), ([Cc, B, A], 2, 1024, True),
+                                         ([A, B], 0, 128, False)]:
+        say("determinism", len(ens_list), block, graphs)
+        spec = u1.Spec(ensembles=ens_list, **kw)
+        ctx = u1.Context(spec)
+        ctx.set_block(block)
+        ctx.set_graphs(graphs)
+        ctx.init_links(1)
+        ctx.sweeps(3)
+        ctx.multilevel()
+        res = ctx.results()[0, idx]
+        runs.append((ctx.links(idx), res, ctx.counter(idx)))
+    for th, res, cnt in runs[1:]:
+        assert np.array_equal(th, runs[0][0])
+        assert np.array_equal(res, runs[0][1])
+        assert cnt == runs[0][2]
+
+
+def test_checkpoint_resume_is_bit_exact(env):
+    u1, O, torch = env
+    kw = dict(levels=[(2, 2, 1)], r=[1], dirs=[0])
+    spec = u1.Spec(ensembles=[u1.Ens((4, 4, 4), 8, 1.0, seed=2)], precision=1, **kw)
+    a = u1.Context(spec)
+    a.init_links(1)
+    a.sweeps(6)
+    a.multilevel()
+    straight = a.links(0), a.results()[0, 0]
+    b = u1.Context(spec)
+    b.init_links(1)
+    b.sweeps(3)
+    saved, cnt = b.links(0), b.counter(0)
+    del b
+    c = u1.Context(spec)
+    c.set_links(saved)
+    c.set_counter(cnt)
+    c.sweeps(3)
+    c.multilevel()
+    assert np.array_equal(c.links(0), straight[0])
+    assert np.array_equal(c.results()[0, 0], straight[1])
+
+
+def test_health_and_state_errors(env):
+    u1, O, torch = env
+    spec = u1.Spec(ensembles=[u1.Ens((4, 4, 4), 4, 1.0)], levels=[(2, 1, 1)], r=[1], max_configs=1)
+    ctx = u1.Context(spec)
+    with pytest.raises(u1.U1MLError) as ei:
+        ctx.multilevel()
+    assert ei.value.status == 4  # ESTATE: links never initialised
+    ctx.init_links(0)
+    assert ctx.health() == 0
+    th = ctx.links(0)
+    th[5] = np.nan
+    th[17] = 4.0
+    ctx.set_links(th)
+    assert ctx.health() == 2
+    ctx.init_links(1)
+    ctx.multilevel()
+    with pytest.raises(u1.U1MLError) as ei:
+        ctx.multilevel()
+    assert ei.value.status == 4  # ring full
+    assert ctx.results().shape[0] == 1
+    ctx.multilevel()

@@ -184,3 +184,24 @@ def test_checkerboard_schedule(orc, L):
                 expect = {(s, mu) for s in members
                           if not (tau > 1 and mu < 3 and _coords(L, s)[3] % tau == 0)}
                 assert changed == expect, (mu, p, tau)
+
+
+def test_overrelaxation_conditioning(orc):
+    """The dynamics itself amplifies rounding-level differences: links perturbed
+    by 1e-15 drift apart by more than 1e-9 within one sweep, almost all of it
+    in the overrelaxation passes.  This is why GPU-vs-oracle comparisons of
+    whole sweeps use the oracle's own response as their tolerance."""
+    from helpers.inputs import random_links
+
+    th = random_links(256, 12)
+    a = orc.Lattice(4, [4, 4, 4, 4], 1.0, seed=1)
+    b = orc.Lattice(4, [4, 4, 4, 4], 1.0, seed=1)
+    a.set_links(th)
+    b.set_links(th + np.random.default_rng(0).uniform(-1e-15, 1e-15, th.size))
+    devs = []
+    for k in range(4):
+        a.pass_(0 if k == 0 else 1, 0)
+        b.pass_(0 if k == 0 else 1, 0)
+        devs.append(circ_dist(a.links(), b.links()).max())
+    assert devs[0] < 1e-12
+    assert devs[3] > 1e-9 and devs[3] < 1e-4
