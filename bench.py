@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--workload", default="c4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
     return ap.parse_args()
 
 
@@ -77,6 +78,27 @@ def cpu_baseline(spec, budget_s: float):
                       f"levels {levels} (tau, n_iter, k_sweeps), FP64, single thread; {t_used:.1f} s"}
 
 
+def time_steps(ctx, steps: int, warmup: int):
+    """Warm up, then time `steps` multilevel configurations with events on the
+    context's stream; returns milliseconds."""
+    import torch
+
+    for _ in range(warmup):
+        ctx.multilevel()
+    torch.cuda.synchronize()
+    ctx.results()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(ctx.stream)
+    for _ in range(steps):
+        ctx.multilevel()
+    stop.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    assert ctx.results().shape[0] == steps
+    return ms
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -95,22 +117,8 @@ def main():
     ctx.init_links(sched["start"])
     tune = ctx.autotune()
     ctx.sweeps(20)
-    for _ in range(args.warmup):
-        ctx.multilevel()
-    torch.cuda.synchronize()
-    ctx.results()
     upd = ctx.plan["updates_per_config"]
-
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(ctx.stream)
-    for _ in range(args.steps):
-        ctx.multilevel()
-    stop.record(ctx.stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
-    res = ctx.results()
-    assert res.shape[0] == args.steps
+    ms = time_steps(ctx, args.steps, args.warmup)
     value = upd * args.steps / (ms / 1e3)
 
     # dominant kernel: spatial overrelaxation phase inside inner slabs
@@ -145,6 +153,19 @@ def main():
                      "bytes_per_launch": b, "updates_per_launch": u, "us_per_launch": us},
         "phases_us": {f"{'OR' if k else 'HB'}_mu{m}": v[0] for (k, m), v in per_phase.items()},
     }
+    if not args.no_fp64 and spec.precision == u1ml.FP32:
+        # the same workload with FP64 link storage and update arithmetic
+        spec64, _ = make()
+        spec64.precision = u1ml.FP64
+        spec64.max_configs = spec.max_configs
+        del ctx
+        ctx64 = u1ml.Context(spec64)
+        ctx64.init_links(sched["start"])
+        ctx64.set_block(tune["chosen_block"])
+        ctx64.sweeps(5)
+        ms64 = time_steps(ctx64, args.steps, args.warmup)
+        line["plain_fp64"] = {"value": upd * args.steps / (ms64 / 1e3), "unit": "link updates/s",
+                              "ms_per_step": ms64 / args.steps, "dtype": "f64"}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -48,6 +48,32 @@ __host__ __device__ inline Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 enum : uint32_t { DOM_HB = 0, DOM_INIT = 1, DOM_METRO = 2, DOM_TEST = 3 };
 
 // ---------------------------------------------------------------------------
+// FP32 atan2 without branches: octant reduction to q = min/max in [0, 1] and
+// atan(q) = q P(q^2), P a degree-7 polynomial in q^2 fitted for this library
+// (iteratively reweighted least squares towards the minimax fit on [0, 1]).
+// Maximum error over the plane 3.2e-7 rad when evaluated in FP32.
+// ---------------------------------------------------------------------------
+__device__ inline float atan2_fast(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float q = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float s = q * q;
+    float p = -0.004054566379636526f;
+    p = fmaf(p, s, 0.021862950176000595f);
+    p = fmaf(p, s, -0.055912312120199203f);
+    p = fmaf(p, s, 0.09642195701599121f);
+    p = fmaf(p, s, -0.1390862911939621f);
+    p = fmaf(p, s, 0.19946564733982086f);
+    p = fmaf(p, s, -0.33329859375953674f);
+    p = fmaf(p, s, 0.9999993443489075f);
+    float r = q * p;
+    r = ay > ax ? 1.57079633f - r : r;
+    r = x < 0.0f ? 3.14159265f - r : r;
+    return copysignf(r, y);
+}
+
+// ---------------------------------------------------------------------------
 // Precision traits.  FP64: library math (ocml), same formulas and order as the
 // definitions; FP32: hardware transcendentals where the error budget allows.
 // ---------------------------------------------------------------------------
@@ -83,11 +109,11 @@ struct M<float> {
         *c = __builtin_amdgcn_cosf(rev);
     }
     __device__ static inline float cos_pi(float u) { return __builtin_amdgcn_cosf(0.5f * u); }
-    __device__ static inline float atan2_(float y, float x) { return atan2f(y, x); }
+    __device__ static inline float atan2_(float y, float x) { return atan2_fast(y, x); }
     __device__ static inline float acos_(float x) { return acosf(x); }
     __device__ static inline float log_(float x) { return __logf(x); }
     __device__ static inline float sqrt_(float x) { return __builtin_sqrtf(x); }
-    __device__ static inline float div_(float a, float b) { return __fdividef(a, b); }
+    __device__ static inline float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     __device__ static inline float floor_(float x) { return floorf(x); }
     // 23-bit uniforms: exact in FP32, never 0 or 1
     __device__ static inline float u1(uint32_t a) { return ((float)(a >> 9) + 0.5f) * (1.0f / 8388608.0f); }
@@ -99,6 +125,12 @@ template <typename real>
 __device__ inline real wrap_angle(real a)
 {
     return a - M<real>::two_pi * M<real>::floor_((a + M<real>::pi) / M<real>::two_pi);
+}
+
+template <>
+__device__ inline float wrap_angle<float>(float a)
+{
+    return a - 6.28318531f * floorf(fmaf(a, 0.159154943f, 0.5f));
 }
 
 // ---------------------------------------------------------------------------
@@ -153,17 +185,20 @@ __device__ inline real vonmises_psi(real kappa, uint32_t k0, uint32_t k1, uint32
 //   r - 1 = (1 - rho)^2 / (2 rho),  1 - z = 2 sin^2(pi U1 / 2),  1 + z = 2 cos^2(pi U1 / 2),
 //   g = 1 - f = (r - 1)(1 - z) / (r + z),   h = 1 + f = (r + 1)(1 + z) / (r + z),
 //   c = kappa (r - f) = kappa ((r - 1) + g),
-//   psi = 2 asin(sqrt(g / 2)) if g <= 1, else pi - 2 asin(sqrt(h / 2)),
 // which are the same quantities as above, free of the cancellation in 1 - f.
-template <>
-__device__ inline float vonmises_psi<float>(float kappa, uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
-                                            uint32_t domain, int* n_att)
+// Returns the accepted deviate as cos(psi) = 1 - g = h - 1 and
+// sin(psi) = sign sqrt(g h), which is all the heatbath needs.
+__device__ inline void vonmises_cs_f32(float kappa, uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t domain,
+                                       float* cpsi, float* spsi, int* n_att)
 {
     using m = M<float>;
     if (kappa == 0.0f) {
         const Block4 b = philox4x32_10(c0, c1, 0u, domain, k0, k1);
+        const float rev = m::u1(b.w[0]) - 0.5f;  // psi = pi (2 U1 - 1) in revolutions
+        *cpsi = __builtin_amdgcn_cosf(rev);
+        *spsi = __builtin_amdgcn_sinf(rev);
         *n_att = 1;
-        return m::pi * (2.0f * m::u1(b.w[0]) - 1.0f);
+        return;
     }
     const float s = m::sqrt_(1.0f + 4.0f * kappa * kappa);
     const float tau = 1.0f + s;
@@ -178,7 +213,7 @@ __device__ inline float vonmises_psi<float>(float kappa, uint32_t k0, uint32_t k
         const float q = 0.25f * m::u1(a);  // pi U1 / 2 in revolutions
         const float sh = __builtin_amdgcn_sinf(q), ch = __builtin_amdgcn_cosf(q);
         const float omz = 2.0f * sh * sh, opz = 2.0f * ch * ch;
-        const float inv = m::div_(1.0f, rm1 + opz);
+        const float inv = __builtin_amdgcn_rcpf(rm1 + opz);
         const float g = rm1 * omz * inv;
         const float c = kappa * (rm1 + g);
         const float u2 = m::u2(bb);
@@ -186,18 +221,25 @@ __device__ inline float vonmises_psi<float>(float kappa, uint32_t k0, uint32_t k
         if (!acc) acc = (m::log_(m::div_(c, u2)) + 1.0f - c >= 0.0f);
         if (acc) {
             *n_att = j + 1;
-            float psi;
-            if (g <= 1.0f) {
-                psi = 2.0f * asinf(m::sqrt_(0.5f * g));
-            } else {
-                const float h = (rm1 + 2.0f) * opz * inv;
-                psi = m::pi - 2.0f * asinf(m::sqrt_(0.5f * h));
-            }
-            return (a & 1u) ? -psi : psi;
+            const float h = (rm1 + 2.0f) * opz * inv;
+            const float sp = m::sqrt_(g * h);
+            *cpsi = g <= 1.0f ? 1.0f - g : h - 1.0f;
+            *spsi = (a & 1u) ? -sp : sp;
+            return;
         }
     }
     *n_att = -1;
-    return 0.0f;
+    *cpsi = 1.0f;
+    *spsi = 0.0f;
+}
+
+template <>
+__device__ inline float vonmises_psi<float>(float kappa, uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
+                                            uint32_t domain, int* n_att)
+{
+    float cp, sp;
+    vonmises_cs_f32(kappa, k0, k1, c0, c1, domain, &cp, &sp, n_att);
+    return atan2_fast(sp, cp);
 }
 
 // ---------------------------------------------------------------------------

@@ -108,11 +108,15 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// Measurement m of the innermost level (one work-item per spatial site):
-//   hist_c[m][s][x]    = exp(i Theta_s(x))
-//   hist_o[m][s][2o+k][x] = sum_{t in s} O_k(P_o(x, t)), k = 0: 2 beta (1 - cos),
-//                            k = 1: sqrt(beta) sin, for the 6 orientations o
-//   vac_part[block][2o+k] = block sum over every plaquette (vacuum <O>)
+// Measurement m of a configuration (one work-item per spatial site x and slab s
+// of the innermost level):
+//   hist_c[m_in][s][x]       = exp(i Theta_s(x)), Theta_s(x) = sum_{t in s} theta_t(x, t)
+//   hist_o[m_in][s][2o+k][x] = sum_{t in s} O_k(P_o(x, t)); k = 0: 2 beta (1 - cos),
+//                              k = 1: sqrt(beta) sin, orientations o = P_xt, P_yt,
+//                              P_zt, P_yz, P_zx, P_xy
+//   vac_part[m][block][2o+k] = block sum of O_k over every plaquette (vacuum <O>)
+// m_in indexes the measurement inside the innermost level, m the measurement
+// inside the configuration.
 // ---------------------------------------------------------------------------
 template <typename real>
 __device__ inline void plaq_O(real th, double beta, double sqrt_beta, double* osq, double* olin);
@@ -137,114 +141,114 @@ __device__ inline void plaq_O<float>(float th, double beta, double sqrt_beta, do
     *olin = sqrt_beta * (double)s;
 }
 
+struct MSite {
+    int x, y, z, t;
+};
+
 template <typename real>
-__global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
-                                                 int n_ens, const real* __restrict__ links, double2* __restrict__ hist_c,
-                                                 double* __restrict__ hist_o, double* __restrict__ vac_part, int m,
-                                                 int tau, int store_o)
+__device__ inline real ld_link(const real* __restrict__ lb, const EnsDesc& E, int dir, const MSite& c)
 {
-    const int bid = blockIdx.x;
-    const int e = find_ens_m(bstart, n_ens, bid);
-    const EnsDesc& E = ens[e];
-    const int blk = bid - bstart[e];
-    const int xs = blk * 256 + (int)threadIdx.x;
-    const int nsig = E.nsig, S = E.nt / tau;
-    const real* base = links + E.link_off;
-    auto ld = [&](int dir, Coord c) -> real {
-        const int par = (c.x + c.y + c.z + c.t) & 1;
-        const int h = (c.x >> 1) + E.nxh * (c.y + E.ny * (c.z + E.nz * c.t));
-        return base[(size_t)(dir * 2 + par) * E.vh + h];
-    };
+    const unsigned par = (unsigned)((c.x + c.y + c.z + c.t) & 1);
+    const unsigned h = (unsigned)((c.x >> 1) + E.nxh * (c.y + E.ny * (c.z + E.nz * c.t)));
+    return lb[((unsigned)dir * 2u + par) * (unsigned)E.vh + h];
+}
+
+// 64-lane wave reduction followed by a fixed-order sum over the waves of the block
+template <int N>
+__device__ inline void block_sum(double* v, double* out)
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    __shared__ double sh[16][N];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) sh[wave][k] = v[k];
+    __syncthreads();
+    if ((int)threadIdx.x < N) {
+        double a = 0.0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) a += sh[w][threadIdx.x];
+        out[threadIdx.x] = a;
+    }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens, const int2* __restrict__ bmap,
+                                                 const real* __restrict__ links, double2* __restrict__ hist_c,
+                                                 double* __restrict__ hist_o, double* __restrict__ vac_part, int m_in,
+                                                 int m, int tau, int store_o)
+{
+    const int2 be = bmap[blockIdx.x];
+    const EnsDesc& E = ens[be.x];
+    const int nsig = E.nsig, S = E.s_in;
+    const int item = be.y * 256 + (int)threadIdx.x;
+    const real* lb = links + E.link_off;
     double vac[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) vac[k] = 0.0;
-    if (xs < nsig) {
+    if (item < nsig * S) {
+        const int s = item / nsig;
+        const int xs = item - s * nsig;
         const int x = xs % E.nx;
         const int y = (xs / E.nx) % E.ny;
         const int z = xs / (E.nx * E.ny);
-        for (int s = 0; s < S; ++s) {
-            double Th = 0.0;
-            double os[12];
+        const int xp = x + 1 == E.nx ? 0 : x + 1, yp = y + 1 == E.ny ? 0 : y + 1, zp = z + 1 == E.nz ? 0 : z + 1;
+        double Th = 0.0;
+        double os[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) os[k] = 0.0;
-            for (int t = s * tau; t < (s + 1) * tau; ++t) {
-                const Coord c = {x, y, z, t};
-                const Coord cx = step(c, 0, +1, E.nx, E.ny, E.nz, E.nt);
-                const Coord cy = step(c, 1, +1, E.nx, E.ny, E.nz, E.nt);
-                const Coord cz = step(c, 2, +1, E.nx, E.ny, E.nz, E.nt);
-                const Coord ct = step(c, 3, +1, E.nx, E.ny, E.nz, E.nt);
-                const real ux = ld(0, c), uy = ld(1, c), uz = ld(2, c), ut = ld(3, c);
-                Th += (double)ut;
-                real th[6];
-                th[0] = ux + ld(3, cx) - ld(0, ct) - ut;  // P_xt
-                th[1] = uy + ld(3, cy) - ld(1, ct) - ut;  // P_yt
-                th[2] = uz + ld(3, cz) - ld(2, ct) - ut;  // P_zt
-                th[3] = uy + ld(2, cy) - ld(1, cz) - uz;  // P_yz
-                th[4] = uz + ld(0, cz) - ld(2, cx) - ux;  // P_zx
-                th[5] = ux + ld(1, cx) - ld(0, cy) - uy;  // P_xy
+        for (int k = 0; k < 12; ++k) os[k] = 0.0;
+        for (int t = s * tau; t < (s + 1) * tau; ++t) {
+            const int tp = t + 1 == E.nt ? 0 : t + 1;
+            const MSite c{x, y, z, t}, cx{xp, y, z, t}, cy{x, yp, z, t}, cz{x, y, zp, t}, ct{x, y, z, tp};
+            const real ux = ld_link(lb, E, 0, c), uy = ld_link(lb, E, 1, c), uz = ld_link(lb, E, 2, c),
+                       ut = ld_link(lb, E, 3, c);
+            const real tx_x = ld_link(lb, E, 3, cx), tx_y = ld_link(lb, E, 3, cy), tx_z = ld_link(lb, E, 3, cz);
+            const real xt = ld_link(lb, E, 0, ct), yt = ld_link(lb, E, 1, ct), zt = ld_link(lb, E, 2, ct);
+            const real zy = ld_link(lb, E, 2, cy), yz = ld_link(lb, E, 1, cz);
+            const real xz = ld_link(lb, E, 0, cz), zx = ld_link(lb, E, 2, cx);
+            const real yx = ld_link(lb, E, 1, cx), xy = ld_link(lb, E, 0, cy);
+            Th += (double)ut;
+            real th[6];
+            th[0] = ux + tx_x - xt - ut;  // P_xt
+            th[1] = uy + tx_y - yt - ut;  // P_yt
+            th[2] = uz + tx_z - zt - ut;  // P_zt
+            th[3] = uy + zy - yz - uz;    // P_yz
+            th[4] = uz + xz - zx - ux;    // P_zx
+            th[5] = ux + yx - xy - uy;    // P_xy
 #pragma unroll
-                for (int o = 0; o < 6; ++o) {
-                    double a, b;
-                    plaq_O<real>(th[o], E.beta, E.sqrt_beta, &a, &b);
-                    os[2 * o] += a;
-                    os[2 * o + 1] += b;
-                }
+            for (int o = 0; o < 6; ++o) {
+                double a, b;
+                plaq_O<real>(th[o], E.beta, E.sqrt_beta, &a, &b);
+                os[2 * o] += a;
+                os[2 * o + 1] += b;
             }
-            double sn, cs;
-            sincos(Th, &sn, &cs);
-            hist_c[E.hc_off + ((size_t)m * S + s) * nsig + xs] = make_double2(cs, sn);
-            if (store_o) {
-                double* ho = hist_o + E.ho_off + ((size_t)m * S + s) * 12 * nsig + xs;
-#pragma unroll
-                for (int k = 0; k < 12; ++k) ho[(size_t)k * nsig] = os[k];
-            }
-#pragma unroll
-            for (int k = 0; k < 12; ++k) vac[k] += os[k];
         }
-    }
-    __shared__ double sh[256];
-    for (int k = 0; k < 12; ++k) {
-        sh[threadIdx.x] = vac[k];
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
+        double sn, cs;
+        sincos(Th, &sn, &cs);
+        hist_c[E.hc_off + ((size_t)m_in * S + s) * nsig + xs] = make_double2(cs, sn);
+        if (store_o) {
+            double* ho = hist_o + E.ho_off + ((size_t)m_in * S + s) * 12 * nsig + xs;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) ho[(size_t)k * nsig] = os[k];
         }
-        if (threadIdx.x == 0) vac_part[E.vac_part_off + (size_t)blk * 12 + k] = sh[0];
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 12; ++k) vac[k] = os[k];
     }
+    block_sum<12>(vac, vac_part + E.vac_part_off + ((size_t)m * E.n_vac_blocks + be.y) * 12);
 }
 
-hipError_t launch_measure(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int precision,
-                          const void* links, double2* hist_c, double* hist_o, double* vac_part, int m, int tau,
-                          int store_o, hipStream_t st)
+hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int precision, const void* links,
+                          double2* hist_c, double* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
+                          hipStream_t st)
 {
     if (precision == 0)
-        hipLaunchKernelGGL(k_measure<double>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens,
-                           (const double*)links, hist_c, hist_o, vac_part, m, tau, store_o);
+        hipLaunchKernelGGL(k_measure<double>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bmap,
+                           (const double*)links, hist_c, hist_o, vac_part, m_in, m, tau, store_o);
     else
-        hipLaunchKernelGGL(k_measure<float>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens,
-                           (const float*)links, hist_c, hist_o, vac_part, m, tau, store_o);
-    return hipGetLastError();
-}
-
-// vac_acc[e][k] (double-double) += sum over the measurement's block partials
-__global__ void k_vac_accum(const EnsDesc* __restrict__ ens, const double* __restrict__ vac_part,
-                            double* __restrict__ vac_acc)
-{
-    const int e = blockIdx.x;
-    const int k = threadIdx.x;
-    if (k >= 12) return;
-    const EnsDesc& E = ens[e];
-    dd a{vac_acc[(e * 12 + k) * 2], vac_acc[(e * 12 + k) * 2 + 1]};
-    for (int b = 0; b < E.n_vac_blocks; ++b) a = dd_add(a, vac_part[E.vac_part_off + (size_t)b * 12 + k]);
-    vac_acc[(e * 12 + k) * 2] = a.hi;
-    vac_acc[(e * 12 + k) * 2 + 1] = a.lo;
-}
-
-hipError_t launch_vac_accum(const EnsDesc* d_ens, int n_ens, const double* vac_part, double* vac_acc, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_vac_accum, dim3(n_ens), dim3(64), 0, st, d_ens, vac_part, vac_acc);
+        hipLaunchKernelGGL(k_measure<float>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bmap,
+                           (const float*)links, hist_c, hist_o, vac_part, m_in, m, tau, store_o);
     return hipGetLastError();
 }
 
@@ -286,14 +290,22 @@ __global__ void __launch_bounds__(256) k_contract(const EnsDesc* __restrict__ en
     const EnsDesc& E = ens[e];
     const ObsDesc& O = *obs;
     const int nsig = E.nsig, S = E.s_in;
+    // item order: 64 consecutive sites, then r, then the 64-site chunk, slab,
+    // axis -- a block covers several r for the same sites, so the shifted
+    // reads of the history overlap inside the block and hit in L1
+    const int nchunk = (nsig + 63) / 64;
     const long long item = (long long)(bid - bstart[e]) * blockDim.x + threadIdx.x;
-    if (item >= (long long)O.n_dirs * O.n_r * S * nsig) return;
-    const int xs = (int)(item % nsig);
-    long long rest = item / nsig;
-    const int s = (int)(rest % S);
-    rest /= S;
+    if (item >= (long long)O.n_dirs * S * nchunk * O.n_r * 64) return;
+    const int lane = (int)(item & 63);
+    long long rest = item >> 6;
     const int ir = (int)(rest % O.n_r);
-    const int id = (int)(rest / O.n_r);
+    rest /= O.n_r;
+    const int chunk = (int)(rest % nchunk);
+    rest /= nchunk;
+    const int s = (int)(rest % S);
+    const int id = (int)(rest / S);
+    const int xs = chunk * 64 + lane;
+    if (xs >= nsig) return;
     const int dir = O.dirs[id];
     const int r = rlist[ir];
     const int x = xs % E.nx, y = (xs / E.nx) % E.ny, z = xs / (E.nx * E.ny);
@@ -552,29 +564,45 @@ hipError_t launch_product(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs,
     return hipGetLastError();
 }
 
-// vacuum <O_sq>, <O_lin> per orientation: sums / (measurements * V)
-__global__ void k_vac_final(const EnsDesc* __restrict__ ens, int n_ens, const ObsDesc* __restrict__ obs,
-                            const double* __restrict__ vac_acc, int n_meas, double* __restrict__ results,
-                            const int* __restrict__ ring)
+// vacuum <O_sq>, <O_lin> per orientation: the sum of every block partial of
+// every measurement of the configuration (double-double, fixed order), divided
+// by (measurements * V).  Block (e, k) reduces quantity k of ensemble e.
+__global__ void __launch_bounds__(256) k_vac_final(const EnsDesc* __restrict__ ens, int n_ens,
+                                                   const ObsDesc* __restrict__ obs, const double* __restrict__ vac_part,
+                                                   int n_meas, double* __restrict__ results,
+                                                   const int* __restrict__ ring)
 {
-    const int e = blockIdx.x;
-    const int k = threadIdx.x;
-    if (k >= 12) return;
-    const ObsDesc& O = *obs;
-    const int slot = *ring;
-    const long long base_v = 2ll * O.n_r + 4ll * O.n_r * O.n_probe * O.n_comp;
-    double* out = results + ((size_t)slot * n_ens + e) * O.n_doubles_per_config;
-    const double v = (vac_acc[(e * 12 + k) * 2] + vac_acc[(e * 12 + k) * 2 + 1]) /
-                     ((double)n_meas * 2.0 * (double)ens[e].vh);
-    // accumulator order is (o, kind); output order is sq[6] then lin[6]
-    const int o = k >> 1, kind = k & 1;
-    out[base_v + kind * 6 + o] = v;
+    const int e = blockIdx.x / 12, k = blockIdx.x % 12;
+    const EnsDesc& E = ens[e];
+    const long long n = (long long)n_meas * E.n_vac_blocks;
+    dd a{0.0, 0.0};
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) a = dd_add(a, vac_part[E.vac_part_off + i * 12 + k]);
+    __shared__ double shh[256], shl[256];
+    shh[threadIdx.x] = a.hi;
+    shl[threadIdx.x] = a.lo;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const dd b = dd_add(dd{shh[threadIdx.x], shl[threadIdx.x]}, dd{shh[threadIdx.x + w], shl[threadIdx.x + w]});
+            shh[threadIdx.x] = b.hi;
+            shl[threadIdx.x] = b.lo;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const ObsDesc& O = *obs;
+        const long long base_v = 2ll * O.n_r + 4ll * O.n_r * O.n_probe * O.n_comp;
+        double* out = results + ((size_t)(*ring) * n_ens + e) * O.n_doubles_per_config;
+        // accumulator order is (o, kind); output order is sq[6] then lin[6]
+        const int o = k >> 1, kind = k & 1;
+        out[base_v + kind * 6 + o] = (shh[0] + shl[0]) / ((double)n_meas * 2.0 * (double)E.vh);
+    }
 }
 
-hipError_t launch_vac_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, const double* vac_acc, int n_meas,
+hipError_t launch_vac_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, const double* vac_part, int n_meas,
                             double* results, const int* d_ring, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_vac_final, dim3(n_ens), dim3(64), 0, st, d_ens, n_ens, d_obs, vac_acc, n_meas, results,
+    hipLaunchKernelGGL(k_vac_final, dim3(n_ens * 12), dim3(256), 0, st, d_ens, n_ens, d_obs, vac_part, n_meas, results,
                        d_ring);
     return hipGetLastError();
 }

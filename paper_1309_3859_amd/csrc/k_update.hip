@@ -34,104 +34,210 @@ struct LinkView {
 };
 
 // ---------------------------------------------------------------------------
-// Staple sum A = sum_{nu != mu} exp(i phi_f) + exp(i phi_b), nu ascending,
-// forward before backward:
-//   phi_f = th_nu(x+mu) - th_mu(x+nu) - th_nu(x)
-//   phi_b = th_nu(x-nu) - th_nu(x+mu-nu) - th_mu(x-nu)
+// Division-free index decode: q = a / b for 0 <= a, b > 0, a / b < 2^22,
+// from the FP32 reciprocal and one exact correction step.
 // ---------------------------------------------------------------------------
-template <typename real>
-__device__ inline void staple(const LinkView<real>& L, Coord c, int mu, int p, int nx, int nt, real* ar, real* ai)
+__device__ inline int fdiv(int a, int b, float inv_b)
 {
-    const int q = p ^ 1;
-    const Coord cpm = step(c, mu, +1, nx, L.ny, L.nz, nt);
-    real sr = real(0), si = real(0);
-#pragma unroll
-    for (int nu = 0; nu < 4; ++nu) {
-        if (nu == mu) continue;
-        const Coord cpn = step(c, nu, +1, nx, L.ny, L.nz, nt);
-        const Coord cmn = step(c, nu, -1, nx, L.ny, L.nz, nt);
-        const Coord cpmmn = step(cpm, nu, -1, nx, L.ny, L.nz, nt);
-        const real phf = L.ld(nu, q, cpm) - L.ld(mu, q, cpn) - L.ld(nu, p, c);
-        const real phb = L.ld(nu, q, cmn) - L.ld(nu, p, cpmmn) - L.ld(mu, q, cmn);
-        real s, co;
-        M<real>::sincos_(phf, &s, &co);
-        sr += co;
-        si += s;
-        M<real>::sincos_(phb, &s, &co);
-        sr += co;
-        si += s;
-    }
-    *ar = sr;
-    *ai = si;
+    int q = (int)((float)a * inv_b);
+    const int r = a - (int)__umul24(q, b);
+    q += (r >= b) - (r < 0);
+    return q;
 }
+
+// Site in even/odd storage: coordinates and hrow = (Nx/2) (y + Ny (z + Nz t)),
+// so the half index of a site is (x >> 1) + hrow.
+struct Site {
+    int x, y, z, t, hrow;
+};
+
+struct Geo {
+    int nx, ny, nz, nt, sy, sz, st;  // sy = Nx/2, sz = sy Ny, st = sz Nz (strides in half indices)
+};
+
+// one periodic step along compile-time direction D, sign S
+template <int D, int S>
+__device__ inline Site mv(Site c, const Geo& g)
+{
+    if (D == 0) {
+        c.x = S > 0 ? (c.x == g.nx - 1 ? 0 : c.x + 1) : (c.x == 0 ? g.nx - 1 : c.x - 1);
+    } else if (D == 1) {
+        if (S > 0) {
+            c.hrow += c.y == g.ny - 1 ? -(g.ny - 1) * g.sy : g.sy;
+            c.y = c.y == g.ny - 1 ? 0 : c.y + 1;
+        } else {
+            c.hrow += c.y == 0 ? (g.ny - 1) * g.sy : -g.sy;
+            c.y = c.y == 0 ? g.ny - 1 : c.y - 1;
+        }
+    } else if (D == 2) {
+        if (S > 0) {
+            c.hrow += c.z == g.nz - 1 ? -(g.nz - 1) * g.sz : g.sz;
+            c.z = c.z == g.nz - 1 ? 0 : c.z + 1;
+        } else {
+            c.hrow += c.z == 0 ? (g.nz - 1) * g.sz : -g.sz;
+            c.z = c.z == 0 ? g.nz - 1 : c.z - 1;
+        }
+    } else {
+        if (S > 0) {
+            c.hrow += c.t == g.nt - 1 ? -(g.nt - 1) * g.st : g.st;
+            c.t = c.t == g.nt - 1 ? 0 : c.t + 1;
+        } else {
+            c.hrow += c.t == 0 ? (g.nt - 1) * g.st : -g.st;
+            c.t = c.t == 0 ? g.nt - 1 : c.t - 1;
+        }
+    }
+    return c;
+}
+
+__device__ inline unsigned hidx(const Site& c) { return (unsigned)((c.x >> 1) + c.hrow); }
+
+// Load from a uniform base with a 32-bit byte offset (one ensemble's links
+// span less than 4 GiB), which maps to global_load with a scalar base.
+template <typename real>
+__device__ inline real ldo(const real* __restrict__ base, unsigned byte_off)
+{
+    return *reinterpret_cast<const real*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// The six angles of the two staples of link (x, MU) in the plane (MU, NU):
+//   v[0..2] = th_nu(x+mu), th_mu(x+nu), th_nu(x)          (forward)
+//   v[3..5] = th_nu(x-nu), th_nu(x+mu-nu), th_mu(x-nu)    (backward)
+// The angles of direction d and parity par start at element (2 d + par) vh.
+template <typename real, int MU, int NU>
+__device__ inline void gather_plane(const real* __restrict__ lb, unsigned vh, const Geo& g, const Site& c,
+                                    const Site& cpm, int p, real* v)
+{
+    const unsigned q = p ^ 1;
+    const Site cpn = mv<NU, +1>(c, g);
+    const Site cmn = mv<NU, -1>(c, g);
+    const Site cpmmn = mv<NU, -1>(cpm, g);
+    constexpr unsigned w = sizeof(real);
+    v[0] = ldo(lb, ((NU * 2 + q) * vh + hidx(cpm)) * w);
+    v[1] = ldo(lb, ((MU * 2 + q) * vh + hidx(cpn)) * w);
+    v[2] = ldo(lb, ((NU * 2 + p) * vh + hidx(c)) * w);
+    v[3] = ldo(lb, ((NU * 2 + q) * vh + hidx(cmn)) * w);
+    v[4] = ldo(lb, ((NU * 2 + p) * vh + hidx(cpmmn)) * w);
+    v[5] = ldo(lb, ((MU * 2 + q) * vh + hidx(cmn)) * w);
+}
+
+template <int MU, int K>
+struct Nu {  // K-th direction other than MU, ascending
+    static constexpr int v = K < MU ? K : K + 1;
+};
 
 // kind 0: heatbath theta = wrap(psi - arg A), psi ~ vonMises(0, beta |A|);
 // kind 1: overrelaxation theta = wrap(-theta - 2 arg A) (unchanged if A = 0).
-template <typename real, int KIND>
-__global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
-                                                 int n_ens, real* __restrict__ links, const uint32_t* __restrict__ upd,
-                                                 int pass_offset, int mu, int parity, int tau)
+// Staple sum A = sum_{nu != mu} exp(i phi_f) + exp(i phi_b), nu ascending,
+// forward before backward, phi_f = v0 - v1 - v2, phi_b = v3 - v4 - v5.
+template <typename real, int KIND, int MU>
+__global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens, const int2* __restrict__ bmap,
+                                                 real* __restrict__ links, const uint32_t* __restrict__ upd,
+                                                 int pass_offset, int parity, int tau, float inv_tm1)
 {
-    const int bid = blockIdx.x;
-    const int e = find_ens(bstart, n_ens, bid);
+    const int2 be = bmap[blockIdx.x];
+    const int e = be.x;
     const EnsDesc& E = ens[e];
-    const int nxh = E.nxh, nx = E.nx, ny = E.ny, nz = E.nz, nt = E.nt;
-    const bool masked = (mu < 3) && (tau > 1);
-    const int slice = nxh * ny * nz;
-    const int active_t = masked ? nt - nt / tau : nt;
-    const int item = (bid - bstart[e]) * (int)blockDim.x + (int)threadIdx.x;
+    const Geo g{E.nx, E.ny, E.nz, E.nt, E.nxh, E.nxh * E.ny, E.nxh * E.ny * E.nz};
+    const bool masked = (MU < 3) && (tau > 1);
+    const int slice = g.st;
+    const int active_t = masked ? g.nt - g.nt / tau : g.nt;
+    const int item = be.y * (int)blockDim.x + (int)threadIdx.x;
     if (item >= slice * active_t) return;
-    const int j = item / slice;
-    const int rem = item - j * slice;
-    const int t = masked ? (j / (tau - 1)) * tau + 1 + (j % (tau - 1)) : j;
-    const int yz = rem / nxh;
-    const int xh = rem - yz * nxh;
-    const int z = yz / ny;
-    const int y = yz - z * ny;
+    const int j = fdiv(item, slice, E.inv_slice);
+    const int rem = item - (int)__umul24(j, slice);
+    int t = j;
+    if (masked) {
+        const int jt = fdiv(j, tau - 1, inv_tm1);
+        t = jt * tau + 1 + (j - jt * (tau - 1));
+    }
+    const int yz = fdiv(rem, g.sy, E.inv_nxh);
+    const int xh = rem - (int)__umul24(yz, g.sy);
+    const int z = fdiv(yz, g.ny, E.inv_ny);
+    const int y = yz - (int)__umul24(z, g.ny);
     const int x = 2 * xh + ((y + z + t + parity) & 1);
-    const Coord c = {x, y, z, t};
+    const Site c{x, y, z, t, (int)(__umul24(g.sy, yz) + __umul24(g.st, t))};
 
-    real* base = links + E.link_off;
-    LinkView<real> L{base, E.vh, nxh, ny, nz};
-    real ar, ai;
-    staple(L, c, mu, parity, nx, nt, &ar, &ai);
-    real* dst = base + (size_t)(mu * 2 + parity) * E.vh + (xh + nxh * (y + ny * (z + nz * t)));
+    real* lb = links + E.link_off;
+    const unsigned vh = (unsigned)E.vh;
+
+    // every load of the update is issued before any arithmetic
+    const Site cpm = mv<MU, +1>(c, g);
+    real v[3][6];
+    gather_plane<real, MU, Nu<MU, 0>::v>(lb, vh, g, c, cpm, parity, v[0]);
+    gather_plane<real, MU, Nu<MU, 1>::v>(lb, vh, g, c, cpm, parity, v[1]);
+    gather_plane<real, MU, Nu<MU, 2>::v>(lb, vh, g, c, cpm, parity, v[2]);
+    const unsigned self = ((MU * 2 + parity) * vh + (unsigned)(xh + c.hrow)) * (unsigned)sizeof(real);
+    real old = real(0);
+    if (KIND == 1) old = ldo(lb, self);
+    real* dst = reinterpret_cast<real*>(reinterpret_cast<char*>(lb) + self);
+
+    real ar = real(0), ai = real(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        real s, co;
+        M<real>::sincos_(v[k][0] - v[k][1] - v[k][2], &s, &co);
+        ar += co;
+        ai += s;
+        M<real>::sincos_(v[k][3] - v[k][4] - v[k][5], &s, &co);
+        ar += co;
+        ai += s;
+    }
     if (KIND == 0) {
         const real R = M<real>::sqrt_(ar * ar + ai * ai);
-        const real phiA = M<real>::atan2_(ai, ar);
         const real kappa = (real)E.beta * R;
-        const uint32_t lid = (uint32_t)(mu + 4 * (x + nx * (y + ny * (z + nz * t))));
+        const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
+        const uint32_t ctr = upd[e] + (uint32_t)pass_offset;
         int na;
-        const real psi = vonmises_psi<real>(kappa, E.seed, E.key_id, lid, upd[e] + (uint32_t)pass_offset, DOM_HB, &na);
-        if (na < 0) return;
-        *dst = wrap_angle<real>(psi - phiA);
+        if constexpr (sizeof(real) == 4) {
+            // theta = psi - arg A as one angle: exp(i theta) is proportional to
+            // exp(i psi) conj(A), so a single atan2 replaces arccos, atan2 and wrap
+            float cp, sp;
+            vonmises_cs_f32(kappa, E.seed, E.key_id, lid, ctr, DOM_HB, &cp, &sp, &na);
+            if (na < 0) return;
+            const float th = atan2_fast(sp * ar - cp * ai, cp * ar + sp * ai);
+            *dst = th >= 3.14159265f ? -3.14159265f : th;
+        } else {
+            const real phiA = M<real>::atan2_(ai, ar);
+            const real psi = vonmises_psi<real>(kappa, E.seed, E.key_id, lid, ctr, DOM_HB, &na);
+            if (na < 0) return;
+            *dst = wrap_angle<real>(psi - phiA);
+        }
     } else {
         if (ar == real(0) && ai == real(0)) return;
         const real phiA = M<real>::atan2_(ai, ar);
-        *dst = wrap_angle<real>(-(*dst) - real(2) * phiA);
+        *dst = wrap_angle<real>(-old - real(2) * phiA);
     }
 }
 
-hipError_t launch_update(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
-                         int precision, void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu,
-                         int parity, int tau, hipStream_t st)
+template <typename real, int KIND>
+static void launch_update_t(dim3 g, dim3 b, hipStream_t st, const EnsDesc* d_ens, const int2* d_bmap, real* links,
+                            const uint32_t* d_upd, int pass_offset, int mu, int parity, int tau, float inv_tm1)
+{
+    switch (mu) {
+    case 0: hipLaunchKernelGGL((k_update<real, KIND, 0>), g, b, 0, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 1: hipLaunchKernelGGL((k_update<real, KIND, 1>), g, b, 0, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 2: hipLaunchKernelGGL((k_update<real, KIND, 2>), g, b, 0, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    default: hipLaunchKernelGGL((k_update<real, KIND, 3>), g, b, 0, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    }
+}
+
+hipError_t launch_update(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int block, int precision,
+                         void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu, int parity, int tau,
+                         hipStream_t st)
 {
     if (total_blocks <= 0) return hipSuccess;
-    dim3 g(total_blocks), b(block);
+    const dim3 g(total_blocks), b(block);
+    const float inv_tm1 = tau > 1 ? 1.0f / (float)(tau - 1) : 1.0f;
     if (precision == 0) {
         if (kind == 0)
-            hipLaunchKernelGGL((k_update<double, 0>), g, b, 0, st, d_ens, d_bstart, n_ens, (double*)links, d_upd,
-                               pass_offset, mu, parity, tau);
+            launch_update_t<double, 0>(g, b, st, d_ens, d_bmap, (double*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else
-            hipLaunchKernelGGL((k_update<double, 1>), g, b, 0, st, d_ens, d_bstart, n_ens, (double*)links, d_upd,
-                               pass_offset, mu, parity, tau);
+            launch_update_t<double, 1>(g, b, st, d_ens, d_bmap, (double*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
     } else {
         if (kind == 0)
-            hipLaunchKernelGGL((k_update<float, 0>), g, b, 0, st, d_ens, d_bstart, n_ens, (float*)links, d_upd,
-                               pass_offset, mu, parity, tau);
+            launch_update_t<float, 0>(g, b, st, d_ens, d_bmap, (float*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else
-            hipLaunchKernelGGL((k_update<float, 1>), g, b, 0, st, d_ens, d_bstart, n_ens, (float*)links, d_upd,
-                               pass_offset, mu, parity, tau);
+            launch_update_t<float, 1>(g, b, st, d_ens, d_bmap, (float*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
     }
     return hipGetLastError();
 }

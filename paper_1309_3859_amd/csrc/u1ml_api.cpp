@@ -35,8 +35,9 @@ struct Layout {
     size_t off_links, off_hc, off_ho, off_at, off_ato, off_ot, off_oto, off_res, off_scr;
     size_t sz_links, sz_hc, sz_ho, sz_at, sz_ato, sz_ot, sz_oto, sz_res, sz_scr;
     // scratch sub-offsets (bytes from off_scr)
-    size_t s_ens, s_obs, s_r, s_probe, s_comp, s_bstart, s_upd, s_ring, s_vpart, s_vacc, s_ppart, s_pout, s_count,
-        s_stage;
+    size_t s_ens, s_obs, s_r, s_probe, s_comp, s_bstart, s_upd, s_ring, s_vpart, s_ppart, s_pout, s_count,
+        s_stage, s_bmap, s_mmap;
+    size_t bmap_stride;  // entries per update class (blocks of 64 threads)
     int n_bstart_tables;
 };
 
@@ -136,6 +137,8 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
         if (E.nt % P->tau_i != 0) return fail(err, "Nt must be a multiple of the inner tau");
         const double V = (double)E.ns[0] * E.ns[1] * E.ns[2] * E.nt;
         if (4.0 * V >= 4294967296.0) return fail(err, "4 V must fit in 32 bits (link ids)");
+        if ((double)E.ns[1] * E.ns[2] >= 4194304.0) return fail(err, "Ny * Nz must be below 2^22");
+        if ((double)E.ns[0] / 2 * E.ns[1] * E.ns[2] >= 16777216.0) return fail(err, "Ns^3 / 2 must be below 2^24");
         for (int i = 0; i < P->n_dirs; ++i) {
             const int d = P->dirs[i];
             for (int rv : P->r)
@@ -159,7 +162,7 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
     const bool store_o = !P.probes.empty();
     const size_t R = P.r.size(), Np = P.probes.size(), Nc = P.comps.size(), nd = (size_t)P.n_dirs;
     size_t L = 0, HC = 0, HO = 0, AT = 0, ATO = 0, OT = 0, OTO = 0, VAC = 0;
-    size_t maxV = 0, paper = 0, upd_cfg = 0, upd_sweep = 0;
+    size_t maxV = 0, paper = 0, upd_cfg = 0, upd_sweep = 0, blocks64 = 0, mblocks = 0;
     S->links.clear();
     S->hc.clear();
     S->ho.clear();
@@ -172,6 +175,7 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
         const size_t nsig = (size_t)E.ns[0] * E.ns[1] * E.ns[2];
         const size_t V = nsig * E.nt;
         maxV = std::max(maxV, V);
+        blocks64 += (V / 2 + 63) / 64;
         const size_t si = E.nt / P.tau_i, so = E.nt / P.tau_o;
         size_t v, t;
         // links: 4 V words, padded to 256 bytes
@@ -203,7 +207,9 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
             }
         }
         S->vac.push_back(VAC);
-        VAC += ((nsig + 255) / 256) * 12;
+        // vacuum partials of every measurement of a configuration
+        VAC += (size_t)P.n_o * P.n_i * ((nsig * si + 255) / 256) * 12;
+        mblocks += (nsig * si + 255) / 256;
         // the paper's running accumulators: 2 doubles per site and per point of
         // the transverse plane, per slab of the inner level (Sec. II.D)
         const size_t area = (size_t)E.ns[(P.dirs[0] + 1) % 3] * E.ns[(P.dirs[0] + 2) % 3];
@@ -245,11 +251,13 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
     Lo->s_upd = take(sizeof(uint32_t) * n);
     Lo->s_ring = take(sizeof(int) * 4);
     Lo->s_vpart = take(sizeof(double) * VAC);
-    Lo->s_vacc = take(sizeof(double) * 24 * n);
     Lo->s_ppart = take(sizeof(double) * 6 * 64 * n);
     Lo->s_pout = take(sizeof(double) * 6 * n);
     Lo->s_count = take(sizeof(unsigned long long) * 2);
     Lo->s_stage = take(sizeof(double) * 4 * maxV);
+    Lo->bmap_stride = blocks64;
+    Lo->s_bmap = take(sizeof(int2) * kUpdateClasses * blocks64);
+    Lo->s_mmap = take(sizeof(int2) * mblocks);
     Lo->sz_scr = s;
     size_t off = 0;
     Lo->off_links = off;
@@ -301,16 +309,19 @@ struct u1ml_ctx {
     // device pointers
     void* links = nullptr;
     double2 *hc = nullptr, *at = nullptr, *ato = nullptr, *ot = nullptr, *oto = nullptr;
-    double *ho = nullptr, *res = nullptr, *vpart = nullptr, *vacc = nullptr, *ppart = nullptr, *pout = nullptr,
+    double *ho = nullptr, *res = nullptr, *vpart = nullptr, *ppart = nullptr, *pout = nullptr,
            *stage = nullptr;
     EnsDesc* d_ens = nullptr;
     ObsDesc* d_obs = nullptr;
     int *d_r = nullptr, *d_probe = nullptr, *d_comp = nullptr, *d_bstart = nullptr, *d_ring = nullptr;
+    int2* d_bmap = nullptr;
+    int2* d_mmap = nullptr;  // measurement launch: block -> (ensemble, local block)
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
     // host mirrors
     std::vector<EnsDesc> h_ens;
     std::vector<int> h_bstart;  // kNumTabs x (n_ens + 1)
+    std::vector<int2> h_bmap;   // kUpdateClasses x bmap_stride: block -> (ensemble, local block)
     int block = 256;
     bool initialised = false;
     int ring_count = 0;
@@ -320,6 +331,7 @@ struct u1ml_ctx {
 
     int tab_total(int tab) const { return h_bstart[(size_t)tab * (P.n_ens + 1) + P.n_ens]; }
     const int* tab_dev(int tab) const { return d_bstart + (size_t)tab * (P.n_ens + 1); }
+    const int2* bmap_dev(int cls) const { return d_bmap + (size_t)cls * Lo.bmap_stride; }
 };
 
 namespace {
@@ -365,6 +377,12 @@ void build_update_tabs(u1ml_ctx* c)
     build_tab(c, kTabUpd + 1, it1, c->block);
     build_tab(c, kTabUpd + 2, it2, c->block);
     build_tab(c, kTabUpd + 3, it3, c->block);
+    c->h_bmap.assign((size_t)kUpdateClasses * c->Lo.bmap_stride, make_int2(0, 0));
+    for (int cls = 0; cls < kUpdateClasses; ++cls) {
+        const int* b = &c->h_bstart[(size_t)(kTabUpd + cls) * (n + 1)];
+        for (int e = 0; e < n; ++e)
+            for (int k = b[e]; k < b[e + 1]; ++k) c->h_bmap[(size_t)cls * c->Lo.bmap_stride + k] = make_int2(e, k - b[e]);
+    }
 }
 
 int update_class(const u1ml_ctx* c, int mu, int tau, bool* ok)
@@ -384,8 +402,8 @@ hipError_t enq_phase(u1ml_ctx* c, hipStream_t st, int kind, int mu, int parity, 
     const int cls = update_class(c, mu, tau, &ok);
     if (!ok) return hipErrorInvalidValue;
     const int tab = kTabUpd + cls;
-    return launch_update(c->d_ens, c->tab_dev(tab), c->P.n_ens, c->tab_total(tab), c->block, c->P.precision, c->links,
-                         c->d_upd, pass_offset, kind, mu, parity, (mu < 3 && tau > 1) ? tau : 0, st);
+    return launch_update(c->d_ens, c->bmap_dev(cls), c->tab_total(tab), c->block, c->P.precision, c->links, c->d_upd,
+                         pass_offset, kind, mu, parity, (mu < 3 && tau > 1) ? tau : 0, st);
 }
 
 hipError_t enq_pass(u1ml_ctx* c, hipStream_t st, int kind, int tau, int pass_offset)
@@ -412,8 +430,8 @@ hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
     const Problem& P = c->P;
     const int n = P.n_ens;
     const int store_o = P.probes.empty() ? 0 : 1;
-    hipError_t e = launch_fill_zero(c->vacc, sizeof(double) * 24 * n, st);
-    if (e == hipSuccess && P.two) {
+    hipError_t e = hipSuccess;
+    if (P.two) {
         e = launch_fill_zero(c->ot, c->Lo.sz_ot, st);
         if (e == hipSuccess && c->Lo.sz_oto) e = launch_fill_zero(c->oto, c->Lo.sz_oto, st);
     }
@@ -424,9 +442,8 @@ hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
         for (int m = 0; e == hipSuccess && m < P.n_i; ++m) {
             for (int k = 0; e == hipSuccess && k < P.k_i; ++k) e = enq_sweep(c, st, P.tau_i, hb++);
             if (e == hipSuccess)
-                e = launch_measure(c->d_ens, c->tab_dev(kTabMeas), n, c->tab_total(kTabMeas), P.precision, c->links,
-                                   c->hc, c->ho, c->vpart, m, P.tau_i, store_o, st);
-            if (e == hipSuccess) e = launch_vac_accum(c->d_ens, n, c->vpart, c->vacc, st);
+                e = launch_measure(c->d_ens, c->d_mmap, c->tab_total(kTabMeas), P.precision, c->links, c->hc, c->ho,
+                                   c->vpart, m, ko * P.n_i + m, P.tau_i, store_o, st);
         }
         if (e == hipSuccess)
             e = launch_contract(c->d_ens, c->tab_dev(kTabCon), n, c->tab_total(kTabCon), c->d_obs, c->d_r, c->d_probe,
@@ -444,7 +461,7 @@ hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
             e = launch_product(c->d_ens, n, c->d_obs, (int)P.r.size(), npg, c->at, c->ato, 0, 1.0, c->res, c->d_ring,
                                st);
     }
-    if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vacc, P.n_o * P.n_i, c->res, c->d_ring, st);
+    if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, c->d_ring, st);
     if (e == hipSuccess) e = launch_ring_advance(c->d_ring, st);
     if (e == hipSuccess && hb > 0) e = launch_advance_counters(c->d_upd, n, hb, st);
     return e;
@@ -610,11 +627,12 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     c->d_upd = (uint32_t*)(s + Lo.s_upd);
     c->d_ring = (int*)(s + Lo.s_ring);
     c->vpart = (double*)(s + Lo.s_vpart);
-    c->vacc = (double*)(s + Lo.s_vacc);
     c->ppart = (double*)(s + Lo.s_ppart);
     c->pout = (double*)(s + Lo.s_pout);
     c->d_count = (unsigned long long*)(s + Lo.s_count);
     c->stage = (double*)(s + Lo.s_stage);
+    c->d_bmap = (int2*)(s + Lo.s_bmap);
+    c->d_mmap = (int2*)(s + Lo.s_mmap);
 
     const Problem& P = c->P;
     const int n = P.n_ens;
@@ -632,7 +650,10 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         E.vh = E.nsig * E.nt / 2;
         E.s_in = E.nt / P.tau_i;
         E.s_out = P.two ? E.nt / P.tau_o : E.s_in;
-        E.n_vac_blocks = (E.nsig + 255) / 256;
+        E.n_vac_blocks = (E.nsig * E.s_in + 255) / 256;
+        E.inv_nxh = 1.0f / (float)E.nxh;
+        E.inv_ny = 1.0f / (float)E.ny;
+        E.inv_slice = 1.0f / (float)(E.nxh * E.ny * E.nz);
         E.beta = U.beta;
         E.sqrt_beta = std::sqrt(U.beta);
         E.seed = U.seed;
@@ -669,8 +690,8 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     for (int e = 0; e < n; ++e) {
         const EnsDesc& E = c->h_ens[e];
         all[e] = 8ll * E.vh;
-        meas[e] = E.nsig;
-        con[e] = (long long)P.n_dirs * P.r.size() * E.s_in * E.nsig;
+        meas[e] = (long long)E.nsig * E.s_in;
+        con[e] = (long long)P.n_dirs * P.r.size() * E.s_in * ((E.nsig + 63) / 64) * 64;
         comb[e] = (long long)P.n_dirs * P.r.size() * E.s_out * E.nsig;
     }
     build_tab(c, kTabAll, all, 256);
@@ -691,6 +712,14 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     up(c->d_probe, probe_flat.data(), sizeof(int) * probe_flat.size());
     up(c->d_comp, P.comps.data(), sizeof(int) * P.comps.size());
     up(c->d_bstart, c->h_bstart.data(), sizeof(int) * c->h_bstart.size());
+    up(c->d_bmap, c->h_bmap.data(), sizeof(int2) * c->h_bmap.size());
+    std::vector<int2> mmap;
+    {
+        const int* b = &c->h_bstart[(size_t)kTabMeas * (n + 1)];
+        for (int e = 0; e < n; ++e)
+            for (int k = b[e]; k < b[e + 1]; ++k) mmap.push_back(make_int2(e, k - b[e]));
+    }
+    up(c->d_mmap, mmap.data(), sizeof(int2) * mmap.size());
     up(c->d_upd, zeros.data(), sizeof(uint32_t) * n);
     up(c->d_ring, ring0, sizeof ring0);
     if (st != U1ML_OK) {
@@ -867,6 +896,7 @@ u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block)
     build_update_tabs(ctx);
     HIPCHK(ctx, hipMemcpy(ctx->d_bstart, ctx->h_bstart.data(), sizeof(int) * 4 * (ctx->P.n_ens + 1),
                           hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(ctx->d_bmap, ctx->h_bmap.data(), sizeof(int2) * ctx->h_bmap.size(), hipMemcpyHostToDevice));
     drop_graphs(ctx);
     return U1ML_OK;
 }

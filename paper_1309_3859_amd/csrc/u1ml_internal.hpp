@@ -13,13 +13,14 @@ struct EnsDesc {
     int nx, ny, nz, nt;
     int nxh, nsig, vh, s_in;  // s_in: slabs of the innermost level
     int s_out, n_vac_blocks, pad0, pad1;
+    float inv_nxh, inv_ny, inv_slice, pad2;  // 1/(Nx/2), 1/Ny, 1/((Nx/2) Ny Nz) for division-free decode
     double beta, sqrt_beta;
     uint32_t seed, key_id;
     long long link_off;
     long long hc_off, ho_off;
     long long at_off, ato_off;
     long long ot_off, oto_off;
-    long long vac_part_off;  // double, [n_vac_blocks][12]
+    long long vac_part_off;  // double, [measurements of a configuration][n_vac_blocks][12]
 };
 
 // Observable tables in device memory.
@@ -36,9 +37,10 @@ constexpr int kUpdateClasses = 4;  // temporal, spatial full, spatial inner tau,
 // --- launchers (k_update.hip) ---
 hipError_t launch_init_links(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
                              void* links, int start, hipStream_t st);
-hipError_t launch_update(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
-                         int precision, void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu,
-                         int parity, int tau, hipStream_t st);
+// d_bmap[b] = (ensemble, block index within the ensemble) for every block of the launch
+hipError_t launch_update(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int block, int precision,
+                         void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu, int parity, int tau,
+                         hipStream_t st);
 hipError_t launch_health(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
                          const void* links, unsigned long long* d_count, hipStream_t st);
 hipError_t launch_plaquette(const EnsDesc* d_ens, int n_ens, int max_blocks_per_ens, int precision, const void* links,
@@ -55,11 +57,9 @@ hipError_t launch_scatter_links(const EnsDesc* d_ens, int ens, int precision, vo
 
 // --- launchers (k_measure.hip) ---
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
-hipError_t launch_measure(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int precision,
-                          const void* links, double2* hist_c, double* hist_o, double* vac_part, int m, int tau,
-                          int store_o, hipStream_t st);
-hipError_t launch_vac_accum(const EnsDesc* d_ens, int n_ens, const double* vac_part, double* vac_acc,
-                            hipStream_t st);
+hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int precision, const void* links,
+                          double2* hist_c, double* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
+                          hipStream_t st);
 hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                            const int* d_r, const int* d_probe, const int* d_comp, const double2* hist_c,
                            const double* hist_o, double2* avg_t, double2* avg_to, int n_meas, hipStream_t st);
@@ -69,7 +69,7 @@ hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, 
 hipError_t launch_product(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, int n_r, int n_pgroups,
                           const double2* src_t, const double2* src_to, int use_outer, double scale, double* results,
                           const int* d_ring, hipStream_t st);
-hipError_t launch_vac_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, const double* vac_acc,
+hipError_t launch_vac_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, const double* vac_part,
                             int n_meas, double* results, const int* d_ring, hipStream_t st);
 hipError_t launch_ring_advance(int* d_ring, hipStream_t st);
 
