@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
+    ap.add_argument("--counters", action="store_true",
+                    help="for hardware-counter runs: one 256 MiB device copy (calibration of the byte counters), "
+                         "then 20 launches each of the heatbath and overrelaxation phases of the dominant kernel")
     return ap.parse_args()
 
 
@@ -99,6 +102,31 @@ def time_steps(ctx, steps: int, warmup: int):
     return ms
 
 
+def run_counter_workload(spec, sched):
+    """Kernels for rocprofv3 --pmc runs: a plain copy of 2^28 bytes (its
+    FETCH_SIZE / WRITE_SIZE give the counters' scale), then the inner-slab
+    spatial heatbath and overrelaxation phases, 20 launches each."""
+    import torch
+
+    from paper_1309_3859_amd import u1ml
+
+    src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx = u1ml.Context(spec)
+    ctx.init_links(sched["start"])
+    ctx.sweeps(2)
+    tau = spec.levels[-1][0]
+    for kind in (0, 1):
+        ctx.time_phase(kind, 0, 0, tau, 20)
+    torch.cuda.synchronize()
+    b0, u0 = ctx.phase_bytes(0, 0, 0, tau)
+    b1, u1 = ctx.phase_bytes(1, 0, 0, tau)
+    print(json.dumps({"copy_bytes": 1 << 28, "hb_bytes": b0, "hb_updates": u0, "or_bytes": b1, "or_updates": u1}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -112,6 +140,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     make = configs.PRESETS[args.workload]
     spec, sched = make()
+    if args.counters:
+        run_counter_workload(spec, sched)
+        return
     spec.max_configs = max(1, args.steps + args.warmup)
     ctx = u1ml.Context(spec)
     ctx.init_links(sched["start"])

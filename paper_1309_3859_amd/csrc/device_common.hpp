@@ -233,6 +233,47 @@ __device__ inline void vonmises_cs_f32(float kappa, uint32_t k0, uint32_t k1, ui
     *spsi = 0.0f;
 }
 
+// The FP32 sampler in pieces, for the heatbath kernel's retry queue: the
+// envelope constant r - 1, and one Philox block's two attempts.
+__device__ inline float bf_rm1_f32(float kappa)
+{
+    using m = M<float>;
+    const float s = m::sqrt_(1.0f + 4.0f * kappa * kappa);
+    const float tau = 1.0f + s;
+    const float rho = m::div_(2.0f * kappa * tau, (s + 1.0f) * (tau + m::sqrt_(2.0f * tau)));
+    const float omr = 1.0f - rho;
+    return m::div_(omr * omr, 2.0f * rho);
+}
+
+// Attempts 2j and 2j+1 of the block b; returns true and (cos psi, sin psi) of
+// the first accepted one.
+__device__ inline bool bf_pair_f32(float kappa, float rm1, const Block4& b, float* cpsi, float* spsi)
+{
+    using m = M<float>;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const uint32_t a = half ? b.w[2] : b.w[0];
+        const uint32_t bb = half ? b.w[3] : b.w[1];
+        const float q = 0.25f * m::u1(a);
+        const float sh = __builtin_amdgcn_sinf(q), ch = __builtin_amdgcn_cosf(q);
+        const float omz = 2.0f * sh * sh, opz = 2.0f * ch * ch;
+        const float inv = __builtin_amdgcn_rcpf(rm1 + opz);
+        const float g = rm1 * omz * inv;
+        const float c = kappa * (rm1 + g);
+        const float u2 = m::u2(bb);
+        bool acc = (c * (2.0f - c) - u2 > 0.0f);
+        if (!acc) acc = (m::log_(m::div_(c, u2)) + 1.0f - c >= 0.0f);
+        if (acc) {
+            const float h = (rm1 + 2.0f) * opz * inv;
+            const float sp = m::sqrt_(g * h);
+            *cpsi = g <= 1.0f ? 1.0f - g : h - 1.0f;
+            *spsi = (a & 1u) ? -sp : sp;
+            return true;
+        }
+    }
+    return false;
+}
+
 template <>
 __device__ inline float vonmises_psi<float>(float kappa, uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
                                             uint32_t domain, int* n_att)
@@ -261,6 +302,72 @@ __device__ inline Coord step(Coord c, int dir, int s, int nx, int ny, int nz, in
     default: c.t = s > 0 ? wrap_p(c.t + 1, nt) : wrap_m(c.t - 1, nt); break;
     }
     return c;
+}
+
+// ---------------------------------------------------------------------------
+// Division-free index decode: q = a / b for 0 <= a, b > 0, a / b < 2^22,
+// from the FP32 reciprocal and one exact correction step.
+// ---------------------------------------------------------------------------
+__device__ inline int fdiv(int a, int b, float inv_b)
+{
+    int q = (int)((float)a * inv_b);
+    const int r = a - (int)__umul24(q, b);
+    q += (r >= b) - (r < 0);
+    return q;
+}
+
+// Site in even/odd storage: coordinates and hrow = (Nx/2) (y + Ny (z + Nz t)),
+// so the half index of a site is (x >> 1) + hrow.
+struct Site {
+    int x, y, z, t, hrow;
+};
+
+struct Geo {
+    int nx, ny, nz, nt, sy, sz, st;  // sy = Nx/2, sz = sy Ny, st = sz Nz (strides in half indices)
+};
+
+// one periodic step along compile-time direction D, sign S
+template <int D, int S>
+__device__ inline Site mv(Site c, const Geo& g)
+{
+    if (D == 0) {
+        c.x = S > 0 ? (c.x == g.nx - 1 ? 0 : c.x + 1) : (c.x == 0 ? g.nx - 1 : c.x - 1);
+    } else if (D == 1) {
+        if (S > 0) {
+            c.hrow += c.y == g.ny - 1 ? -(g.ny - 1) * g.sy : g.sy;
+            c.y = c.y == g.ny - 1 ? 0 : c.y + 1;
+        } else {
+            c.hrow += c.y == 0 ? (g.ny - 1) * g.sy : -g.sy;
+            c.y = c.y == 0 ? g.ny - 1 : c.y - 1;
+        }
+    } else if (D == 2) {
+        if (S > 0) {
+            c.hrow += c.z == g.nz - 1 ? -(g.nz - 1) * g.sz : g.sz;
+            c.z = c.z == g.nz - 1 ? 0 : c.z + 1;
+        } else {
+            c.hrow += c.z == 0 ? (g.nz - 1) * g.sz : -g.sz;
+            c.z = c.z == 0 ? g.nz - 1 : c.z - 1;
+        }
+    } else {
+        if (S > 0) {
+            c.hrow += c.t == g.nt - 1 ? -(g.nt - 1) * g.st : g.st;
+            c.t = c.t == g.nt - 1 ? 0 : c.t + 1;
+        } else {
+            c.hrow += c.t == 0 ? (g.nt - 1) * g.st : -g.st;
+            c.t = c.t == 0 ? g.nt - 1 : c.t - 1;
+        }
+    }
+    return c;
+}
+
+__device__ inline unsigned hidx(const Site& c) { return (unsigned)((c.x >> 1) + c.hrow); }
+
+// Load from a uniform base with a 32-bit byte offset (one ensemble's links
+// span less than 4 GiB), which maps to global_load with a scalar base.
+template <typename real>
+__device__ inline real ldo(const real* __restrict__ base, unsigned byte_off)
+{
+    return *reinterpret_cast<const real*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
 }  // namespace u1ml

@@ -141,36 +141,21 @@ __device__ inline void plaq_O<float>(float th, double beta, double sqrt_beta, do
     *olin = sqrt_beta * (double)s;
 }
 
-struct MSite {
-    int x, y, z, t;
-};
-
-template <typename real>
-__device__ inline real ld_link(const real* __restrict__ lb, const EnsDesc& E, int dir, const MSite& c)
+// Sum of 12 per-thread doubles over a 256-thread block in a fixed order:
+// through LDS, each wave then reduces three of the quantities.
+__device__ inline void block_sum12(const double* v, double* out)
 {
-    const unsigned par = (unsigned)((c.x + c.y + c.z + c.t) & 1);
-    const unsigned h = (unsigned)((c.x >> 1) + E.nxh * (c.y + E.ny * (c.z + E.nz * c.t)));
-    return lb[((unsigned)dir * 2u + par) * (unsigned)E.vh + h];
-}
-
-// 64-lane wave reduction followed by a fixed-order sum over the waves of the block
-template <int N>
-__device__ inline void block_sum(double* v, double* out)
-{
+    __shared__ double red[12][256];
 #pragma unroll
-    for (int k = 0; k < N; ++k)
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    __shared__ double sh[16][N];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < N; ++k) sh[wave][k] = v[k];
+    for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = v[k];
     __syncthreads();
-    if ((int)threadIdx.x < N) {
-        double a = 0.0;
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int w = 0; w < nw; ++w) a += sh[w][threadIdx.x];
-        out[threadIdx.x] = a;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        const int k = 3 * wave + kk;
+        double a = red[k][lane] + red[k][lane + 64] + red[k][lane + 128] + red[k][lane + 192];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        if (lane == 0) out[k] = a;
     }
 }
 
@@ -185,36 +170,42 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
     const int nsig = E.nsig, S = E.s_in;
     const int item = be.y * 256 + (int)threadIdx.x;
     const real* lb = links + E.link_off;
+    const unsigned vh = (unsigned)E.vh;
+    constexpr unsigned w = sizeof(real);
     double vac[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) vac[k] = 0.0;
     if (item < nsig * S) {
+        const Geo g{E.nx, E.ny, E.nz, E.nt, E.nxh, E.nxh * E.ny, E.nxh * E.ny * E.nz};
         const int s = item / nsig;
         const int xs = item - s * nsig;
-        const int x = xs % E.nx;
-        const int y = (xs / E.nx) % E.ny;
-        const int z = xs / (E.nx * E.ny);
-        const int xp = x + 1 == E.nx ? 0 : x + 1, yp = y + 1 == E.ny ? 0 : y + 1, zp = z + 1 == E.nz ? 0 : z + 1;
+        const int yz = xs / E.nx;
+        const int x = xs - yz * E.nx;
+        const int z = yz / E.ny;
+        const int y = yz - z * E.ny;
         double Th = 0.0;
         double os[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) os[k] = 0.0;
-        for (int t = s * tau; t < (s + 1) * tau; ++t) {
-            const int tp = t + 1 == E.nt ? 0 : t + 1;
-            const MSite c{x, y, z, t}, cx{xp, y, z, t}, cy{x, yp, z, t}, cz{x, y, zp, t}, ct{x, y, z, tp};
-            const real ux = ld_link(lb, E, 0, c), uy = ld_link(lb, E, 1, c), uz = ld_link(lb, E, 2, c),
-                       ut = ld_link(lb, E, 3, c);
-            const real tx_x = ld_link(lb, E, 3, cx), tx_y = ld_link(lb, E, 3, cy), tx_z = ld_link(lb, E, 3, cz);
-            const real xt = ld_link(lb, E, 0, ct), yt = ld_link(lb, E, 1, ct), zt = ld_link(lb, E, 2, ct);
-            const real zy = ld_link(lb, E, 2, cy), yz = ld_link(lb, E, 1, cz);
-            const real xz = ld_link(lb, E, 0, cz), zx = ld_link(lb, E, 2, cx);
-            const real yx = ld_link(lb, E, 1, cx), xy = ld_link(lb, E, 0, cy);
+        Site c{x, y, z, s * tau, g.sy * yz + g.st * (s * tau)};
+        for (int k = 0; k < tau; ++k) {
+            const unsigned p = (unsigned)((x + y + z + c.t) & 1), q = p ^ 1u;
+            const Site cx = mv<0, +1>(c, g), cy = mv<1, +1>(c, g), cz = mv<2, +1>(c, g), ct = mv<3, +1>(c, g);
+            auto L = [&](unsigned dir, unsigned par, const Site& st) {
+                return ldo(lb, ((dir * 2u + par) * vh + hidx(st)) * w);
+            };
+            const real ux = L(0, p, c), uy = L(1, p, c), uz = L(2, p, c), ut = L(3, p, c);
+            const real tx_x = L(3, q, cx), tx_y = L(3, q, cy), tx_z = L(3, q, cz);
+            const real xt = L(0, q, ct), yt = L(1, q, ct), zt = L(2, q, ct);
+            const real zy = L(2, q, cy), yz_ = L(1, q, cz);
+            const real xz = L(0, q, cz), zx = L(2, q, cx);
+            const real yx = L(1, q, cx), xy = L(0, q, cy);
             Th += (double)ut;
             real th[6];
             th[0] = ux + tx_x - xt - ut;  // P_xt
             th[1] = uy + tx_y - yt - ut;  // P_yt
             th[2] = uz + tx_z - zt - ut;  // P_zt
-            th[3] = uy + zy - yz - uz;    // P_yz
+            th[3] = uy + zy - yz_ - uz;   // P_yz
             th[4] = uz + xz - zx - ux;    // P_zx
             th[5] = ux + yx - xy - uy;    // P_xy
 #pragma unroll
@@ -224,6 +215,7 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
                 os[2 * o] += a;
                 os[2 * o + 1] += b;
             }
+            c = ct;
         }
         double sn, cs;
         sincos(Th, &sn, &cs);
@@ -236,7 +228,7 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
 #pragma unroll
         for (int k = 0; k < 12; ++k) vac[k] = os[k];
     }
-    block_sum<12>(vac, vac_part + E.vac_part_off + ((size_t)m * E.n_vac_blocks + be.y) * 12);
+    block_sum12(vac, vac_part + E.vac_part_off + ((size_t)m * E.n_vac_blocks + be.y) * 12);
 }
 
 hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int precision, const void* links,

@@ -33,72 +33,6 @@ struct LinkView {
     }
 };
 
-// ---------------------------------------------------------------------------
-// Division-free index decode: q = a / b for 0 <= a, b > 0, a / b < 2^22,
-// from the FP32 reciprocal and one exact correction step.
-// ---------------------------------------------------------------------------
-__device__ inline int fdiv(int a, int b, float inv_b)
-{
-    int q = (int)((float)a * inv_b);
-    const int r = a - (int)__umul24(q, b);
-    q += (r >= b) - (r < 0);
-    return q;
-}
-
-// Site in even/odd storage: coordinates and hrow = (Nx/2) (y + Ny (z + Nz t)),
-// so the half index of a site is (x >> 1) + hrow.
-struct Site {
-    int x, y, z, t, hrow;
-};
-
-struct Geo {
-    int nx, ny, nz, nt, sy, sz, st;  // sy = Nx/2, sz = sy Ny, st = sz Nz (strides in half indices)
-};
-
-// one periodic step along compile-time direction D, sign S
-template <int D, int S>
-__device__ inline Site mv(Site c, const Geo& g)
-{
-    if (D == 0) {
-        c.x = S > 0 ? (c.x == g.nx - 1 ? 0 : c.x + 1) : (c.x == 0 ? g.nx - 1 : c.x - 1);
-    } else if (D == 1) {
-        if (S > 0) {
-            c.hrow += c.y == g.ny - 1 ? -(g.ny - 1) * g.sy : g.sy;
-            c.y = c.y == g.ny - 1 ? 0 : c.y + 1;
-        } else {
-            c.hrow += c.y == 0 ? (g.ny - 1) * g.sy : -g.sy;
-            c.y = c.y == 0 ? g.ny - 1 : c.y - 1;
-        }
-    } else if (D == 2) {
-        if (S > 0) {
-            c.hrow += c.z == g.nz - 1 ? -(g.nz - 1) * g.sz : g.sz;
-            c.z = c.z == g.nz - 1 ? 0 : c.z + 1;
-        } else {
-            c.hrow += c.z == 0 ? (g.nz - 1) * g.sz : -g.sz;
-            c.z = c.z == 0 ? g.nz - 1 : c.z - 1;
-        }
-    } else {
-        if (S > 0) {
-            c.hrow += c.t == g.nt - 1 ? -(g.nt - 1) * g.st : g.st;
-            c.t = c.t == g.nt - 1 ? 0 : c.t + 1;
-        } else {
-            c.hrow += c.t == 0 ? (g.nt - 1) * g.st : -g.st;
-            c.t = c.t == 0 ? g.nt - 1 : c.t - 1;
-        }
-    }
-    return c;
-}
-
-__device__ inline unsigned hidx(const Site& c) { return (unsigned)((c.x >> 1) + c.hrow); }
-
-// Load from a uniform base with a 32-bit byte offset (one ensemble's links
-// span less than 4 GiB), which maps to global_load with a scalar base.
-template <typename real>
-__device__ inline real ldo(const real* __restrict__ base, unsigned byte_off)
-{
-    return *reinterpret_cast<const real*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
 // The six angles of the two staples of link (x, MU) in the plane (MU, NU):
 //   v[0..2] = th_nu(x+mu), th_mu(x+nu), th_nu(x)          (forward)
 //   v[3..5] = th_nu(x-nu), th_nu(x+mu-nu), th_mu(x-nu)    (backward)
@@ -129,12 +63,25 @@ struct Nu {  // K-th direction other than MU, ascending
 // kind 1: overrelaxation theta = wrap(-theta - 2 arg A) (unchanged if A = 0).
 // Staple sum A = sum_{nu != mu} exp(i phi_f) + exp(i phi_b), nu ascending,
 // forward before backward, phi_f = v0 - v1 - v2, phi_b = v3 - v4 - v5.
+//
+// FP32 heatbath: every lane makes the first two rejection attempts (one Philox
+// block); the links still pending (about 1 in 10) are compacted, in lane
+// order, into a queue in LDS and finished by consecutive threads, so a wave no
+// longer waits for its slowest lane.  A link's result depends only on its own
+// counters, so the queue changes no result.
+struct RetryQ {
+    float kappa, ar, ai;
+    unsigned lid, off;
+};
+
 template <typename real, int KIND, int MU>
 __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens, const int2* __restrict__ bmap,
                                                  real* __restrict__ links, const uint32_t* __restrict__ upd,
                                                  int pass_offset, int parity, int tau, float inv_tm1)
 {
+    constexpr bool kQueue = (KIND == 0) && (sizeof(real) == 4);
     const int2 be = bmap[blockIdx.x];
+    if (be.x < 0) return;  // padding block of the XCD-aware order (uniform for the block)
     const int e = be.x;
     const EnsDesc& E = ens[e];
     const Geo g{E.nx, E.ny, E.nz, E.nt, E.nxh, E.nxh * E.ny, E.nxh * E.ny * E.nz};
@@ -142,70 +89,126 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
     const int slice = g.st;
     const int active_t = masked ? g.nt - g.nt / tau : g.nt;
     const int item = be.y * (int)blockDim.x + (int)threadIdx.x;
-    if (item >= slice * active_t) return;
-    const int j = fdiv(item, slice, E.inv_slice);
-    const int rem = item - (int)__umul24(j, slice);
-    int t = j;
-    if (masked) {
-        const int jt = fdiv(j, tau - 1, inv_tm1);
-        t = jt * tau + 1 + (j - jt * (tau - 1));
-    }
-    const int yz = fdiv(rem, g.sy, E.inv_nxh);
-    const int xh = rem - (int)__umul24(yz, g.sy);
-    const int z = fdiv(yz, g.ny, E.inv_ny);
-    const int y = yz - (int)__umul24(z, g.ny);
-    const int x = 2 * xh + ((y + z + t + parity) & 1);
-    const Site c{x, y, z, t, (int)(__umul24(g.sy, yz) + __umul24(g.st, t))};
-
+    const bool active = item < slice * active_t;
+    if (!kQueue && !active) return;
     real* lb = links + E.link_off;
     const unsigned vh = (unsigned)E.vh;
-
-    // every load of the update is issued before any arithmetic
-    const Site cpm = mv<MU, +1>(c, g);
-    real v[3][6];
-    gather_plane<real, MU, Nu<MU, 0>::v>(lb, vh, g, c, cpm, parity, v[0]);
-    gather_plane<real, MU, Nu<MU, 1>::v>(lb, vh, g, c, cpm, parity, v[1]);
-    gather_plane<real, MU, Nu<MU, 2>::v>(lb, vh, g, c, cpm, parity, v[2]);
-    const unsigned self = ((MU * 2 + parity) * vh + (unsigned)(xh + c.hrow)) * (unsigned)sizeof(real);
-    real old = real(0);
-    if (KIND == 1) old = ldo(lb, self);
-    real* dst = reinterpret_cast<real*>(reinterpret_cast<char*>(lb) + self);
-
-    real ar = real(0), ai = real(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        real s, co;
-        M<real>::sincos_(v[k][0] - v[k][1] - v[k][2], &s, &co);
-        ar += co;
-        ai += s;
-        M<real>::sincos_(v[k][3] - v[k][4] - v[k][5], &s, &co);
-        ar += co;
-        ai += s;
-    }
-    if (KIND == 0) {
-        const real R = M<real>::sqrt_(ar * ar + ai * ai);
-        const real kappa = (real)E.beta * R;
-        const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
-        const uint32_t ctr = upd[e] + (uint32_t)pass_offset;
-        int na;
-        if constexpr (sizeof(real) == 4) {
-            // theta = psi - arg A as one angle: exp(i theta) is proportional to
-            // exp(i psi) conj(A), so a single atan2 replaces arccos, atan2 and wrap
-            float cp, sp;
-            vonmises_cs_f32(kappa, E.seed, E.key_id, lid, ctr, DOM_HB, &cp, &sp, &na);
-            if (na < 0) return;
-            const float th = atan2_fast(sp * ar - cp * ai, cp * ar + sp * ai);
-            *dst = th >= 3.14159265f ? -3.14159265f : th;
-        } else {
-            const real phiA = M<real>::atan2_(ai, ar);
-            const real psi = vonmises_psi<real>(kappa, E.seed, E.key_id, lid, ctr, DOM_HB, &na);
-            if (na < 0) return;
-            *dst = wrap_angle<real>(psi - phiA);
+    bool pending = false;
+    float q_kappa = 0.0f, q_ar = 0.0f, q_ai = 0.0f;
+    unsigned q_lid = 0, q_off = 0;
+    if (active) {
+        const int j = fdiv(item, slice, E.inv_slice);
+        const int rem = item - (int)__umul24(j, slice);
+        int t = j;
+        if (masked) {
+            const int jt = fdiv(j, tau - 1, inv_tm1);
+            t = jt * tau + 1 + (j - jt * (tau - 1));
         }
-    } else {
-        if (ar == real(0) && ai == real(0)) return;
-        const real phiA = M<real>::atan2_(ai, ar);
-        *dst = wrap_angle<real>(-old - real(2) * phiA);
+        const int yz = fdiv(rem, g.sy, E.inv_nxh);
+        const int xh = rem - (int)__umul24(yz, g.sy);
+        const int z = fdiv(yz, g.ny, E.inv_ny);
+        const int y = yz - (int)__umul24(z, g.ny);
+        const int x = 2 * xh + ((y + z + t + parity) & 1);
+        const Site c{x, y, z, t, (int)(__umul24(g.sy, yz) + __umul24(g.st, t))};
+
+        // every load of the update is issued before any arithmetic
+        const Site cpm = mv<MU, +1>(c, g);
+        real v[3][6];
+        gather_plane<real, MU, Nu<MU, 0>::v>(lb, vh, g, c, cpm, parity, v[0]);
+        gather_plane<real, MU, Nu<MU, 1>::v>(lb, vh, g, c, cpm, parity, v[1]);
+        gather_plane<real, MU, Nu<MU, 2>::v>(lb, vh, g, c, cpm, parity, v[2]);
+        const unsigned self = ((MU * 2 + parity) * vh + (unsigned)(xh + c.hrow)) * (unsigned)sizeof(real);
+        real old = real(0);
+        if (KIND == 1) old = ldo(lb, self);
+        real* dst = reinterpret_cast<real*>(reinterpret_cast<char*>(lb) + self);
+
+        real ar = real(0), ai = real(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            real s, co;
+            M<real>::sincos_(v[k][0] - v[k][1] - v[k][2], &s, &co);
+            ar += co;
+            ai += s;
+            M<real>::sincos_(v[k][3] - v[k][4] - v[k][5], &s, &co);
+            ar += co;
+            ai += s;
+        }
+        if (KIND == 0) {
+            const real R = M<real>::sqrt_(ar * ar + ai * ai);
+            const real kappa = (real)E.beta * R;
+            const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
+            const uint32_t ctr = upd[e] + (uint32_t)pass_offset;
+            if constexpr (kQueue) {
+                // theta = psi - arg A as one angle: exp(i theta) is proportional to
+                // exp(i psi) conj(A), so a single atan2 replaces arccos, atan2 and wrap
+                float cp = 1.0f, sp = 0.0f;
+                bool done;
+                if (kappa == 0.0f) {
+                    int na;
+                    vonmises_cs_f32(0.0f, E.seed, E.key_id, lid, ctr, DOM_HB, &cp, &sp, &na);
+                    done = true;
+                } else {
+                    const Block4 b0 = philox4x32_10(lid, ctr, 0u, DOM_HB, E.seed, E.key_id);
+                    done = bf_pair_f32(kappa, bf_rm1_f32(kappa), b0, &cp, &sp);
+                }
+                if (done) {
+                    const float th = atan2_fast(sp * ar - cp * ai, cp * ar + sp * ai);
+                    *dst = th >= 3.14159265f ? -3.14159265f : th;
+                } else {
+                    pending = true;
+                    q_kappa = kappa;
+                    q_ar = ar;
+                    q_ai = ai;
+                    q_lid = lid;
+                    q_off = self;
+                }
+            } else {
+                int na;
+                const real phiA = M<real>::atan2_(ai, ar);
+                const real psi = vonmises_psi<real>(kappa, E.seed, E.key_id, lid, ctr, DOM_HB, &na);
+                if (na < 0) return;
+                *dst = wrap_angle<real>(psi - phiA);
+            }
+        } else {
+            if (ar == real(0) && ai == real(0)) return;
+            const real phiA = M<real>::atan2_(ai, ar);
+            *dst = wrap_angle<real>(-old - real(2) * phiA);
+        }
+    }
+    if constexpr (kQueue) {
+        extern __shared__ RetryQ queue[];
+        __shared__ int wave_count[16];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const unsigned long long m = __ballot(pending);
+        if (lane == 0) wave_count[wave] = __popcll(m);
+        __syncthreads();
+        int base = 0, total = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) {
+            base += w < wave ? wave_count[w] : 0;
+            total += wave_count[w];
+        }
+        if (pending) {
+            const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+            queue[pos] = RetryQ{q_kappa, q_ar, q_ai, q_lid, q_off};
+        }
+        __syncthreads();
+        const uint32_t ctr = upd[e] + (uint32_t)pass_offset;
+        for (int i = threadIdx.x; i < total; i += blockDim.x) {
+            const RetryQ r = queue[i];
+            const float rm1 = bf_rm1_f32(r.kappa);
+            float cp = 1.0f, sp = 0.0f;
+            bool done = false;
+            for (uint32_t jp = 1; jp < 32768u && !done; ++jp) {
+                const Block4 b = philox4x32_10(r.lid, ctr, jp, DOM_HB, E.seed, E.key_id);
+                done = bf_pair_f32(r.kappa, rm1, b, &cp, &sp);
+            }
+            if (done) {
+                const float th = atan2_fast(sp * r.ar - cp * r.ai, cp * r.ar + sp * r.ai);
+                *reinterpret_cast<float*>(reinterpret_cast<char*>(lb) + r.off) =
+                    th >= 3.14159265f ? -3.14159265f : th;
+            }
+        }
     }
 }
 
@@ -213,11 +216,12 @@ template <typename real, int KIND>
 static void launch_update_t(dim3 g, dim3 b, hipStream_t st, const EnsDesc* d_ens, const int2* d_bmap, real* links,
                             const uint32_t* d_upd, int pass_offset, int mu, int parity, int tau, float inv_tm1)
 {
+    const size_t lds = (KIND == 0 && sizeof(real) == 4) ? sizeof(RetryQ) * b.x : 0;
     switch (mu) {
-    case 0: hipLaunchKernelGGL((k_update<real, KIND, 0>), g, b, 0, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
-    case 1: hipLaunchKernelGGL((k_update<real, KIND, 1>), g, b, 0, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
-    case 2: hipLaunchKernelGGL((k_update<real, KIND, 2>), g, b, 0, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
-    default: hipLaunchKernelGGL((k_update<real, KIND, 3>), g, b, 0, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 0: hipLaunchKernelGGL((k_update<real, KIND, 0>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 1: hipLaunchKernelGGL((k_update<real, KIND, 1>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 2: hipLaunchKernelGGL((k_update<real, KIND, 2>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    default: hipLaunchKernelGGL((k_update<real, KIND, 3>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
     }
 }
 

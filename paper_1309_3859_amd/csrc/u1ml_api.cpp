@@ -47,6 +47,7 @@ constexpr int kTabMeas = 5;   // spatial sites
 constexpr int kTabCon = 6;    // contraction items
 constexpr int kTabComb = 7;   // combine items
 constexpr int kNumTabs = 8;
+constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
 struct Problem {
     int n_ens = 0;
@@ -176,6 +177,7 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
         const size_t V = nsig * E.nt;
         maxV = std::max(maxV, V);
         blocks64 += (V / 2 + 63) / 64;
+        blocks64 += 8;  // padding of the XCD-aware block order
         const size_t si = E.nt / P.tau_i, so = E.nt / P.tau_o;
         size_t v, t;
         // links: 4 V words, padded to 256 bytes
@@ -315,7 +317,8 @@ struct u1ml_ctx {
     ObsDesc* d_obs = nullptr;
     int *d_r = nullptr, *d_probe = nullptr, *d_comp = nullptr, *d_bstart = nullptr, *d_ring = nullptr;
     int2* d_bmap = nullptr;
-    int2* d_mmap = nullptr;  // measurement launch: block -> (ensemble, local block)
+    int2* d_mmap = nullptr;
+    int upd_grid[kUpdateClasses] = {0, 0, 0, 0};  // grid size of each update class (multiple of 8)  // measurement launch: block -> (ensemble, local block)
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
     // host mirrors
@@ -377,11 +380,24 @@ void build_update_tabs(u1ml_ctx* c)
     build_tab(c, kTabUpd + 1, it1, c->block);
     build_tab(c, kTabUpd + 2, it2, c->block);
     build_tab(c, kTabUpd + 3, it3, c->block);
-    c->h_bmap.assign((size_t)kUpdateClasses * c->Lo.bmap_stride, make_int2(0, 0));
+    // Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8),
+    // and each XCD has its own L2.  Logical block L(b) = (b mod 8) per + b / 8
+    // gives every XCD one contiguous stretch of the lattice, so neighbouring
+    // rows shared by adjacent blocks are fetched into one L2 instead of
+    // several.  Launches have 8 per blocks; entries past the end are idle.
+    c->h_bmap.assign((size_t)kUpdateClasses * c->Lo.bmap_stride, make_int2(-1, 0));
     for (int cls = 0; cls < kUpdateClasses; ++cls) {
         const int* b = &c->h_bstart[(size_t)(kTabUpd + cls) * (n + 1)];
+        const int total = b[n];
+        const int per = (total + kXcds - 1) / kXcds;
+        std::vector<int2> logical(total);
         for (int e = 0; e < n; ++e)
-            for (int k = b[e]; k < b[e + 1]; ++k) c->h_bmap[(size_t)cls * c->Lo.bmap_stride + k] = make_int2(e, k - b[e]);
+            for (int k = b[e]; k < b[e + 1]; ++k) logical[k] = make_int2(e, k - b[e]);
+        for (int phys = 0; phys < per * kXcds; ++phys) {
+            const int L = (phys % kXcds) * per + phys / kXcds;
+            c->h_bmap[(size_t)cls * c->Lo.bmap_stride + phys] = L < total ? logical[L] : make_int2(-1, 0);
+        }
+        c->upd_grid[cls] = per * kXcds;
     }
 }
 
@@ -402,7 +418,8 @@ hipError_t enq_phase(u1ml_ctx* c, hipStream_t st, int kind, int mu, int parity, 
     const int cls = update_class(c, mu, tau, &ok);
     if (!ok) return hipErrorInvalidValue;
     const int tab = kTabUpd + cls;
-    return launch_update(c->d_ens, c->bmap_dev(cls), c->tab_total(tab), c->block, c->P.precision, c->links, c->d_upd,
+    (void)tab;
+    return launch_update(c->d_ens, c->bmap_dev(cls), c->upd_grid[cls], c->block, c->P.precision, c->links, c->d_upd,
                          pass_offset, kind, mu, parity, (mu < 3 && tau > 1) ? tau : 0, st);
 }
 
