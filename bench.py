@@ -25,6 +25,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_update_or_c4_counters.md")
+KERNEL_SOURCES = ["k_update.hip", "device_common.hpp", "u1ml_internal.hpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1309_3859_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the ratio of
+    a plain copy's known bytes to what the same counter read for it), or None
+    when the summary is missing or the kernel sources changed since."""
+    try:
+        vals = {}
+        with open(COUNTERS_FILE) as fh:
+            for line in fh:
+                if line.startswith("- ") and ":" in line:
+                    k, v = line[2:].split(":", 1)
+                    vals[k.strip()] = v.strip().strip("`")
+        if vals.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        fetch = float(vals["fetch_kib_per_launch"]) * float(vals["fetch_scale"])
+        write = float(vals["write_kib_per_launch"]) * float(vals["write_scale"])
+        return (fetch + write) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -179,7 +212,8 @@ def main():
                    "levels": spec.levels, "n_or": spec.n_or, "updates_per_step": upd,
                    "block": tune["chosen_block"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic() if args.workload == "c4" else None,
                      "kernel": "k_update<float,1> (overrelaxation, spatial mu, inner slabs)",
                      "bytes_per_launch": b, "updates_per_launch": u, "us_per_launch": us},
         "phases_us": {f"{'OR' if k else 'HB'}_mu{m}": v[0] for (k, m), v in per_phase.items()},

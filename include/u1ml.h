@@ -214,8 +214,10 @@ u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block);
 u1ml_status u1ml_set_graphs(u1ml_ctx* ctx, int enable);
 
 /* Synchronises.  Average device time in microseconds of one launch of the
- * given checkerboard phase over n_rep launches bracketed by HIP events on the
- * context's stream (links change; counters do not). */
+ * given checkerboard phase: n_rep launches on the context's stream, each with
+ * a start/stop event pair that takes the dispatch's own begin and end
+ * timestamps (hipExtLaunchKernelGGL), so launch gaps are not counted.  Links
+ * change; counters do not. */
 u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int n_rep, double* us);
 
 /* Algorithmic bytes moved by one launch of that phase under the streaming

@@ -162,7 +162,7 @@ __device__ inline void block_sum12(const double* v, double* out)
 template <typename real>
 __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens, const int2* __restrict__ bmap,
                                                  const real* __restrict__ links, double2* __restrict__ hist_c,
-                                                 double* __restrict__ hist_o, double* __restrict__ vac_part, int m_in,
+                                                 real* __restrict__ hist_o, double* __restrict__ vac_part, int m_in,
                                                  int m, int tau, int store_o)
 {
     const int2 be = bmap[blockIdx.x];
@@ -221,9 +221,11 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
         sincos(Th, &sn, &cs);
         hist_c[E.hc_off + ((size_t)m_in * S + s) * nsig + xs] = make_double2(cs, sn);
         if (store_o) {
-            double* ho = hist_o + E.ho_off + ((size_t)m_in * S + s) * 12 * nsig + xs;
+            // per-measurement slab sums are stored in the link precision; the sums
+            // over measurements are formed in FP64 by the contraction
+            real* ho = hist_o + E.ho_off + ((size_t)m_in * S + s) * 12 * nsig + xs;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) ho[(size_t)k * nsig] = os[k];
+            for (int k = 0; k < 12; ++k) ho[(size_t)k * nsig] = (real)os[k];
         }
 #pragma unroll
         for (int k = 0; k < 12; ++k) vac[k] = os[k];
@@ -232,15 +234,15 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
 }
 
 hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int precision, const void* links,
-                          double2* hist_c, double* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
+                          double2* hist_c, void* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
                           hipStream_t st)
 {
     if (precision == 0)
         hipLaunchKernelGGL(k_measure<double>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bmap,
-                           (const double*)links, hist_c, hist_o, vac_part, m_in, m, tau, store_o);
+                           (const double*)links, hist_c, (double*)hist_o, vac_part, m_in, m, tau, store_o);
     else
         hipLaunchKernelGGL(k_measure<float>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bmap,
-                           (const float*)links, hist_c, hist_o, vac_part, m_in, m, tau, store_o);
+                           (const float*)links, hist_c, (float*)hist_o, vac_part, m_in, m, tau, store_o);
     return hipGetLastError();
 }
 
@@ -270,11 +272,12 @@ __device__ inline int probe_site(int x, int y, int z, int dir, int l, int p1, in
     return c[0] + nx * (c[1] + ny * c[2]);
 }
 
+template <typename ot>
 __global__ void __launch_bounds__(256) k_contract(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
                                                   int n_ens, const ObsDesc* __restrict__ obs,
                                                   const int* __restrict__ rlist, const int* __restrict__ probes,
                                                   const int* __restrict__ comps, const double2* __restrict__ hist_c,
-                                                  const double* __restrict__ hist_o, double2* __restrict__ avg_t,
+                                                  const ot* __restrict__ hist_o, double2* __restrict__ avg_t,
                                                   double2* __restrict__ avg_to, int n_meas)
 {
     const int bid = blockIdx.x;
@@ -282,20 +285,20 @@ __global__ void __launch_bounds__(256) k_contract(const EnsDesc* __restrict__ en
     const EnsDesc& E = ens[e];
     const ObsDesc& O = *obs;
     const int nsig = E.nsig, S = E.s_in;
-    // item order: 64 consecutive sites, then r, then the 64-site chunk, slab,
-    // axis -- a block covers several r for the same sites, so the shifted
-    // reads of the history overlap inside the block and hit in L1
+    // grid: x = (64 consecutive sites, then r, then the 64-site chunk) of one
+    // ensemble, y = slab, z = charge axis; slab and axis are uniform per block,
+    // so the history rows are addressed from scalar bases.  A block covers
+    // several r for the same sites, so the shifted reads overlap in L1.
+    const int s = blockIdx.y;
+    const int id = blockIdx.z;
+    if (s >= S) return;
     const int nchunk = (nsig + 63) / 64;
-    const long long item = (long long)(bid - bstart[e]) * blockDim.x + threadIdx.x;
-    if (item >= (long long)O.n_dirs * S * nchunk * O.n_r * 64) return;
-    const int lane = (int)(item & 63);
-    long long rest = item >> 6;
-    const int ir = (int)(rest % O.n_r);
-    rest /= O.n_r;
-    const int chunk = (int)(rest % nchunk);
-    rest /= nchunk;
-    const int s = (int)(rest % S);
-    const int id = (int)(rest / S);
+    const int item = (bid - bstart[e]) * (int)blockDim.x + (int)threadIdx.x;
+    if (item >= nchunk * O.n_r * 64) return;
+    const int lane = item & 63;
+    const int rest = item >> 6;
+    const int ir = rest % O.n_r;
+    const int chunk = rest / O.n_r;
     const int xs = chunk * 64 + lane;
     if (xs >= nsig) return;
     const int dir = O.dirs[id];
@@ -315,47 +318,69 @@ __global__ void __launch_bounds__(256) k_contract(const EnsDesc* __restrict__ en
     }
     avg_t[E.at_off + (((size_t)id * O.n_r + ir) * S + s) * nsig + xs] = make_double2(tre * inv, tim * inv);
 
+    // insertions: probes in chunks of 2, every component and both kinds;
+    // per measurement, T is formed once and the chunk's 24 slab sums are read
     const int nc = O.n_comp;
-    for (int p = 0; p < O.n_probe; ++p) {
-        const int l = probes[4 * p], p1 = probes[4 * p + 1], p2 = probes[4 * p + 2], mode = probes[4 * p + 3];
-        const int y_span = probe_site(x, y, z, dir, l + (mode ? (r - 1) / 2 : 0), p1, p2, E.nx, E.ny, E.nz);
-        const int y_orth = probe_site(x, y, z, dir, l + (mode ? r / 2 : 0), p1, p2, E.nx, E.ny, E.nz);
-        int ys[6], ko[6];
+    constexpr int PC = 2;
+    for (int p0 = 0; p0 < O.n_probe; p0 += PC) {
+        unsigned off[PC][6];  // element offset (orientation row + site) of each (probe, component)
 #pragma unroll
-        for (int ic = 0; ic < 6; ++ic) {
-            const int c = ic < nc ? comps[ic] : 0;
-            ys[ic] = comp_spans_axis(c) ? y_span : y_orth;
-            ko[ic] = 2 * comp_orient(c, dir);
+        for (int pp = 0; pp < PC; ++pp) {
+            const int p = p0 + pp < O.n_probe ? p0 + pp : p0;
+            const int l = probes[4 * p], p1 = probes[4 * p + 1], p2 = probes[4 * p + 2], mode = probes[4 * p + 3];
+            const int y_span = probe_site(x, y, z, dir, l + (mode ? (r - 1) / 2 : 0), p1, p2, E.nx, E.ny, E.nz);
+            const int y_orth = probe_site(x, y, z, dir, l + (mode ? r / 2 : 0), p1, p2, E.nx, E.ny, E.nz);
+#pragma unroll
+            for (int ic = 0; ic < 6; ++ic) {
+                const int c = ic < nc ? comps[ic] : 0;
+                off[pp][ic] = (unsigned)(2 * comp_orient(c, dir)) * (unsigned)nsig +
+                              (unsigned)(comp_spans_axis(c) ? y_span : y_orth);
+            }
         }
-        double acc[6][4];
+        double acc[PC][6][4];
 #pragma unroll
-        for (int ic = 0; ic < 6; ++ic)
+        for (int pp = 0; pp < PC; ++pp)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) acc[ic][k] = 0.0;
+            for (int ic = 0; ic < 6; ++ic)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[pp][ic][k] = 0.0;
         for (int m = 0; m < n_meas; ++m) {
             const double2 a = hc[m * mstride + xs];
             const double2 b = hc[m * mstride + xr];
+            const ot* ho = hist_o + E.ho_off + ((size_t)m * S + s) * 12 * nsig;  // uniform
+            double osq[PC][6], olin[PC][6];
+#pragma unroll
+            for (int pp = 0; pp < PC; ++pp)
+#pragma unroll
+                for (int ic = 0; ic < 6; ++ic) {
+                    osq[pp][ic] = ic < nc ? (double)ldo(ho, off[pp][ic] * (unsigned)sizeof(ot)) : 0.0;
+                    olin[pp][ic] = ic < nc ? (double)ldo(ho, (off[pp][ic] + nsig) * (unsigned)sizeof(ot)) : 0.0;
+                }
             const double Tr = a.x * b.x + a.y * b.y;
             const double Ti = a.x * b.y - a.y * b.x;
-            const double* ho = hist_o + E.ho_off + ((size_t)m * S + s) * 12 * nsig;
+#pragma unroll
+            for (int pp = 0; pp < PC; ++pp)
+#pragma unroll
+                for (int ic = 0; ic < 6; ++ic) {
+                    acc[pp][ic][0] += Tr * osq[pp][ic];
+                    acc[pp][ic][1] += Ti * osq[pp][ic];
+                    acc[pp][ic][2] += Tr * olin[pp][ic];
+                    acc[pp][ic][3] += Ti * olin[pp][ic];
+                }
+        }
+#pragma unroll
+        for (int pp = 0; pp < PC; ++pp) {
+            const int p = p0 + pp;
+            if (p >= O.n_probe) break;
 #pragma unroll
             for (int ic = 0; ic < 6; ++ic) {
                 if (ic < nc) {
-                    const double osq = ho[(size_t)ko[ic] * nsig + ys[ic]];
-                    const double olin = ho[(size_t)(ko[ic] + 1) * nsig + ys[ic]];
-                    acc[ic][0] += Tr * osq;
-                    acc[ic][1] += Ti * osq;
-                    acc[ic][2] += Tr * olin;
-                    acc[ic][3] += Ti * olin;
+                    const size_t k0 = ((((size_t)id * O.n_r + ir) * O.n_probe + p) * nc + ic) * 2;
+                    avg_to[E.ato_off + ((k0 + 0) * S + s) * nsig + xs] =
+                        make_double2(acc[pp][ic][0] * inv, acc[pp][ic][1] * inv);
+                    avg_to[E.ato_off + ((k0 + 1) * S + s) * nsig + xs] =
+                        make_double2(acc[pp][ic][2] * inv, acc[pp][ic][3] * inv);
                 }
-            }
-        }
-#pragma unroll
-        for (int ic = 0; ic < 6; ++ic) {
-            if (ic < nc) {
-                const size_t k0 = ((((size_t)id * O.n_r + ir) * O.n_probe + p) * nc + ic) * 2;
-                avg_to[E.ato_off + ((k0 + 0) * S + s) * nsig + xs] = make_double2(acc[ic][0] * inv, acc[ic][1] * inv);
-                avg_to[E.ato_off + ((k0 + 1) * S + s) * nsig + xs] = make_double2(acc[ic][2] * inv, acc[ic][3] * inv);
             }
         }
     }
@@ -363,10 +388,16 @@ __global__ void __launch_bounds__(256) k_contract(const EnsDesc* __restrict__ en
 
 hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                            const int* d_r, const int* d_probe, const int* d_comp, const double2* hist_c,
-                           const double* hist_o, double2* avg_t, double2* avg_to, int n_meas, hipStream_t st)
+                           const void* hist_o, double2* avg_t, double2* avg_to, int n_meas, int precision,
+                           int max_slabs, int n_dirs, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_contract, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, d_r, d_probe,
-                       d_comp, hist_c, hist_o, avg_t, avg_to, n_meas);
+    const dim3 g(total_blocks, max_slabs, n_dirs);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_contract<double>, g, dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, d_r, d_probe, d_comp,
+                           hist_c, (const double*)hist_o, avg_t, avg_to, n_meas);
+    else
+        hipLaunchKernelGGL(k_contract<float>, g, dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, d_r, d_probe, d_comp,
+                           hist_c, (const float*)hist_o, avg_t, avg_to, n_meas);
     return hipGetLastError();
 }
 

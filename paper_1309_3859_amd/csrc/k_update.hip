@@ -11,6 +11,8 @@
 // 18 angles: 12 of the other parity (coalesced, shifted by one site), 6 of the
 // same parity; none of them is written by the phase, so the update is in place.
 #include "device_common.hpp"
+#include <hip/hip_ext.h>
+
 #include "u1ml_internal.hpp"
 
 namespace u1ml {
@@ -212,36 +214,53 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
     }
 }
 
+// With a start/stop event pair the launch goes through hipExtLaunchKernelGGL,
+// whose events take the dispatch's own begin and end timestamps.
+template <typename real, int KIND, int MU>
+static void launch_update_mu(dim3 g, dim3 b, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                             const EnsDesc* d_ens, const int2* d_bmap, real* links, const uint32_t* d_upd,
+                             int pass_offset, int parity, int tau, float inv_tm1)
+{
+    if (ev0)
+        hipExtLaunchKernelGGL((k_update<real, KIND, MU>), g, b, lds, st, ev0, ev1, 0, d_ens, d_bmap, links, d_upd,
+                              pass_offset, parity, tau, inv_tm1);
+    else
+        hipLaunchKernelGGL((k_update<real, KIND, MU>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset,
+                           parity, tau, inv_tm1);
+}
+
 template <typename real, int KIND>
-static void launch_update_t(dim3 g, dim3 b, hipStream_t st, const EnsDesc* d_ens, const int2* d_bmap, real* links,
-                            const uint32_t* d_upd, int pass_offset, int mu, int parity, int tau, float inv_tm1)
+static void launch_update_t(dim3 g, dim3 b, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const EnsDesc* d_ens,
+                            const int2* d_bmap, real* links, const uint32_t* d_upd, int pass_offset, int mu,
+                            int parity, int tau, float inv_tm1)
 {
     const size_t lds = (KIND == 0 && sizeof(real) == 4) ? sizeof(RetryQ) * b.x : 0;
     switch (mu) {
-    case 0: hipLaunchKernelGGL((k_update<real, KIND, 0>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
-    case 1: hipLaunchKernelGGL((k_update<real, KIND, 1>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
-    case 2: hipLaunchKernelGGL((k_update<real, KIND, 2>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
-    default: hipLaunchKernelGGL((k_update<real, KIND, 3>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 0: launch_update_mu<real, KIND, 0>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 1: launch_update_mu<real, KIND, 1>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 2: launch_update_mu<real, KIND, 2>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    default: launch_update_mu<real, KIND, 3>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
     }
 }
 
 hipError_t launch_update(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int block, int precision,
                          void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu, int parity, int tau,
-                         hipStream_t st)
+                         hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     if (total_blocks <= 0) return hipSuccess;
+    if ((ev_start == nullptr) != (ev_stop == nullptr)) return hipErrorInvalidValue;
     const dim3 g(total_blocks), b(block);
     const float inv_tm1 = tau > 1 ? 1.0f / (float)(tau - 1) : 1.0f;
     if (precision == 0) {
         if (kind == 0)
-            launch_update_t<double, 0>(g, b, st, d_ens, d_bmap, (double*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<double, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, (double*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else
-            launch_update_t<double, 1>(g, b, st, d_ens, d_bmap, (double*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<double, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, (double*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
     } else {
         if (kind == 0)
-            launch_update_t<float, 0>(g, b, st, d_ens, d_bmap, (float*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<float, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, (float*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else
-            launch_update_t<float, 1>(g, b, st, d_ens, d_bmap, (float*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<float, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, (float*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
     }
     return hipGetLastError();
 }

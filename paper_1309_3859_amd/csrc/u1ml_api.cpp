@@ -190,7 +190,7 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
         S->ho.push_back(HO);
         if (store_o) {
             if (!mul_ok((size_t)P.n_i * si * 12, nsig, &t) || !add_ok(HO, t, &HO)) return fail(err, "size overflow (history)");
-            HO = align_up(HO * 8) / 8;
+            HO = align_up(HO * word) / word;
         }
         S->at.push_back(AT);
         AT = align_up((AT + nd * R * si * nsig) * 16) / 16;
@@ -227,7 +227,7 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
     }
     Lo->sz_links = align_up(L);
     Lo->sz_hc = align_up(HC * 16);
-    Lo->sz_ho = align_up(HO * 8);
+    Lo->sz_ho = align_up(HO * word);
     Lo->sz_at = align_up(AT * 16);
     Lo->sz_ato = align_up(ATO * 16);
     Lo->sz_ot = align_up(OT * 16);
@@ -311,14 +311,16 @@ struct u1ml_ctx {
     // device pointers
     void* links = nullptr;
     double2 *hc = nullptr, *at = nullptr, *ato = nullptr, *ot = nullptr, *oto = nullptr;
-    double *ho = nullptr, *res = nullptr, *vpart = nullptr, *ppart = nullptr, *pout = nullptr,
+    void* ho = nullptr;
+    double *res = nullptr, *vpart = nullptr, *ppart = nullptr, *pout = nullptr,
            *stage = nullptr;
     EnsDesc* d_ens = nullptr;
     ObsDesc* d_obs = nullptr;
     int *d_r = nullptr, *d_probe = nullptr, *d_comp = nullptr, *d_bstart = nullptr, *d_ring = nullptr;
     int2* d_bmap = nullptr;
     int2* d_mmap = nullptr;
-    int upd_grid[kUpdateClasses] = {0, 0, 0, 0};  // grid size of each update class (multiple of 8)  // measurement launch: block -> (ensemble, local block)
+    int upd_grid[kUpdateClasses] = {0, 0, 0, 0};  // grid size of each update class (multiple of 8)
+    int max_s_in = 1;                              // largest number of inner slabs in the batch  // measurement launch: block -> (ensemble, local block)
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
     // host mirrors
@@ -412,15 +414,14 @@ int update_class(const u1ml_ctx* c, int mu, int tau, bool* ok)
     return -1;
 }
 
-hipError_t enq_phase(u1ml_ctx* c, hipStream_t st, int kind, int mu, int parity, int tau, int pass_offset)
+hipError_t enq_phase(u1ml_ctx* c, hipStream_t st, int kind, int mu, int parity, int tau, int pass_offset,
+                     hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr)
 {
     bool ok;
     const int cls = update_class(c, mu, tau, &ok);
     if (!ok) return hipErrorInvalidValue;
-    const int tab = kTabUpd + cls;
-    (void)tab;
     return launch_update(c->d_ens, c->bmap_dev(cls), c->upd_grid[cls], c->block, c->P.precision, c->links, c->d_upd,
-                         pass_offset, kind, mu, parity, (mu < 3 && tau > 1) ? tau : 0, st);
+                         pass_offset, kind, mu, parity, (mu < 3 && tau > 1) ? tau : 0, st, ev_start, ev_stop);
 }
 
 hipError_t enq_pass(u1ml_ctx* c, hipStream_t st, int kind, int tau, int pass_offset)
@@ -464,7 +465,7 @@ hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
         }
         if (e == hipSuccess)
             e = launch_contract(c->d_ens, c->tab_dev(kTabCon), n, c->tab_total(kTabCon), c->d_obs, c->d_r, c->d_probe,
-                                c->d_comp, c->hc, c->ho, c->at, c->ato, P.n_i, st);
+                                c->d_comp, c->hc, c->ho, c->at, c->ato, P.n_i, P.precision, c->max_s_in, P.n_dirs, st);
         if (e == hipSuccess && P.two)
             e = launch_combine(c->d_ens, c->tab_dev(kTabComb), n, c->tab_total(kTabComb), c->d_obs, c->at, c->ato,
                                c->ot, c->oto, P.tau_o / P.tau_i, st);
@@ -628,7 +629,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     char* w = c->ws;
     c->links = w + Lo.off_links;
     c->hc = (double2*)(w + Lo.off_hc);
-    c->ho = (double*)(w + Lo.off_ho);
+    c->ho = (void*)(w + Lo.off_ho);
     c->at = (double2*)(w + Lo.off_at);
     c->ato = (double2*)(w + Lo.off_ato);
     c->ot = (double2*)(w + Lo.off_ot);
@@ -708,7 +709,8 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         const EnsDesc& E = c->h_ens[e];
         all[e] = 8ll * E.vh;
         meas[e] = (long long)E.nsig * E.s_in;
-        con[e] = (long long)P.n_dirs * P.r.size() * E.s_in * ((E.nsig + 63) / 64) * 64;
+        con[e] = (long long)P.r.size() * ((E.nsig + 63) / 64) * 64;  // per (slab, axis): grid y and z
+        c->max_s_in = std::max(c->max_s_in, E.s_in);
         comb[e] = (long long)P.n_dirs * P.r.size() * E.s_out * E.nsig;
     }
     build_tab(c, kTabAll, all, 256);
@@ -933,18 +935,24 @@ u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau
     bool ok;
     update_class(ctx, mu, tau, &ok);
     if (!ok) return set_err(ctx, U1ML_EINVAL, "tau must be <= 1 or one of the problem's level thicknesses");
-    hipEvent_t a, b;
-    HIPCHK(ctx, hipEventCreate(&a));
-    HIPCHK(ctx, hipEventCreate(&b));
-    HIPCHK(ctx, hipEventRecord(a, ctx->stream));
-    for (int i = 0; i < n_rep; ++i) HIPCHK(ctx, enq_phase(ctx, ctx->stream, kind, mu, parity, tau, 0));
-    HIPCHK(ctx, hipEventRecord(b, ctx->stream));
-    HIPCHK(ctx, hipEventSynchronize(b));
-    float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    *us = 1000.0 * ms / n_rep;
+    // every launch carries its own start/stop events, which take the dispatch's
+    // begin and end timestamps: the average is the kernel's own duration, the
+    // figure a kernel trace reports, without the launch gaps between dispatches
+    std::vector<hipEvent_t> ev(2 * (size_t)n_rep, nullptr);
+    for (auto& x : ev) HIPCHK(ctx, hipEventCreate(&x));
+    hipError_t he = hipSuccess;
+    for (int i = 0; i < n_rep && he == hipSuccess; ++i)
+        he = enq_phase(ctx, ctx->stream, kind, mu, parity, tau, 0, ev[2 * i], ev[2 * i + 1]);
+    if (he == hipSuccess) he = hipEventSynchronize(ev.back());
+    double total = 0.0;
+    for (int i = 0; i < n_rep && he == hipSuccess; ++i) {
+        float ms = 0.f;
+        he = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+        total += ms;
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (he != hipSuccess) return set_err(ctx, U1ML_EDEVICE, std::string("time_phase: ") + hipGetErrorString(he));
+    *us = 1000.0 * total / n_rep;
     return U1ML_OK;
 }
 

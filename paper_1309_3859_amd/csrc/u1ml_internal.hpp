@@ -37,10 +37,11 @@ constexpr int kUpdateClasses = 4;  // temporal, spatial full, spatial inner tau,
 // --- launchers (k_update.hip) ---
 hipError_t launch_init_links(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
                              void* links, int start, hipStream_t st);
-// d_bmap[b] = (ensemble, block index within the ensemble) for every block of the launch
+// d_bmap[b] = (ensemble, block index within the ensemble) for every block of the launch;
+// ev_start/ev_stop (both or neither) record the dispatch's begin and end timestamps
 hipError_t launch_update(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int block, int precision,
                          void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu, int parity, int tau,
-                         hipStream_t st);
+                         hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_health(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
                          const void* links, unsigned long long* d_count, hipStream_t st);
 hipError_t launch_plaquette(const EnsDesc* d_ens, int n_ens, int max_blocks_per_ens, int precision, const void* links,
@@ -58,11 +59,12 @@ hipError_t launch_scatter_links(const EnsDesc* d_ens, int ens, int precision, vo
 // --- launchers (k_measure.hip) ---
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int precision, const void* links,
-                          double2* hist_c, double* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
+                          double2* hist_c, void* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
                           hipStream_t st);
 hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                            const int* d_r, const int* d_probe, const int* d_comp, const double2* hist_c,
-                           const double* hist_o, double2* avg_t, double2* avg_to, int n_meas, hipStream_t st);
+                           const void* hist_o, double2* avg_t, double2* avg_to, int n_meas, int precision,
+                           int max_slabs, int n_dirs, hipStream_t st);
 hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                           const double2* avg_t, const double2* avg_to, double2* out_t, double2* out_to, int q,
                           hipStream_t st);
