@@ -57,7 +57,7 @@ __device__ inline dd dd_add(dd a, dd b)
     return dd{hi, err - (hi - s)};
 }
 
-// scaled complex: value = (re + i im) * 2^ex, max(|re|,|im|) in [1, 2) or 0
+// scaled complex: value = (re + i im) * 2^ex, max(|re|,|im|) >= 2^-600 or 0
 struct sc {
     double re, im;
     int ex;
@@ -71,14 +71,20 @@ __device__ inline sc sc_norm(double re, double im, int ex)
     return sc{ldexp(re, -k), ldexp(im, -k), ex + k};
 }
 
-__device__ inline sc sc_mul(sc a, double2 b)
+// The mantissa is renormalised only once its magnitude falls below 2^-600:
+// scaling by a power of two commutes with rounding while values stay normal,
+// so the result equals renormalising after every product, bit for bit.
+__device__ inline sc sc_lazy(double re, double im, int ex)
 {
-    return sc_norm(a.re * b.x - a.im * b.y, a.re * b.y + a.im * b.x, a.ex);
+    if (fmax(fabs(re), fabs(im)) < 0x1p-600) return sc_norm(re, im, ex);
+    return sc{re, im, ex};
 }
+
+__device__ inline sc sc_mul(sc a, double2 b) { return sc_lazy(a.re * b.x - a.im * b.y, a.re * b.y + a.im * b.x, a.ex); }
 
 __device__ inline sc sc_mul(sc a, sc b)
 {
-    return sc_norm(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re, a.ex + b.ex);
+    return sc_lazy(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re, a.ex + b.ex);
 }
 
 __device__ inline double2 sc_val(sc a) { return make_double2(ldexp(a.re, a.ex), ldexp(a.im, a.ex)); }
@@ -114,7 +120,8 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st)
 //   hist_o[m_in][s][2o+k][x] = sum_{t in s} O_k(P_o(x, t)); k = 0: 2 beta (1 - cos),
 //                              k = 1: sqrt(beta) sin, orientations o = P_xt, P_yt,
 //                              P_zt, P_yz, P_zx, P_xy
-//   vac_part[m][block][2o+k] = block sum of O_k over every plaquette (vacuum <O>)
+//   vac_part[block][2o+k]    += block sum of O_k over every plaquette (vacuum <O>),
+//                              double-double, measurements in order
 // m_in indexes the measurement inside the innermost level, m the measurement
 // inside the configuration.
 // ---------------------------------------------------------------------------
@@ -141,9 +148,12 @@ __device__ inline void plaq_O<float>(float th, double beta, double sqrt_beta, do
     *olin = sqrt_beta * (double)s;
 }
 
-// Sum of 12 per-thread doubles over a 256-thread block in a fixed order:
-// through LDS, each wave then reduces three of the quantities.
-__device__ inline void block_sum12(const double* v, double* out)
+// Sum of 12 per-thread doubles over a 256-thread block in a fixed order
+// (through LDS, then each wave reduces three of the quantities), added to the
+// block's running double-double partials acc[12][2] of the configuration; the
+// first measurement (first != 0) overwrites them instead, so they need no
+// clearing between configurations.
+__device__ inline void block_sum12(const double* v, double* acc, int first)
 {
     __shared__ double red[12][256];
 #pragma unroll
@@ -155,7 +165,11 @@ __device__ inline void block_sum12(const double* v, double* out)
         const int k = 3 * wave + kk;
         double a = red[k][lane] + red[k][lane + 64] + red[k][lane + 128] + red[k][lane + 192];
         for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
-        if (lane == 0) out[k] = a;
+        if (lane == 0) {
+            const dd r = first ? dd{a, 0.0} : dd_add(dd{acc[2 * k], acc[2 * k + 1]}, a);
+            acc[2 * k] = r.hi;
+            acc[2 * k + 1] = r.lo;
+        }
     }
 }
 
@@ -230,7 +244,7 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
 #pragma unroll
         for (int k = 0; k < 12; ++k) vac[k] = os[k];
     }
-    block_sum12(vac, vac_part + E.vac_part_off + ((size_t)m * E.n_vac_blocks + be.y) * 12);
+    block_sum12(vac, vac_part + E.vac_part_off + (size_t)be.y * 24, m == 0);
 }
 
 hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int precision, const void* links,
@@ -247,157 +261,239 @@ hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_bl
 }
 
 // ---------------------------------------------------------------------------
-// Inner-level contraction: one work-item per (ensemble, axis, r, slab s, x).
-//   [T](s,x,r)  = 1/n sum_m conj(c_m(s,x)) c_m(s,x+r mu)
-//   [TO](s,x,r,p,c,k) = 1/n sum_m T_m(s,x,r) Osum_m(s, x0(x,r,p,c), o(c,mu), k)
+// Inner-level contraction, for charge axis mu and slab s (c_m: stored slab
+// phases, O_m: stored slab sums of measurement m):
+//   [T](s,x,r)        = 1/n sum_m conj(c_m(x)) c_m(x + r mu)
+//   [TO](s,x,r,p,c,k) = 1/n sum_m T_m(s,x,r) O_m(x + l mu + p1 e1 + p2 e2, o(c), k)
+// Everything a pair (x, r) reads lies on its own line parallel to mu and, per
+// probe, on the line displaced by (p1, p2).  A group of threads owns one line,
+// one thread per pair (x, r); the line's phases, and the displaced line's O
+// sums for one probe at a time, are staged through LDS in chunks of
+// measurements, so memory delivers each history element once per line
+// (once per probe for the O sums) rather than once per separation.  The sums
+// over measurements run in order m = 0, 1, ... in every thread.
+// Launch: grid (work-groups of the ensembles' lines, slab, axis); a
+// work-group holds E.con_lpb lines of blockDim / con_lpb threads each.
 // ---------------------------------------------------------------------------
-__device__ inline int shift_site(int x, int y, int z, int dir, int d, int nx, int ny, int nz)
+template <typename ot, bool INS>
+__global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
+                                                   int n_ens, const ObsDesc* __restrict__ obs,
+                                                   const int* __restrict__ rlist, const int* __restrict__ probes,
+                                                   const int* __restrict__ comps, const double2* __restrict__ hist_c,
+                                                   const ot* __restrict__ hist_o, double2* __restrict__ avg_t,
+                                                   double2* __restrict__ avg_to, int n_meas)
 {
-    int c[3] = {x, y, z};
-    const int n[3] = {nx, ny, nz};
-    int v = (c[dir] + d) % n[dir];
-    if (v < 0) v += n[dir];
-    c[dir] = v;
-    return c[0] + nx * (c[1] + ny * c[2]);
-}
-
-__device__ inline int probe_site(int x, int y, int z, int dir, int l, int p1, int p2, int nx, int ny, int nz)
-{
-    const int n[3] = {nx, ny, nz};
-    int c[3] = {x, y, z};
-    const int d1 = (dir + 1) % 3, d2 = (dir + 2) % 3;
-    c[dir] = ((c[dir] + l) % n[dir] + n[dir]) % n[dir];
-    c[d1] = ((c[d1] + p1) % n[d1] + n[d1]) % n[d1];
-    c[d2] = ((c[d2] + p2) % n[d2] + n[d2]) % n[d2];
-    return c[0] + nx * (c[1] + ny * c[2]);
-}
-
-template <typename ot>
-__global__ void __launch_bounds__(256) k_contract(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
-                                                  int n_ens, const ObsDesc* __restrict__ obs,
-                                                  const int* __restrict__ rlist, const int* __restrict__ probes,
-                                                  const int* __restrict__ comps, const double2* __restrict__ hist_c,
-                                                  const ot* __restrict__ hist_o, double2* __restrict__ avg_t,
-                                                  double2* __restrict__ avg_to, int n_meas)
-{
-    const int bid = blockIdx.x;
-    const int e = find_ens_m(bstart, n_ens, bid);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int e = find_ens_m(bstart, n_ens, blockIdx.x);
     const EnsDesc& E = ens[e];
     const ObsDesc& O = *obs;
-    const int nsig = E.nsig, S = E.s_in;
-    // grid: x = (64 consecutive sites, then r, then the 64-site chunk) of one
-    // ensemble, y = slab, z = charge axis; slab and axis are uniform per block,
-    // so the history rows are addressed from scalar bases.  A block covers
-    // several r for the same sites, so the shifted reads overlap in L1.
-    const int s = blockIdx.y;
-    const int id = blockIdx.z;
-    if (s >= S) return;
-    const int nchunk = (nsig + 63) / 64;
-    const int item = (bid - bstart[e]) * (int)blockDim.x + (int)threadIdx.x;
-    if (item >= nchunk * O.n_r * 64) return;
-    const int lane = item & 63;
-    const int rest = item >> 6;
-    const int ir = rest % O.n_r;
-    const int chunk = rest / O.n_r;
-    const int xs = chunk * 64 + lane;
-    if (xs >= nsig) return;
-    const int dir = O.dirs[id];
-    const int r = rlist[ir];
-    const int x = xs % E.nx, y = (xs / E.nx) % E.ny, z = xs / (E.nx * E.ny);
-    const int xr = shift_site(x, y, z, dir, r, E.nx, E.ny, E.nz);
+    const int S = E.s_in, s = blockIdx.y;
+    if (s >= S) return;  // uniform for the block
+    const int id = blockIdx.z, dir = O.dirs[id];
+    const int n3[3] = {E.nx, E.ny, E.nz};
+    const int N = n3[dir];
+    const int d1 = dir == 2 ? 0 : dir + 1, d2 = dir == 0 ? 2 : dir - 1;  // (dir + 1) % 3, (dir + 2) % 3
+    const int nsig = E.nsig;
+    const int nlines = nsig / N;
+    const int lpb = E.con_lpb, G = (int)blockDim.x / lpb;
+    const int grp = (int)threadIdx.x / G, lane = (int)threadIdx.x - grp * G;
+    const int line = (blockIdx.x - bstart[e]) * lpb + grp;
+    if ((blockIdx.x - bstart[e]) * lpb >= nlines) return;  // whole block past this axis' lines (uniform)
+    const bool line_ok = line < nlines;
+    const int mc = E.con_mc;
+    const int nmax = max(E.nx, max(E.ny, E.nz));
+    const int row_len = mc * nmax;  // LDS elements per staged row of one line
+    double2* cl = reinterpret_cast<double2*>(lds_raw) + (size_t)grp * row_len;
+    ot* ol = reinterpret_cast<ot*>(lds_raw + (size_t)lpb * row_len * sizeof(double2)) + (size_t)grp * 12 * row_len;
+
+    // transverse coordinates of the line; sites along it are `stride` apart
+    const int a1 = line_ok ? line % n3[d1] : 0, a2 = line_ok ? line / n3[d1] : 0;
+    const int stride = dir == 0 ? 1 : (dir == 1 ? E.nx : E.nx * E.ny);
+    auto site0 = [&](int o1, int o2) {  // line position 0, displaced by (o1, o2) across the axis
+        int c[3];
+        c[dir] = 0;
+        c[d1] = ((a1 + o1) % n3[d1] + n3[d1]) % n3[d1];
+        c[d2] = ((a2 + o2) % n3[d2] + n3[d2]) % n3[d2];
+        return c[0] + E.nx * (c[1] + E.ny * c[2]);
+    };
+    const int base = site0(0, 0);
     const size_t mstride = (size_t)S * nsig;
-    const double2* hc = hist_c + E.hc_off + (size_t)s * nsig;
+    const double2* hc = hist_c + E.hc_off + (size_t)s * nsig + base;
     const double inv = 1.0 / (double)n_meas;
+    const int nr = O.n_r, pairs = N * nr;
+    const int npass = (pairs + G - 1) / G;
 
-    double tre = 0.0, tim = 0.0;
-    for (int m = 0; m < n_meas; ++m) {
-        const double2 a = hc[m * mstride + xs];
-        const double2 b = hc[m * mstride + xr];
-        tre += a.x * b.x + a.y * b.y;
-        tim += a.x * b.y - a.y * b.x;
-    }
-    avg_t[E.at_off + (((size_t)id * O.n_r + ir) * S + s) * nsig + xs] = make_double2(tre * inv, tim * inv);
+    // element j of a staged block of rows of N: (row, k) = (j / N, j % N),
+    // carried from lane to lane + G without a division per element
+    const int g_q = G / N, g_k = G - (G / N) * N;
+    const int l_q = lane / N, l_k = lane - (lane / N) * N;
+    auto stage_c = [&](int m0, int mm) {
+        int q = l_q, k = l_k;
+        for (int j = lane; j < mm * N; j += G) {
+            cl[q * N + k] = hc[(size_t)(m0 + q) * mstride + (size_t)k * stride];
+            q += g_q;
+            k += g_k;
+            if (k >= N) {
+                k -= N;
+                ++q;
+            }
+        }
+    };
 
-    // insertions: probes in chunks of 2, every component and both kinds;
-    // per measurement, T is formed once and the chunk's 24 slab sums are read
-    const int nc = O.n_comp;
-    constexpr int PC = 2;
-    for (int p0 = 0; p0 < O.n_probe; p0 += PC) {
-        unsigned off[PC][6];  // element offset (orientation row + site) of each (probe, component)
+    for (int pass = 0; !INS && pass < npass; ++pass) {
+        const int pr = pass * G + lane;
+        const bool act = line_ok && pr < pairs;
+        const int ir = act ? pr / N : 0;
+        const int x = act ? pr - ir * N : 0;
+        int xr = x + rlist[ir];  // 1 <= r < N
+        if (xr >= N) xr -= N;
+        double tre = 0.0, tim = 0.0;
+        for (int m0 = 0; m0 < n_meas; m0 += mc) {
+            const int mm = min(mc, n_meas - m0);
+            __syncthreads();
+            if (line_ok) stage_c(m0, mm);
+            __syncthreads();
+            if (act) {
+                int q = 0;
+                for (; q + 4 <= mm; q += 4) {  // four measurements' reads in flight, summed in order
+                    double2 a[4], b[4];
 #pragma unroll
-        for (int pp = 0; pp < PC; ++pp) {
-            const int p = p0 + pp < O.n_probe ? p0 + pp : p0;
-            const int l = probes[4 * p], p1 = probes[4 * p + 1], p2 = probes[4 * p + 2], mode = probes[4 * p + 3];
-            const int y_span = probe_site(x, y, z, dir, l + (mode ? (r - 1) / 2 : 0), p1, p2, E.nx, E.ny, E.nz);
-            const int y_orth = probe_site(x, y, z, dir, l + (mode ? r / 2 : 0), p1, p2, E.nx, E.ny, E.nz);
+                    for (int u = 0; u < 4; ++u) {
+                        a[u] = cl[(q + u) * N + x];
+                        b[u] = cl[(q + u) * N + xr];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        tre += a[u].x * b[u].x + a[u].y * b[u].y;
+                        tim += a[u].x * b[u].y - a[u].y * b[u].x;
+                    }
+                }
+                for (; q < mm; ++q) {
+                    const double2 a = cl[q * N + x];
+                    const double2 b = cl[q * N + xr];
+                    tre += a.x * b.x + a.y * b.y;
+                    tim += a.x * b.y - a.y * b.x;
+                }
+            }
+        }
+        if (act)
+            avg_t[E.at_off + (((size_t)id * nr + ir) * S + s) * nsig + base + (size_t)x * stride] =
+                make_double2(tre * inv, tim * inv);
+    }
+    if (!INS || O.n_probe == 0) return;  // uniform
+
+    // insertions, one probe at a time: all components, both kinds
+    const int nc = O.n_comp;
+    const size_t mstride_o = (size_t)S * 12 * nsig;
+    const ot* ho = hist_o + E.ho_off + (size_t)s * 12 * nsig;
+    int row[6];
+#pragma unroll
+    for (int ic = 0; ic < 6; ++ic) row[ic] = 2 * comp_orient(ic < nc ? comps[ic] : 0, dir);
+    for (int p = 0; p < O.n_probe; ++p) {
+        const int l = probes[4 * p], p1 = probes[4 * p + 1], p2 = probes[4 * p + 2], mode = probes[4 * p + 3];
+        const int obase = site0(p1, p2);
+        for (int pass = 0; pass < npass; ++pass) {
+            const int pr = pass * G + lane;
+            const bool act = line_ok && pr < pairs;
+            const int ir = act ? pr / N : 0;
+            const int x = act ? pr - ir * N : 0;
+            const int r = rlist[ir];
+            int xr = x + r;
+            if (xr >= N) xr -= N;
+            int pos[6];
 #pragma unroll
             for (int ic = 0; ic < 6; ++ic) {
                 const int c = ic < nc ? comps[ic] : 0;
-                off[pp][ic] = (unsigned)(2 * comp_orient(c, dir)) * (unsigned)nsig +
-                              (unsigned)(comp_spans_axis(c) ? y_span : y_orth);
+                const int sh = l + (mode ? (comp_spans_axis(c) ? (r - 1) / 2 : r / 2) : 0);
+                pos[ic] = ((x + sh) % N + N) % N;
             }
-        }
-        double acc[PC][6][4];
-#pragma unroll
-        for (int pp = 0; pp < PC; ++pp)
+            double acc[6][4];
 #pragma unroll
             for (int ic = 0; ic < 6; ++ic)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc[pp][ic][k] = 0.0;
-        for (int m = 0; m < n_meas; ++m) {
-            const double2 a = hc[m * mstride + xs];
-            const double2 b = hc[m * mstride + xr];
-            const ot* ho = hist_o + E.ho_off + ((size_t)m * S + s) * 12 * nsig;  // uniform
-            double osq[PC][6], olin[PC][6];
+                for (int k = 0; k < 4; ++k) acc[ic][k] = 0.0;
+            for (int m0 = 0; m0 < n_meas; m0 += mc) {
+                const int mm = min(mc, n_meas - m0);
+                __syncthreads();
+                if (line_ok) {
+                    stage_c(m0, mm);
+                    // rows [12][mm][N] of the displaced line (row rq = rw * mm + q)
+                    int rw = l_q / mm, q = l_q - (l_q / mm) * mm, k = l_k;
+                    for (int j = lane; j < 12 * mm * N; j += G) {
+                        ol[(rw * mc + q) * N + k] =
+                            ho[(size_t)(m0 + q) * mstride_o + (size_t)rw * nsig + obase + (size_t)k * stride];
+                        q += g_q;
+                        k += g_k;
+                        if (k >= N) {
+                            k -= N;
+                            ++q;
+                        }
+                        while (q >= mm) {
+                            q -= mm;
+                            ++rw;
+                        }
+                    }
+                }
+                __syncthreads();
+                if (act) {
+                    // every component slot is evaluated (slots past n_comp read a valid
+                    // row and are never stored), so the 12 reads issue together
+                    int q = 0;
+                    for (; q < mm; ++q) {
+                        const double2 a = cl[q * N + x];
+                        const double2 b = cl[q * N + xr];
+                        const double Tr = a.x * b.x + a.y * b.y;
+                        const double Ti = a.x * b.y - a.y * b.x;
 #pragma unroll
-            for (int pp = 0; pp < PC; ++pp)
+                        for (int ic = 0; ic < 6; ++ic) {
+                            const double osq = (double)ol[(row[ic] * mc + q) * N + pos[ic]];
+                            const double olin = (double)ol[((row[ic] + 1) * mc + q) * N + pos[ic]];
+                            acc[ic][0] += Tr * osq;
+                            acc[ic][1] += Ti * osq;
+                            acc[ic][2] += Tr * olin;
+                            acc[ic][3] += Ti * olin;
+                        }
+                    }
+                }
+            }
+            if (act) {
+                const size_t xs = (size_t)base + (size_t)x * stride;
 #pragma unroll
                 for (int ic = 0; ic < 6; ++ic) {
-                    osq[pp][ic] = ic < nc ? (double)ldo(ho, off[pp][ic] * (unsigned)sizeof(ot)) : 0.0;
-                    olin[pp][ic] = ic < nc ? (double)ldo(ho, (off[pp][ic] + nsig) * (unsigned)sizeof(ot)) : 0.0;
-                }
-            const double Tr = a.x * b.x + a.y * b.y;
-            const double Ti = a.x * b.y - a.y * b.x;
-#pragma unroll
-            for (int pp = 0; pp < PC; ++pp)
-#pragma unroll
-                for (int ic = 0; ic < 6; ++ic) {
-                    acc[pp][ic][0] += Tr * osq[pp][ic];
-                    acc[pp][ic][1] += Ti * osq[pp][ic];
-                    acc[pp][ic][2] += Tr * olin[pp][ic];
-                    acc[pp][ic][3] += Ti * olin[pp][ic];
-                }
-        }
-#pragma unroll
-        for (int pp = 0; pp < PC; ++pp) {
-            const int p = p0 + pp;
-            if (p >= O.n_probe) break;
-#pragma unroll
-            for (int ic = 0; ic < 6; ++ic) {
-                if (ic < nc) {
-                    const size_t k0 = ((((size_t)id * O.n_r + ir) * O.n_probe + p) * nc + ic) * 2;
-                    avg_to[E.ato_off + ((k0 + 0) * S + s) * nsig + xs] =
-                        make_double2(acc[pp][ic][0] * inv, acc[pp][ic][1] * inv);
-                    avg_to[E.ato_off + ((k0 + 1) * S + s) * nsig + xs] =
-                        make_double2(acc[pp][ic][2] * inv, acc[pp][ic][3] * inv);
+                    if (ic < nc) {
+                        const size_t k0 = ((((size_t)id * nr + ir) * O.n_probe + p) * nc + ic) * 2;
+                        avg_to[E.ato_off + ((k0 + 0) * S + s) * nsig + xs] =
+                            make_double2(acc[ic][0] * inv, acc[ic][1] * inv);
+                        avg_to[E.ato_off + ((k0 + 1) * S + s) * nsig + xs] =
+                            make_double2(acc[ic][2] * inv, acc[ic][3] * inv);
+                    }
                 }
             }
         }
     }
 }
 
-hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
-                           const int* d_r, const int* d_probe, const int* d_comp, const double2* hist_c,
-                           const void* hist_o, double2* avg_t, double2* avg_to, int n_meas, int precision,
-                           int max_slabs, int n_dirs, hipStream_t st)
+hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
+                           size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_probe,
+                           const int* d_comp, const double2* hist_c, const void* hist_o, double2* avg_t,
+                           double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st)
 {
     const dim3 g(total_blocks, max_slabs, n_dirs);
-    if (precision == 0)
-        hipLaunchKernelGGL(k_contract<double>, g, dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, d_r, d_probe, d_comp,
-                           hist_c, (const double*)hist_o, avg_t, avg_to, n_meas);
-    else
-        hipLaunchKernelGGL(k_contract<float>, g, dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, d_r, d_probe, d_comp,
-                           hist_c, (const float*)hist_o, avg_t, avg_to, n_meas);
+    // slab averages of T, then (if there are probes) the insertions, which
+    // need about twice the registers
+    if (precision == 0) {
+        hipLaunchKernelGGL((k_contract<double, false>), g, dim3(block), lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,
+                           d_r, d_probe, d_comp, hist_c, (const double*)hist_o, avg_t, avg_to, n_meas);
+        if (hist_o)
+            hipLaunchKernelGGL((k_contract<double, true>), g, dim3(block), lds_bytes, st, d_ens, d_bstart, n_ens,
+                               d_obs, d_r, d_probe, d_comp, hist_c, (const double*)hist_o, avg_t, avg_to, n_meas);
+    } else {
+        hipLaunchKernelGGL((k_contract<float, false>), g, dim3(block), lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,
+                           d_r, d_probe, d_comp, hist_c, (const float*)hist_o, avg_t, avg_to, n_meas);
+        if (hist_o)
+            hipLaunchKernelGGL((k_contract<float, true>), g, dim3(block), lds_bytes, st, d_ens, d_bstart, n_ens,
+                               d_obs, d_r, d_probe, d_comp, hist_c, (const float*)hist_o, avg_t, avg_to, n_meas);
+    }
     return hipGetLastError();
 }
 
@@ -464,24 +560,28 @@ hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, 
 }
 
 // ---------------------------------------------------------------------------
-// Slab products and sums over sites.  Block (e, r, probe): every thread walks
-// (axis, x) in a fixed stride, forms P(x) = prod_S A(S) and
-// W_S(x) = prod_{S' != S} A(S') as scaled complex numbers, and adds
-// P (correlator, probe 0 only) and sum_S B(S) W_S (insertions) to
-// double-double accumulators; a fixed-order tree reduces the block.
+// Slab products and sums over sites.  Work-group (e, r, probe group, chunk):
+// every thread walks the chunk's (axis, x) items in a fixed stride, forms
+// P(x) = prod_S A(S) and W_S(x) = prod_{S' != S} A(S') as scaled complex
+// numbers, and adds P (correlator, probe 0 only) and sum_S B(S) W_S
+// (insertions) to double-double accumulators; a fixed-order tree reduces the
+// work-group into part[wg][26][hi, lo], and k_product_final adds the chunks
+// of each (e, r, probe) in chunk order.
 // src_t  = A * scale_t, src_to = B * scale_t (scale_t = 1 or 1/n_outer).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_product(const EnsDesc* __restrict__ ens, const ObsDesc* __restrict__ obs,
-                                                 int n_pgroups, const double2* __restrict__ src_t,
-                                                 const double2* __restrict__ src_to, int use_outer, double scale_t,
-                                                 double* __restrict__ results, const int* __restrict__ ring)
+__global__ void __launch_bounds__(256) k_product(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
+                                                 int n_ens, const ObsDesc* __restrict__ obs, int n_pgroups,
+                                                 const double2* __restrict__ src_t, const double2* __restrict__ src_to,
+                                                 int use_outer, double scale_t, double* __restrict__ part)
 {
-    const int n_r = obs->n_r;
-    const int e = blockIdx.x / (n_r * n_pgroups);
-    const int ir = (blockIdx.x / n_pgroups) % n_r;
-    const int p = blockIdx.x % n_pgroups;
+    const int e = find_ens_m(bstart, n_ens, blockIdx.x);
     const EnsDesc& E = ens[e];
     const ObsDesc& O = *obs;
+    const int n_r = O.n_r;
+    const int local = blockIdx.x - bstart[e];
+    const int ch = local % E.prod_nch;
+    const int p = (local / E.prod_nch) % n_pgroups;
+    const int ir = local / (E.prod_nch * n_pgroups);
     const int nsig = E.nsig;
     const int S = use_outer ? E.s_out : E.s_in;
     const long long t_off = use_outer ? E.ot_off : E.at_off;
@@ -496,7 +596,8 @@ __global__ void __launch_bounds__(256) k_product(const EnsDesc* __restrict__ ens
         oim[k] = dd{0, 0};
     }
     const int n_items = O.n_dirs * nsig;
-    for (int it = threadIdx.x; it < n_items; it += blockDim.x) {
+    const int it_end = min(n_items, (ch + 1) * kProdChunk);
+    for (int it = ch * kProdChunk + (int)threadIdx.x; it < it_end; it += blockDim.x) {
         const int id = it / nsig, xs = it - id * nsig;
         const size_t trow = ((size_t)id * n_r + ir) * S;
         sc P{1.0, 0.0, 0};
@@ -535,12 +636,7 @@ __global__ void __launch_bounds__(256) k_product(const EnsDesc* __restrict__ ens
             }
         }
     }
-    // fixed-order block reduction of each quantity
     __shared__ double shh[256], shl[256];
-    const int slot = *ring;
-    double* out = results + ((size_t)slot * gridDim.x / (n_r * n_pgroups) + e) * O.n_doubles_per_config;
-    const double nC = 1.0 / ((double)nsig * O.n_dirs);
-    const double nCO = nC / (double)E.nt;
     auto reduce = [&](dd v) -> dd {
         shh[threadIdx.x] = v.hi;
         shl[threadIdx.x] = v.lo;
@@ -558,38 +654,80 @@ __global__ void __launch_bounds__(256) k_product(const EnsDesc* __restrict__ ens
         __syncthreads();
         return r;
     };
-    if (p == 0) {
-        const dd a = reduce(cre), b = reduce(cim);
+    double* out = part + (size_t)blockIdx.x * kProdQ * 2;
+    auto put = [&](int q, dd v) {
         if (threadIdx.x == 0) {
-            out[2 * ir] = (a.hi + a.lo) * nC;
-            out[2 * ir + 1] = (b.hi + b.lo) * nC;
+            out[2 * q] = v.hi;
+            out[2 * q + 1] = v.lo;
         }
+    };
+    if (p == 0) {
+        put(0, reduce(cre));
+        put(1, reduce(cim));
     }
     if (has_probe) {
-        const long long base_co = 2ll * n_r;
-        for (int k = 0; k < 2 * nc; ++k) {
-            const dd a = reduce(ore[k]), b = reduce(oim[k]);
-            if (threadIdx.x == 0) {
-                const long long idx = (((long long)ir * O.n_probe + p) * nc) * 2 + k;
-                out[base_co + 2 * idx] = (a.hi + a.lo) * nCO;
-                out[base_co + 2 * idx + 1] = (b.hi + b.lo) * nCO;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            if (k < 2 * nc) {  // uniform
+                put(2 + 2 * k, reduce(ore[k]));
+                put(3 + 2 * k, reduce(oim[k]));
             }
         }
     }
 }
 
-hipError_t launch_product(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, int n_r, int n_pgroups,
-                          const double2* src_t, const double2* src_to, int use_outer, double scale, double* results,
-                          const int* d_ring, hipStream_t st)
+// One work-item per (e, r, probe group, quantity): the chunk partials in
+// chunk order, normalised and written to the configuration's result row.
+__global__ void __launch_bounds__(64) k_product_final(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
+                                                      int n_ens, const ObsDesc* __restrict__ obs, int n_pgroups,
+                                                      const double* __restrict__ part, double* __restrict__ results,
+                                                      const int* __restrict__ ring)
 {
-    hipLaunchKernelGGL(k_product, dim3(n_ens * n_r * n_pgroups), dim3(256), 0, st, d_ens, d_obs, n_pgroups, src_t,
-                       src_to, use_outer, scale, results, d_ring);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const ObsDesc& O = *obs;
+    const int n_r = O.n_r;
+    if (i >= n_ens * n_r * n_pgroups * kProdQ) return;
+    const int q = i % kProdQ;
+    const int p = (i / kProdQ) % n_pgroups;
+    const int ir = (i / (kProdQ * n_pgroups)) % n_r;
+    const int e = i / (kProdQ * n_pgroups * n_r);
+    const EnsDesc& E = ens[e];
+    const int nc = O.n_comp;
+    if (q < 2 && p != 0) return;
+    if (q >= 2 && (O.n_probe == 0 || q - 2 >= 4 * nc)) return;
+    const int b0 = bstart[e] + (ir * n_pgroups + p) * E.prod_nch;
+    dd a{0.0, 0.0};
+    for (int c = 0; c < E.prod_nch; ++c) {
+        const double* src = part + ((size_t)(b0 + c) * kProdQ + q) * 2;
+        a = dd_add(a, dd{src[0], src[1]});
+    }
+    double* out = results + ((size_t)(*ring) * n_ens + e) * O.n_doubles_per_config;
+    const double nC = 1.0 / ((double)E.nsig * O.n_dirs);
+    if (q < 2) {
+        out[2 * ir + q] = (a.hi + a.lo) * nC;
+    } else {
+        const int k = (q - 2) >> 1, im = (q - 2) & 1;
+        const long long idx = (((long long)ir * O.n_probe + p) * nc) * 2 + k;
+        out[2ll * n_r + 2 * idx + im] = (a.hi + a.lo) * (nC / (double)E.nt);
+    }
+}
+
+hipError_t launch_product(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+                          const ObsDesc* d_obs, int n_r, int n_pgroups, const double2* src_t, const double2* src_to,
+                          int use_outer, double scale, double* part, double* results, const int* d_ring,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_product, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, n_pgroups,
+                       src_t, src_to, use_outer, scale, part);
+    const int nq = n_ens * n_r * n_pgroups * kProdQ;
+    hipLaunchKernelGGL(k_product_final, dim3((nq + 63) / 64), dim3(64), 0, st, d_ens, d_bstart, n_ens, d_obs, n_pgroups,
+                       part, results, d_ring);
     return hipGetLastError();
 }
 
-// vacuum <O_sq>, <O_lin> per orientation: the sum of every block partial of
-// every measurement of the configuration (double-double, fixed order), divided
-// by (measurements * V).  Block (e, k) reduces quantity k of ensemble e.
+// vacuum <O_sq>, <O_lin> per orientation: the running block partials of the
+// configuration summed in a fixed-order double-double tree, divided by
+// (measurements * V).  Block (e, k) reduces quantity k of ensemble e.
 __global__ void __launch_bounds__(256) k_vac_final(const EnsDesc* __restrict__ ens, int n_ens,
                                                    const ObsDesc* __restrict__ obs, const double* __restrict__ vac_part,
                                                    int n_meas, double* __restrict__ results,
@@ -597,9 +735,11 @@ __global__ void __launch_bounds__(256) k_vac_final(const EnsDesc* __restrict__ e
 {
     const int e = blockIdx.x / 12, k = blockIdx.x % 12;
     const EnsDesc& E = ens[e];
-    const long long n = (long long)n_meas * E.n_vac_blocks;
     dd a{0.0, 0.0};
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) a = dd_add(a, vac_part[E.vac_part_off + i * 12 + k]);
+    for (int i = threadIdx.x; i < E.n_vac_blocks; i += blockDim.x) {
+        const double* p = vac_part + E.vac_part_off + (size_t)i * 24 + 2 * k;
+        a = dd_add(a, dd{p[0], p[1]});
+    }
     __shared__ double shh[256], shl[256];
     shh[threadIdx.x] = a.hi;
     shl[threadIdx.x] = a.lo;

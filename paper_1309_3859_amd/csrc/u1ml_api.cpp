@@ -36,7 +36,7 @@ struct Layout {
     size_t sz_links, sz_hc, sz_ho, sz_at, sz_ato, sz_ot, sz_oto, sz_res, sz_scr;
     // scratch sub-offsets (bytes from off_scr)
     size_t s_ens, s_obs, s_r, s_probe, s_comp, s_bstart, s_upd, s_ring, s_vpart, s_ppart, s_pout, s_count,
-        s_stage, s_bmap, s_mmap;
+        s_stage, s_bmap, s_mmap, s_prodpart;
     size_t bmap_stride;  // entries per update class (blocks of 64 threads)
     int n_bstart_tables;
 };
@@ -46,7 +46,8 @@ constexpr int kTabAll = 4;    // all links (init, health)
 constexpr int kTabMeas = 5;   // spatial sites
 constexpr int kTabCon = 6;    // contraction items
 constexpr int kTabComb = 7;   // combine items
-constexpr int kNumTabs = 8;
+constexpr int kTabProd = 8;   // slab-product work-groups
+constexpr int kNumTabs = 9;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
 struct Problem {
@@ -162,7 +163,7 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
     const size_t word = P.precision == U1ML_FP64 ? 8 : 4;
     const bool store_o = !P.probes.empty();
     const size_t R = P.r.size(), Np = P.probes.size(), Nc = P.comps.size(), nd = (size_t)P.n_dirs;
-    size_t L = 0, HC = 0, HO = 0, AT = 0, ATO = 0, OT = 0, OTO = 0, VAC = 0;
+    size_t L = 0, HC = 0, HO = 0, AT = 0, ATO = 0, OT = 0, OTO = 0, VAC = 0, PP = 0;
     size_t maxV = 0, paper = 0, upd_cfg = 0, upd_sweep = 0, blocks64 = 0, mblocks = 0;
     S->links.clear();
     S->hc.clear();
@@ -209,8 +210,10 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
             }
         }
         S->vac.push_back(VAC);
-        // vacuum partials of every measurement of a configuration
-        VAC += (size_t)P.n_o * P.n_i * ((nsig * si + 255) / 256) * 12;
+        // running double-double vacuum partials, one set of 12 per measurement block
+        VAC += ((nsig * si + 255) / 256) * 24;
+        // slab-product partials: per (r, probe group, site chunk) work-group
+        PP += R * std::max<size_t>(Np, 1) * ((nd * nsig + kProdChunk - 1) / kProdChunk) * kProdQ * 2;
         mblocks += (nsig * si + 255) / 256;
         // the paper's running accumulators: 2 doubles per site and per point of
         // the transverse plane, per slab of the inner level (Sec. II.D)
@@ -260,6 +263,7 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
     Lo->bmap_stride = blocks64;
     Lo->s_bmap = take(sizeof(int2) * kUpdateClasses * blocks64);
     Lo->s_mmap = take(sizeof(int2) * mblocks);
+    Lo->s_prodpart = take(sizeof(double) * PP);
     Lo->sz_scr = s;
     size_t off = 0;
     Lo->off_links = off;
@@ -320,7 +324,10 @@ struct u1ml_ctx {
     int2* d_bmap = nullptr;
     int2* d_mmap = nullptr;
     int upd_grid[kUpdateClasses] = {0, 0, 0, 0};  // grid size of each update class (multiple of 8)
-    int max_s_in = 1;                              // largest number of inner slabs in the batch  // measurement launch: block -> (ensemble, local block)
+    int max_s_in = 1;                              // largest number of inner slabs in the batch
+    int con_block = 64;                            // contraction work-group size
+    size_t con_lds = 0;                            // contraction dynamic LDS per work-group
+    double* prodpart = nullptr;                    // slab-product partials
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
     // host mirrors
@@ -464,8 +471,9 @@ hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
                                    c->vpart, m, ko * P.n_i + m, P.tau_i, store_o, st);
         }
         if (e == hipSuccess)
-            e = launch_contract(c->d_ens, c->tab_dev(kTabCon), n, c->tab_total(kTabCon), c->d_obs, c->d_r, c->d_probe,
-                                c->d_comp, c->hc, c->ho, c->at, c->ato, P.n_i, P.precision, c->max_s_in, P.n_dirs, st);
+            e = launch_contract(c->d_ens, c->tab_dev(kTabCon), n, c->tab_total(kTabCon), c->con_block, c->con_lds,
+                                c->d_obs, c->d_r, c->d_probe, c->d_comp, c->hc, store_o ? c->ho : nullptr, c->at, c->ato, P.n_i,
+                                P.precision, c->max_s_in, P.n_dirs, st);
         if (e == hipSuccess && P.two)
             e = launch_combine(c->d_ens, c->tab_dev(kTabComb), n, c->tab_total(kTabComb), c->d_obs, c->at, c->ato,
                                c->ot, c->oto, P.tau_o / P.tau_i, st);
@@ -473,11 +481,11 @@ hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
     const int npg = std::max<int>(1, (int)P.probes.size());
     if (e == hipSuccess) {
         if (P.two)
-            e = launch_product(c->d_ens, n, c->d_obs, (int)P.r.size(), npg, c->ot, c->oto, 1, 1.0 / P.n_o, c->res,
-                               c->d_ring, st);
+            e = launch_product(c->d_ens, c->tab_dev(kTabProd), n, c->tab_total(kTabProd), c->d_obs, (int)P.r.size(),
+                               npg, c->ot, c->oto, 1, 1.0 / P.n_o, c->prodpart, c->res, c->d_ring, st);
         else
-            e = launch_product(c->d_ens, n, c->d_obs, (int)P.r.size(), npg, c->at, c->ato, 0, 1.0, c->res, c->d_ring,
-                               st);
+            e = launch_product(c->d_ens, c->tab_dev(kTabProd), n, c->tab_total(kTabProd), c->d_obs, (int)P.r.size(),
+                               npg, c->at, c->ato, 0, 1.0, c->prodpart, c->res, c->d_ring, st);
     }
     if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, c->d_ring, st);
     if (e == hipSuccess) e = launch_ring_advance(c->d_ring, st);
@@ -651,6 +659,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     c->stage = (double*)(s + Lo.s_stage);
     c->d_bmap = (int2*)(s + Lo.s_bmap);
     c->d_mmap = (int2*)(s + Lo.s_mmap);
+    c->prodpart = (double*)(s + Lo.s_prodpart);
 
     const Problem& P = c->P;
     const int n = P.n_ens;
@@ -704,19 +713,47 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     // tables
     c->h_bstart.assign((size_t)kNumTabs * (n + 1), 0);
     build_update_tabs(c);
-    std::vector<long long> all(n), meas(n), con(n), comb(n);
+    std::vector<long long> all(n), meas(n), con(n), comb(n), prod(n);
+    // Contraction shape: a line of N sites along a charge axis has N * n_r
+    // pairs (x, r), one thread each; a work-group of con_block threads holds
+    // con_lpb such lines, and stages con_mc measurements at a time in LDS.
+    const size_t R = P.r.size();
+    const size_t o_word = P.probes.empty() ? 0 : (P.precision == U1ML_FP64 ? 8 : 4);
+    std::vector<int> group(n);
+    c->con_block = 256;
     for (int e = 0; e < n; ++e) {
         const EnsDesc& E = c->h_ens[e];
+        const int n3[3] = {E.nx, E.ny, E.nz};
+        int maxpairs = 0;
+        for (int i = 0; i < P.n_dirs; ++i) maxpairs = std::max(maxpairs, n3[P.dirs[i]] * (int)R);
+        group[e] = std::min(512, (maxpairs + 63) / 64 * 64);  // the kernel is built for <= 512 threads
+        c->con_block = std::max(c->con_block, group[e]);
+    }
+    c->con_lds = 0;
+    for (int e = 0; e < n; ++e) {
+        EnsDesc& E = c->h_ens[e];
+        const int n3[3] = {E.nx, E.ny, E.nz};
+        const size_t nmax = (size_t)std::max(E.nx, std::max(E.ny, E.nz));
+        const size_t per = 16 + 12 * o_word;  // LDS bytes per (measurement, line site)
+        E.con_lpb = c->con_block / group[e];
+        const size_t fit = (size_t)kConLds / ((size_t)E.con_lpb * nmax * per);
+        E.con_mc = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)P.n_i));
+        c->con_lds = std::max(c->con_lds, (size_t)E.con_lpb * E.con_mc * nmax * per);
+        int lines = 0;
+        for (int i = 0; i < P.n_dirs; ++i) lines = std::max(lines, E.nsig / n3[P.dirs[i]]);
+        con[e] = (lines + E.con_lpb - 1) / E.con_lpb;
+        E.prod_nch = (P.n_dirs * E.nsig + kProdChunk - 1) / kProdChunk;
+        prod[e] = (long long)R * std::max<size_t>(P.probes.size(), 1) * E.prod_nch;
         all[e] = 8ll * E.vh;
         meas[e] = (long long)E.nsig * E.s_in;
-        con[e] = (long long)P.r.size() * ((E.nsig + 63) / 64) * 64;  // per (slab, axis): grid y and z
         c->max_s_in = std::max(c->max_s_in, E.s_in);
         comb[e] = (long long)P.n_dirs * P.r.size() * E.s_out * E.nsig;
     }
     build_tab(c, kTabAll, all, 256);
     build_tab(c, kTabMeas, meas, 256);
-    build_tab(c, kTabCon, con, 256);
+    build_tab(c, kTabCon, con, 1);
     build_tab(c, kTabComb, comb, 256);
+    build_tab(c, kTabProd, prod, 1);
     std::vector<uint32_t> zeros(n, 0u);
     int ring0[4] = {0, 0, 0, 0};
     u1ml_status st = U1ML_OK;

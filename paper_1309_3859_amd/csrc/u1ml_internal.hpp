@@ -12,15 +12,17 @@ namespace u1ml {
 struct EnsDesc {
     int nx, ny, nz, nt;
     int nxh, nsig, vh, s_in;  // s_in: slabs of the innermost level
-    int s_out, n_vac_blocks, pad0, pad1;
-    float inv_nxh, inv_ny, inv_slice, pad2;  // 1/(Nx/2), 1/Ny, 1/((Nx/2) Ny Nz) for division-free decode
+    int s_out, n_vac_blocks;
+    int con_lpb, con_mc;  // contraction: lines per work-group, measurements per LDS chunk
+    int prod_nch, pad0, pad1, pad2;  // slab products: site chunks per (r, probe)
+    float inv_nxh, inv_ny, inv_slice, pad3;  // 1/(Nx/2), 1/Ny, 1/((Nx/2) Ny Nz) for division-free decode
     double beta, sqrt_beta;
     uint32_t seed, key_id;
     long long link_off;
     long long hc_off, ho_off;
     long long at_off, ato_off;
     long long ot_off, oto_off;
-    long long vac_part_off;  // double, [measurements of a configuration][n_vac_blocks][12]
+    long long vac_part_off;  // double, [n_vac_blocks][12][hi, lo]: running sums over the configuration's measurements
 };
 
 // Observable tables in device memory.
@@ -33,6 +35,9 @@ struct ObsDesc {
 };
 
 constexpr int kUpdateClasses = 4;  // temporal, spatial full, spatial inner tau, spatial outer tau
+constexpr int kProdChunk = 2048;    // slab products: (axis, site) items per work-group
+constexpr int kProdQ = 26;          // slab products: correlator re, im and 12 insertion quantities re, im
+constexpr int kConLds = 32768;      // contraction: LDS budget per work-group (bytes)
 
 // --- launchers (k_update.hip) ---
 hipError_t launch_init_links(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
@@ -61,16 +66,19 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int precision, const void* links,
                           double2* hist_c, void* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
                           hipStream_t st);
-hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
-                           const int* d_r, const int* d_probe, const int* d_comp, const double2* hist_c,
-                           const void* hist_o, double2* avg_t, double2* avg_to, int n_meas, int precision,
-                           int max_slabs, int n_dirs, hipStream_t st);
+// work-groups of `block` threads, each holding E.con_lpb lines; lds_bytes of dynamic LDS
+hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
+                           size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_probe,
+                           const int* d_comp, const double2* hist_c, const void* hist_o, double2* avg_t,
+                           double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st);
 hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                           const double2* avg_t, const double2* avg_to, double2* out_t, double2* out_to, int q,
                           hipStream_t st);
-hipError_t launch_product(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, int n_r, int n_pgroups,
-                          const double2* src_t, const double2* src_to, int use_outer, double scale, double* results,
-                          const int* d_ring, hipStream_t st);
+// d_bstart: per ensemble n_r * n_pgroups * E.prod_nch work-groups; part: 52 doubles per work-group
+hipError_t launch_product(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+                          const ObsDesc* d_obs, int n_r, int n_pgroups, const double2* src_t, const double2* src_to,
+                          int use_outer, double scale, double* part, double* results, const int* d_ring,
+                          hipStream_t st);
 hipError_t launch_vac_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, const double* vac_part,
                             int n_meas, double* results, const int* d_ring, hipStream_t st);
 hipError_t launch_ring_advance(int* d_ring, hipStream_t st);
