@@ -56,6 +56,21 @@ enum { U1ML_FP64 = 0, U1ML_FP32 = 1 };         /* link storage / update arithmet
 enum { U1ML_COLD = 0, U1ML_HOT = 1 };          /* start of u1ml_init_links         */
 enum { U1ML_HEATBATH = 0, U1ML_OVERRELAX = 1 }; /* update kind of u1ml_phase        */
 
+/* How the insertion estimators are contracted (Sec. II.C.3 defines what is
+ * computed; both forms give the same estimator up to FP64 rounding):
+ *   HISTORY:  per-site slab averages [TO](x) of every probe, formed from the
+ *             stored measurements of the inner level; memory grows with the
+ *             number of probes.
+ *   SPECTRAL: the sum over sites of weight x T x O for every transverse
+ *             displacement at once, by 2D discrete Fourier transforms over
+ *             the plane orthogonal to the charge axis; with two levels the
+ *             weights need the whole configuration's outer averages, so each
+ *             configuration runs twice from the same start (the second pass
+ *             replays the first bit for bit).  Memory does not grow with the
+ *             number of probes.
+ *   AUTO:     HISTORY unless its averages would exceed 16 GiB. */
+enum { U1ML_FORM_AUTO = 0, U1ML_FORM_HISTORY = 1, U1ML_FORM_SPECTRAL = 2 };
+
 /* One ensemble: Ns^3 x Nt lattice (Sec. II), coupling beta = 1/g^2 and its
  * Philox key.  Every extent must be even and >= 2 (checkerboard across the
  * periodic wrap). */
@@ -98,7 +113,9 @@ typedef struct {
  *   levels: outer first; with two levels the outer tau must be a multiple of
  *          the inner tau, and Nt a multiple of the outer tau.
  *   dirs:   charge axes (0, 1, 2) summed over in the estimators (Sec. II.C.3).
- *   max_configs: capacity of the device results ring (configurations). */
+ *   max_configs: capacity of the device results ring (configurations).
+ *   form:   U1ML_FORM_* (SPECTRAL needs every transverse plane of a charge
+ *           axis to fit 64 KiB of complex doubles, i.e. at most 4096 sites). */
 typedef struct {
     int n_ens;
     const u1ml_ensemble* ens;
@@ -115,6 +132,7 @@ typedef struct {
     int n_comp;
     const int* comps;
     int max_configs;
+    int form;
 } u1ml_problem;
 
 /* Planner output (bytes of each workspace section, 256-byte aligned). */
@@ -135,6 +153,10 @@ typedef struct {
     long updates_per_config;  /* non-frozen link updates of one multilevel
                                  configuration, all ensembles               */
     long updates_per_sweep;   /* link updates of one full-lattice sweep      */
+    int form;                 /* the contraction form chosen (U1ML_FORM_HISTORY
+                                 or U1ML_FORM_SPECTRAL)                       */
+    size_t spectral_bytes;    /* weights, plane spectra, spectral sums and the
+                                 replay copy of the links (SPECTRAL only)    */
 } u1ml_plan_info;
 
 typedef struct u1ml_ctx u1ml_ctx;

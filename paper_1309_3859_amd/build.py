@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libu1ml.so")
-SOURCES = ["k_update.hip", "k_measure.hip", "u1ml_api.cpp"]
+SOURCES = ["k_update.hip", "k_measure.hip", "k_spectral.hip", "u1ml_api.cpp"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

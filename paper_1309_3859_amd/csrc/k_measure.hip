@@ -530,6 +530,7 @@ __global__ void __launch_bounds__(256) k_combine(const EnsDesc* __restrict__ ens
         if (j < q) T4 = cmul(T4, A[j]);
     double2* ot = out_t + E.ot_off + ((size_t)idr * So + S) * nsig + xs;
     *ot = make_double2(ot->x + T4.x, ot->y + T4.y);
+    if (!avg_to) return;  // spectral form: no per-site insertion averages
     const long long n_to = (long long)O.n_probe * O.n_comp * 2;
     for (long long k = 0; k < n_to; ++k) {
         const size_t row = (size_t)idr * n_to + k;
@@ -582,12 +583,13 @@ __global__ void __launch_bounds__(256) k_product(const EnsDesc* __restrict__ ens
     const int ch = local % E.prod_nch;
     const int p = (local / E.prod_nch) % n_pgroups;
     const int ir = local / (E.prod_nch * n_pgroups);
+    if (ir >= n_r) return;  // the work-group table holds n_r * n_pgroups * prod_nch per ensemble (uniform)
     const int nsig = E.nsig;
     const int S = use_outer ? E.s_out : E.s_in;
     const long long t_off = use_outer ? E.ot_off : E.at_off;
     const long long to_off = use_outer ? E.oto_off : E.ato_off;
     const int nc = O.n_comp;
-    const bool has_probe = O.n_probe > 0;
+    const bool has_probe = O.n_probe > 0 && src_to != nullptr;  // null: insertions come from the spectral form
     dd cre{0, 0}, cim{0, 0};
     dd ore[12], oim[12];
 #pragma unroll
@@ -681,7 +683,7 @@ __global__ void __launch_bounds__(256) k_product(const EnsDesc* __restrict__ ens
 __global__ void __launch_bounds__(64) k_product_final(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
                                                       int n_ens, const ObsDesc* __restrict__ obs, int n_pgroups,
                                                       const double* __restrict__ part, double* __restrict__ results,
-                                                      const int* __restrict__ ring)
+                                                      const int* __restrict__ ring, int with_ins)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const ObsDesc& O = *obs;
@@ -694,7 +696,7 @@ __global__ void __launch_bounds__(64) k_product_final(const EnsDesc* __restrict_
     const EnsDesc& E = ens[e];
     const int nc = O.n_comp;
     if (q < 2 && p != 0) return;
-    if (q >= 2 && (O.n_probe == 0 || q - 2 >= 4 * nc)) return;
+    if (q >= 2 && (!with_ins || O.n_probe == 0 || q - 2 >= 4 * nc)) return;
     const int b0 = bstart[e] + (ir * n_pgroups + p) * E.prod_nch;
     dd a{0.0, 0.0};
     for (int c = 0; c < E.prod_nch; ++c) {
@@ -721,7 +723,7 @@ hipError_t launch_product(const EnsDesc* d_ens, const int* d_bstart, int n_ens, 
                        src_t, src_to, use_outer, scale, part);
     const int nq = n_ens * n_r * n_pgroups * kProdQ;
     hipLaunchKernelGGL(k_product_final, dim3((nq + 63) / 64), dim3(64), 0, st, d_ens, d_bstart, n_ens, d_obs, n_pgroups,
-                       part, results, d_ring);
+                       part, results, d_ring, src_to != nullptr ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -27,16 +27,20 @@ bool mul_ok(size_t a, size_t b, size_t* out) { return !__builtin_mul_overflow(a,
 bool add_ok(size_t a, size_t b, size_t* out) { return !__builtin_add_overflow(a, b, out); }
 
 struct Sizes {
-    // per ensemble element counts
+    // per ensemble element offsets
     std::vector<size_t> links, hc, ho, at, ato, ot, oto, vac;
+    std::vector<size_t> wf, gf, sph, spo, facc;  // spectral form (double2 elements)
 };
 
 struct Layout {
     size_t off_links, off_hc, off_ho, off_at, off_ato, off_ot, off_oto, off_res, off_scr;
     size_t sz_links, sz_hc, sz_ho, sz_at, sz_ato, sz_ot, sz_oto, sz_res, sz_scr;
+    // spectral form: weights W, G; plane spectra of T and O; spectral sums; replay copy of the links
+    size_t off_wf, off_gf, off_sph, off_spo, off_facc, off_saved;
+    size_t sz_wf, sz_gf, sz_sph, sz_spo, sz_facc, sz_saved;
     // scratch sub-offsets (bytes from off_scr)
     size_t s_ens, s_obs, s_r, s_probe, s_comp, s_bstart, s_upd, s_ring, s_vpart, s_ppart, s_pout, s_count,
-        s_stage, s_bmap, s_mmap, s_prodpart;
+        s_stage, s_bmap, s_mmap, s_prodpart, s_pgroup, s_gdesc;
     size_t bmap_stride;  // entries per update class (blocks of 64 threads)
     int n_bstart_tables;
 };
@@ -47,7 +51,10 @@ constexpr int kTabMeas = 5;   // spatial sites
 constexpr int kTabCon = 6;    // contraction items
 constexpr int kTabComb = 7;   // combine items
 constexpr int kTabProd = 8;   // slab-product work-groups
-constexpr int kNumTabs = 9;
+constexpr int kTabSite = 9;   // spectral weights: (axis, r, site) items
+constexpr int kTabPlane = 10; // spectral plane transforms: work-groups
+constexpr int kTabMac = 11;   // spectral sums: items
+constexpr int kNumTabs = 12;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
 struct Problem {
@@ -61,9 +68,13 @@ struct Problem {
     std::vector<u1ml_probe> probes;
     std::vector<int> comps;
     int max_configs = 1;
+    int form_req = U1ML_FORM_AUTO;
     // derived
     int tau_i = 2, n_i = 1, k_i = 1, tau_o = 2, n_o = 1, k_o = 0;
     bool two = false;
+    bool spectral = false;        // insertion contraction in the spectral form
+    std::vector<int> pgroup;      // probe -> group of probes sharing (l, mode)
+    std::vector<int> gdesc;       // group -> (l, mode)
     long long nd_cfg = 0;
 };
 
@@ -155,14 +166,61 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
         }
     }
     P->nd_cfg = 2ll * P->r.size() + 4ll * P->r.size() * P->probes.size() * P->comps.size() + 12;
+    if (p->form < U1ML_FORM_AUTO || p->form > U1ML_FORM_SPECTRAL) return fail(err, "form must be 0, 1 or 2");
+    P->form_req = p->form;
+    if (p->form == U1ML_FORM_SPECTRAL)
+        for (const u1ml_ensemble& E : P->ens)
+            for (int i = 0; i < P->n_dirs; ++i)
+                if ((long long)E.ns[0] * E.ns[1] * E.ns[2] / E.ns[P->dirs[i]] > 4096)
+                    return fail(err, "spectral form: a transverse plane has more than 4096 sites");
+    // probes sharing (l, mode) share one longitudinal offset per (r, component)
+    P->pgroup.clear();
+    P->gdesc.clear();
+    for (const u1ml_probe& pr : P->probes) {
+        int g = 0;
+        while (g < (int)P->gdesc.size() / 2 && !(P->gdesc[2 * g] == pr.l && P->gdesc[2 * g + 1] == pr.mode)) ++g;
+        if (g == (int)P->gdesc.size() / 2) {
+            P->gdesc.push_back(pr.l);
+            P->gdesc.push_back(pr.mode);
+        }
+        P->pgroup.push_back(g);
+    }
     return true;
 }
 
-bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::string* err)
+// probe groups of the slab-product launch: every probe in the history form,
+// one (the correlator only) otherwise; the work-group table, the partial
+// buffer and the launch all use this count
+int prod_groups(const Problem& P) { return (!P.spectral && !P.probes.empty()) ? (int)P.probes.size() : 1; }
+
+bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::string* err)
 {
     const size_t word = P.precision == U1ML_FP64 ? 8 : 4;
     const bool store_o = !P.probes.empty();
     const size_t R = P.r.size(), Np = P.probes.size(), Nc = P.comps.size(), nd = (size_t)P.n_dirs;
+    const size_t NG = P.gdesc.size() / 2;
+    // contraction form: the spectral form needs every transverse plane of a
+    // charge axis within 4096 sites; AUTO takes it when the per-site
+    // averages of the history form would exceed 16 GiB
+    {
+        bool plane_ok = true;
+        double hist_avg = 0.0;
+        for (const u1ml_ensemble& E : P.ens) {
+            const double nsig = (double)E.ns[0] * E.ns[1] * E.ns[2];
+            for (int i = 0; i < P.n_dirs; ++i)
+                if (nsig / E.ns[P.dirs[i]] > 4096.0) plane_ok = false;
+            const double per = (double)nd * R * Np * Nc * 2 * nsig * 16.0;
+            hist_avg += per * (E.nt / P.tau_i) + (P.two ? per * (E.nt / P.tau_o) : 0.0);
+        }
+        if (P.form_req == U1ML_FORM_SPECTRAL) {
+            P.spectral = !P.probes.empty();  // planes checked by read_problem
+        } else if (P.form_req == U1ML_FORM_AUTO) {
+            P.spectral = !P.probes.empty() && plane_ok && hist_avg > 16.0 * 1024 * 1024 * 1024;
+        } else {
+            P.spectral = false;
+        }
+    }
+    const bool spec = P.spectral;
     size_t L = 0, HC = 0, HO = 0, AT = 0, ATO = 0, OT = 0, OTO = 0, VAC = 0, PP = 0;
     size_t maxV = 0, paper = 0, upd_cfg = 0, upd_sweep = 0, blocks64 = 0, mblocks = 0;
     S->links.clear();
@@ -173,6 +231,12 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
     S->ot.clear();
     S->oto.clear();
     S->vac.clear();
+    S->wf.clear();
+    S->gf.clear();
+    S->sph.clear();
+    S->spo.clear();
+    S->facc.clear();
+    size_t WF = 0, GF = 0, SPH = 0, SPO = 0, FACC = 0;
     for (const u1ml_ensemble& E : P.ens) {
         const size_t nsig = (size_t)E.ns[0] * E.ns[1] * E.ns[2];
         const size_t V = nsig * E.nt;
@@ -196,7 +260,7 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
         S->at.push_back(AT);
         AT = align_up((AT + nd * R * si * nsig) * 16) / 16;
         S->ato.push_back(ATO);
-        if (store_o) {
+        if (store_o && !spec) {
             if (!mul_ok(nd * R * Np * Nc * 2 * si, nsig, &t) || !add_ok(ATO, t, &ATO)) return fail(err, "size overflow (averages)");
             ATO = align_up(ATO * 16) / 16;
         }
@@ -204,16 +268,32 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
         S->oto.push_back(OTO);
         if (P.two) {
             OT = align_up((OT + nd * R * so * nsig) * 16) / 16;
-            if (store_o) {
+            if (store_o && !spec) {
                 if (!mul_ok(nd * R * Np * Nc * 2 * so, nsig, &t) || !add_ok(OTO, t, &OTO)) return fail(err, "size overflow (outer)");
                 OTO = align_up(OTO * 16) / 16;
             }
+        }
+        S->wf.push_back(WF);
+        S->gf.push_back(GF);
+        S->sph.push_back(SPH);
+        S->spo.push_back(SPO);
+        S->facc.push_back(FACC);
+        if (spec) {
+            size_t n12max = 0;
+            for (int i = 0; i < P.n_dirs; ++i) n12max = std::max(n12max, nsig / (size_t)E.ns[P.dirs[i]]);
+            if (P.two) WF = align_up((WF + nd * R * so * nsig) * 16) / 16;
+            GF = align_up((GF + nd * R * si * nsig) * 16) / 16;
+            SPH = align_up((SPH + nd * si * R * nsig) * 16) / 16;
+            SPO = align_up((SPO + nd * si * 12 * nsig) * 16) / 16;
+            if (!mul_ok(nd * si * R * Nc * 2 * NG, n12max, &t) || !add_ok(FACC, t, &FACC))
+                return fail(err, "size overflow (spectral sums)");
+            FACC = align_up(FACC * 16) / 16;
         }
         S->vac.push_back(VAC);
         // running double-double vacuum partials, one set of 12 per measurement block
         VAC += ((nsig * si + 255) / 256) * 24;
         // slab-product partials: per (r, probe group, site chunk) work-group
-        PP += R * std::max<size_t>(Np, 1) * ((nd * nsig + kProdChunk - 1) / kProdChunk) * kProdQ * 2;
+        PP += R * (size_t)prod_groups(P) * ((nd * nsig + kProdChunk - 1) / kProdChunk) * kProdQ * 2;
         mblocks += (nsig * si + 255) / 256;
         // the paper's running accumulators: 2 doubles per site and per point of
         // the transverse plane, per slab of the inner level (Sec. II.D)
@@ -235,6 +315,12 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
     Lo->sz_ato = align_up(ATO * 16);
     Lo->sz_ot = align_up(OT * 16);
     Lo->sz_oto = align_up(OTO * 16);
+    Lo->sz_wf = align_up(WF * 16);
+    Lo->sz_gf = align_up(GF * 16);
+    Lo->sz_sph = align_up(SPH * 16);
+    Lo->sz_spo = align_up(SPO * 16);
+    Lo->sz_facc = align_up(FACC * 16);
+    Lo->sz_saved = (spec && P.two) ? Lo->sz_links : 0;
     size_t res;
     if (!mul_ok((size_t)P.max_configs * P.n_ens, (size_t)P.nd_cfg * 8, &res)) return fail(err, "size overflow (results)");
     Lo->sz_res = align_up(res);
@@ -264,6 +350,8 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
     Lo->s_bmap = take(sizeof(int2) * kUpdateClasses * blocks64);
     Lo->s_mmap = take(sizeof(int2) * mblocks);
     Lo->s_prodpart = take(sizeof(double) * PP);
+    Lo->s_pgroup = take(sizeof(int) * std::max<size_t>(Np, 1));
+    Lo->s_gdesc = take(sizeof(int) * std::max<size_t>(2 * NG, 2));
     Lo->sz_scr = s;
     size_t off = 0;
     Lo->off_links = off;
@@ -282,6 +370,18 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
     off += Lo->sz_oto;
     Lo->off_res = off;
     off += Lo->sz_res;
+    Lo->off_wf = off;
+    off += Lo->sz_wf;
+    Lo->off_gf = off;
+    off += Lo->sz_gf;
+    Lo->off_sph = off;
+    off += Lo->sz_sph;
+    Lo->off_spo = off;
+    off += Lo->sz_spo;
+    Lo->off_facc = off;
+    off += Lo->sz_facc;
+    Lo->off_saved = off;
+    off += Lo->sz_saved;
     Lo->off_scr = off;
     off += Lo->sz_scr;
     if (info) {
@@ -297,6 +397,8 @@ bool compute_sizes(const Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo,
         info->n_doubles_per_config = P.nd_cfg;
         info->updates_per_config = (long)upd_cfg;
         info->updates_per_sweep = (long)upd_sweep;
+        info->form = spec ? U1ML_FORM_SPECTRAL : U1ML_FORM_HISTORY;
+        info->spectral_bytes = Lo->sz_wf + Lo->sz_gf + Lo->sz_sph + Lo->sz_spo + Lo->sz_facc + Lo->sz_saved;
     }
     return true;
 }
@@ -328,6 +430,12 @@ struct u1ml_ctx {
     int con_block = 64;                            // contraction work-group size
     size_t con_lds = 0;                            // contraction dynamic LDS per work-group
     double* prodpart = nullptr;                    // slab-product partials
+    double2 *wf = nullptr, *gf = nullptr, *sph = nullptr, *spo = nullptr, *facc = nullptr;  // spectral form
+    void* saved = nullptr;                         // replay copy of the links
+    int spec_npm = 0;                              // largest lattice extent (spectral launches)
+    long long spec_n12max = 0;                     // largest transverse plane (sites)
+    int spec_tile = 4;                             // plane-transform tile (4, or 2 if an extent is not a multiple of 4)
+    int *d_pgroup = nullptr, *d_gdesc = nullptr;
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
     // host mirrors
@@ -449,16 +557,20 @@ hipError_t enq_sweep(u1ml_ctx* c, hipStream_t st, int tau, int hb)
     return e;
 }
 
-// Body of Algorithm 1 for one outer configuration.
-hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
+// The n_o outer iterations of Algorithm 1 (one iteration for one level).
+//   store_o:  measurements keep the slab sums of O
+//   ins_hist: history form: per-site insertion averages, combined per level
+//   spec_acc: spectral form: after each inner level, weights G_k and the
+//             plane transforms of every stored measurement into the sums
+// *hb returns the number of heatbath counter offsets used.
+hipError_t enq_levels(u1ml_ctx* c, hipStream_t st, bool store_o, bool ins_hist, bool spec_acc, int* hb_out)
 {
     const Problem& P = c->P;
     const int n = P.n_ens;
-    const int store_o = P.probes.empty() ? 0 : 1;
     hipError_t e = hipSuccess;
-    if (P.two) {
+    if (P.two && !spec_acc) {
         e = launch_fill_zero(c->ot, c->Lo.sz_ot, st);
-        if (e == hipSuccess && c->Lo.sz_oto) e = launch_fill_zero(c->oto, c->Lo.sz_oto, st);
+        if (e == hipSuccess && ins_hist && c->Lo.sz_oto) e = launch_fill_zero(c->oto, c->Lo.sz_oto, st);
     }
     int hb = 0;
     for (int ko = 0; e == hipSuccess && ko < P.n_o; ++ko) {
@@ -468,26 +580,89 @@ hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
             for (int k = 0; e == hipSuccess && k < P.k_i; ++k) e = enq_sweep(c, st, P.tau_i, hb++);
             if (e == hipSuccess)
                 e = launch_measure(c->d_ens, c->d_mmap, c->tab_total(kTabMeas), P.precision, c->links, c->hc, c->ho,
-                                   c->vpart, m, ko * P.n_i + m, P.tau_i, store_o, st);
+                                   c->vpart, m, ko * P.n_i + m, P.tau_i, store_o ? 1 : 0, st);
         }
         if (e == hipSuccess)
             e = launch_contract(c->d_ens, c->tab_dev(kTabCon), n, c->tab_total(kTabCon), c->con_block, c->con_lds,
-                                c->d_obs, c->d_r, c->d_probe, c->d_comp, c->hc, store_o ? c->ho : nullptr, c->at, c->ato, P.n_i,
-                                P.precision, c->max_s_in, P.n_dirs, st);
-        if (e == hipSuccess && P.two)
-            e = launch_combine(c->d_ens, c->tab_dev(kTabComb), n, c->tab_total(kTabComb), c->d_obs, c->at, c->ato,
-                               c->ot, c->oto, P.tau_o / P.tau_i, st);
+                                c->d_obs, c->d_r, c->d_probe, c->d_comp, c->hc, ins_hist ? c->ho : nullptr, c->at,
+                                c->ato, P.n_i, P.precision, c->max_s_in, P.n_dirs, st);
+        if (e == hipSuccess && P.two && !spec_acc)
+            e = launch_combine(c->d_ens, c->tab_dev(kTabComb), n, c->tab_total(kTabComb), c->d_obs, c->at,
+                               ins_hist ? c->ato : nullptr, c->ot, ins_hist ? c->oto : nullptr, P.tau_o / P.tau_i, st);
+        if (spec_acc) {
+            if (e == hipSuccess)
+                e = launch_gfac(c->d_ens, c->tab_dev(kTabSite), n, c->tab_total(kTabSite), c->d_obs, c->at,
+                                P.two ? c->wf : nullptr, P.two ? P.tau_o / P.tau_i : 0, c->gf, st);
+            const size_t lds = (2 * (size_t)c->spec_n12max + 2 * (size_t)c->spec_npm) * sizeof(double2);
+            for (int m = 0; e == hipSuccess && m < P.n_i; ++m) {
+                e = launch_dft_planes(c->d_ens, c->tab_dev(kTabPlane), n, c->tab_total(kTabPlane), lds, c->d_obs,
+                                      c->d_r, c->hc, c->ho, c->gf, c->sph, c->spo, m, P.precision, c->spec_tile,
+                                      st);
+                if (e == hipSuccess)
+                    e = launch_spec_mac(c->d_ens, c->tab_dev(kTabMac), n, c->tab_total(kTabMac), c->d_obs, c->d_r,
+                                        c->d_comp, c->d_gdesc, c->sph, c->spo, c->facc, st);
+            }
+        }
     }
-    const int npg = std::max<int>(1, (int)P.probes.size());
-    if (e == hipSuccess) {
+    *hb_out = hb;
+    return e;
+}
+
+// Body of Algorithm 1 for one configuration.
+//  history form: one pass; per-site averages of every probe, then products.
+//  spectral form, one level: one pass; after the level the weights
+//    W_s = prod_{s' != s} [T] are known and the stored measurements are
+//    transformed into the spectral sums.
+//  spectral form, two levels: pass 1 computes the correlator, the vacuum
+//    sums and the outer averages A (no insertions); the links are restored
+//    to the configuration's start and pass 2 repeats the same updates with
+//    the same counters (so the same trajectory, bit for bit), forming the
+//    spectral sums with G_k = W_S prod [T]_k after every inner level.
+hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
+{
+    const Problem& P = c->P;
+    const int n = P.n_ens;
+    const bool probes = !P.probes.empty();
+    const int npg = prod_groups(P);
+    const int R = (int)P.r.size();
+    hipError_t e = hipSuccess;
+    int hb = 0;
+    auto product = [&](bool ins) {  // ins only in the history form, where npg = number of probes
         if (P.two)
-            e = launch_product(c->d_ens, c->tab_dev(kTabProd), n, c->tab_total(kTabProd), c->d_obs, (int)P.r.size(),
-                               npg, c->ot, c->oto, 1, 1.0 / P.n_o, c->prodpart, c->res, c->d_ring, st);
-        else
-            e = launch_product(c->d_ens, c->tab_dev(kTabProd), n, c->tab_total(kTabProd), c->d_obs, (int)P.r.size(),
-                               npg, c->at, c->ato, 0, 1.0, c->prodpart, c->res, c->d_ring, st);
+            return launch_product(c->d_ens, c->tab_dev(kTabProd), n, c->tab_total(kTabProd), c->d_obs, R, npg, c->ot,
+                                  ins ? c->oto : nullptr, 1, 1.0 / P.n_o, c->prodpart, c->res, c->d_ring, st);
+        return launch_product(c->d_ens, c->tab_dev(kTabProd), n, c->tab_total(kTabProd), c->d_obs, R, npg, c->at,
+                              ins ? c->ato : nullptr, 0, 1.0, c->prodpart, c->res, c->d_ring, st);
+    };
+    const long long n_out = (long long)R * P.probes.size() * P.comps.size() * 2;
+    if (!P.spectral) {
+        e = enq_levels(c, st, probes, probes, false, &hb);
+        if (e == hipSuccess) e = product(probes);
+        if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, c->d_ring, st);
+    } else if (!P.two) {
+        e = launch_fill_zero(c->facc, c->Lo.sz_facc, st);
+        if (e == hipSuccess) e = enq_levels(c, st, true, false, true, &hb);
+        if (e == hipSuccess) e = product(false);
+        if (e == hipSuccess)
+            e = launch_spec_final(c->d_ens, n, c->d_obs, n_out, c->spec_npm, c->d_probe, c->d_pgroup, c->facc,
+                                  (double)P.n_i, c->res, c->d_ring, st);
+        if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vpart, P.n_i, c->res, c->d_ring, st);
+    } else {
+        e = launch_copy(c->links, c->saved, c->Lo.sz_links, st);
+        if (e == hipSuccess) e = enq_levels(c, st, false, false, false, &hb);
+        if (e == hipSuccess) e = product(false);
+        if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, c->d_ring, st);
+        if (e == hipSuccess)
+            e = launch_wfac(c->d_ens, c->tab_dev(kTabSite), n, c->tab_total(kTabSite), c->d_obs, c->ot, 1.0 / P.n_o,
+                            c->wf, st);
+        if (e == hipSuccess) e = launch_copy(c->saved, c->links, c->Lo.sz_links, st);
+        if (e == hipSuccess) e = launch_fill_zero(c->facc, c->Lo.sz_facc, st);
+        int hb2 = 0;
+        if (e == hipSuccess) e = enq_levels(c, st, true, false, true, &hb2);
+        if (e == hipSuccess)
+            e = launch_spec_final(c->d_ens, n, c->d_obs, n_out, c->spec_npm, c->d_probe, c->d_pgroup, c->facc,
+                                  (double)P.n_o * P.n_i, c->res, c->d_ring, st);
     }
-    if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, c->d_ring, st);
     if (e == hipSuccess) e = launch_ring_advance(c->d_ring, st);
     if (e == hipSuccess && hb > 0) e = launch_advance_counters(c->d_upd, n, hb, st);
     return e;
@@ -660,6 +835,14 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     c->d_bmap = (int2*)(s + Lo.s_bmap);
     c->d_mmap = (int2*)(s + Lo.s_mmap);
     c->prodpart = (double*)(s + Lo.s_prodpart);
+    c->d_pgroup = (int*)(s + Lo.s_pgroup);
+    c->d_gdesc = (int*)(s + Lo.s_gdesc);
+    c->wf = (double2*)(w + Lo.off_wf);
+    c->gf = (double2*)(w + Lo.off_gf);
+    c->sph = (double2*)(w + Lo.off_sph);
+    c->spo = (double2*)(w + Lo.off_spo);
+    c->facc = (double2*)(w + Lo.off_facc);
+    c->saved = (void*)(w + Lo.off_saved);
 
     const Problem& P = c->P;
     const int n = P.n_ens;
@@ -693,6 +876,11 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         E.ot_off = (long long)c->S.ot[e];
         E.oto_off = (long long)c->S.oto[e];
         E.vac_part_off = (long long)c->S.vac[e];
+        E.wf_off = (long long)c->S.wf[e];
+        E.gf_off = (long long)c->S.gf[e];
+        E.sph_off = (long long)c->S.sph[e];
+        E.spo_off = (long long)c->S.spo[e];
+        E.facc_off = (long long)c->S.facc[e];
     }
     ObsDesc O;
     std::memset(&O, 0, sizeof O);
@@ -702,6 +890,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     O.n_probe = (int)P.probes.size();
     O.n_comp = (int)P.comps.size();
     O.store_o = P.probes.empty() ? 0 : 1;
+    O.n_groups = (int)(P.gdesc.size() / 2);
     O.n_doubles_per_config = P.nd_cfg;
     std::vector<int> probe_flat;
     for (const u1ml_probe& p : P.probes) {
@@ -743,7 +932,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         for (int i = 0; i < P.n_dirs; ++i) lines = std::max(lines, E.nsig / n3[P.dirs[i]]);
         con[e] = (lines + E.con_lpb - 1) / E.con_lpb;
         E.prod_nch = (P.n_dirs * E.nsig + kProdChunk - 1) / kProdChunk;
-        prod[e] = (long long)R * std::max<size_t>(P.probes.size(), 1) * E.prod_nch;
+        prod[e] = (long long)R * prod_groups(P) * E.prod_nch;
         all[e] = 8ll * E.vh;
         meas[e] = (long long)E.nsig * E.s_in;
         c->max_s_in = std::max(c->max_s_in, E.s_in);
@@ -754,6 +943,42 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     build_tab(c, kTabCon, con, 1);
     build_tab(c, kTabComb, comb, 256);
     build_tab(c, kTabProd, prod, 1);
+    {
+        std::vector<long long> site(n), plane(n), mac(n);
+        const size_t NG = P.gdesc.size() / 2;
+        for (int e = 0; e < n; ++e) {
+            const EnsDesc& E = c->h_ens[e];
+            const int n3[3] = {E.nx, E.ny, E.nz};
+            const long long npm = std::max(E.nx, std::max(E.ny, E.nz));
+            long long n12max = 0;
+            for (int i = 0; i < P.n_dirs; ++i) n12max = std::max<long long>(n12max, E.nsig / n3[P.dirs[i]]);
+            site[e] = (long long)P.n_dirs * P.r.size() * E.nsig;
+            plane[e] = P.spectral ? (long long)P.n_dirs * E.s_in * ((long long)P.r.size() + 12) * npm : 0;
+            mac[e] = P.spectral ? (long long)P.n_dirs * E.s_in * P.r.size() * P.comps.size() * 2 * NG * n12max : 0;
+            c->spec_npm = std::max<int>(c->spec_npm, (int)npm);
+            for (int i = 0; i < P.n_dirs; ++i)
+                for (int k = 1; k < 3; ++k)
+                    if (n3[(P.dirs[i] + k) % 3] % 4 != 0) c->spec_tile = 2;
+            c->spec_n12max = std::max<long long>(c->spec_n12max, n12max);
+        }
+        build_tab(c, kTabSite, site, 256);
+        build_tab(c, kTabPlane, plane, 1);
+        build_tab(c, kTabMac, mac, 256);
+    }
+    {
+        // every dynamic LDS request must fit the device's limit per work-group
+        int lds_max = 0;
+        hipError_t ea = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+        const size_t plane_lds = P.spectral ? (2 * (size_t)c->spec_n12max + 2 * (size_t)c->spec_npm) * sizeof(double2) : 0;
+        const size_t need = std::max(c->con_lds, plane_lds);
+        if (ea != hipSuccess || (size_t)lds_max < need) {
+            (void)hipStreamDestroy(c->cap);
+            delete c;
+            return set_err(nullptr, ea != hipSuccess ? U1ML_EDEVICE : U1ML_ENOTSUP,
+                           "work-group LDS of " + std::to_string(need) + " bytes exceeds the device limit of " +
+                               std::to_string(lds_max));
+        }
+    }
     std::vector<uint32_t> zeros(n, 0u);
     int ring0[4] = {0, 0, 0, 0};
     u1ml_status st = U1ML_OK;
@@ -767,6 +992,8 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     up(c->d_r, P.r.data(), sizeof(int) * P.r.size());
     up(c->d_probe, probe_flat.data(), sizeof(int) * probe_flat.size());
     up(c->d_comp, P.comps.data(), sizeof(int) * P.comps.size());
+    up(c->d_pgroup, P.pgroup.data(), sizeof(int) * P.pgroup.size());
+    up(c->d_gdesc, P.gdesc.data(), sizeof(int) * P.gdesc.size());
     up(c->d_bstart, c->h_bstart.data(), sizeof(int) * c->h_bstart.size());
     up(c->d_bmap, c->h_bmap.data(), sizeof(int2) * c->h_bmap.size());
     std::vector<int2> mmap;

@@ -23,6 +23,8 @@ struct EnsDesc {
     long long at_off, ato_off;
     long long ot_off, oto_off;
     long long vac_part_off;  // double, [n_vac_blocks][12][hi, lo]: running sums over the configuration's measurements
+    // spectral form (double2 offsets)
+    long long wf_off, gf_off, sph_off, spo_off, facc_off;
 };
 
 // Observable tables in device memory.
@@ -31,6 +33,7 @@ struct ObsDesc {
     int dirs[3];
     int n_r, n_probe, n_comp;
     int store_o;  // 1 if insertions are requested (history keeps O sums)
+    int n_groups;  // probe groups sharing (l, mode) (spectral form)
     long long n_doubles_per_config;
 };
 
@@ -82,5 +85,22 @@ hipError_t launch_product(const EnsDesc* d_ens, const int* d_bstart, int n_ens, 
 hipError_t launch_vac_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, const double* vac_part,
                             int n_meas, double* results, const int* d_ring, hipStream_t st);
 hipError_t launch_ring_advance(int* d_ring, hipStream_t st);
+
+// --- spectral form (k_spectral.hip) ---
+hipError_t launch_wfac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
+                       const double2* out_t, double scale, double2* wf, hipStream_t st);
+hipError_t launch_gfac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
+                       const double2* avg_t, const double2* wf, int q, double2* gf, hipStream_t st);
+hipError_t launch_dft_planes(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, size_t lds_bytes,
+                             const ObsDesc* d_obs, const int* d_r, const double2* hist_c, const void* hist_o,
+                             const double2* gf, double2* sph, double2* spo, int m_in, int precision, int tile,
+                             hipStream_t st);
+hipError_t launch_spec_mac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+                           const ObsDesc* d_obs, const int* d_r, const int* d_comp, const int* d_gdesc,
+                           const double2* sph, const double2* spo, double2* facc, hipStream_t st);
+hipError_t launch_spec_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, long long n_outputs, int npm,
+                             const int* d_probe, const int* d_pgroup, const double2* facc, double n_meas_total,
+                             double* results, const int* d_ring, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 
 }  // namespace u1ml

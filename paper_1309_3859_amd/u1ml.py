@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libu1ml.so")
 FP64, FP32 = 0, 1
 COLD, HOT = 0, 1
 HEATBATH, OVERRELAX = 0, 1
+FORM_AUTO, FORM_HISTORY, FORM_SPECTRAL = 0, 1, 2
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENOTSUP"}
 
 
@@ -49,7 +50,7 @@ class _Problem(C.Structure):
         ("n_ens", C.c_int), ("ens", C.POINTER(_Ensemble)), ("precision", C.c_int), ("n_or", C.c_int),
         ("n_levels", C.c_int), ("levels", _Level * 2), ("n_dirs", C.c_int), ("dirs", C.c_int * 3),
         ("n_r", C.c_int), ("r", C.POINTER(C.c_int)), ("n_probe", C.c_int), ("probes", C.POINTER(_Probe)),
-        ("n_comp", C.c_int), ("comps", C.POINTER(C.c_int)), ("max_configs", C.c_int),
+        ("n_comp", C.c_int), ("comps", C.POINTER(C.c_int)), ("max_configs", C.c_int), ("form", C.c_int),
     ]
 
 
@@ -58,7 +59,8 @@ class _PlanInfo(C.Structure):
         ("ws_bytes", C.c_size_t), ("link_bytes", C.c_size_t), ("history_bytes", C.c_size_t),
         ("average_bytes", C.c_size_t), ("outer_bytes", C.c_size_t), ("result_bytes", C.c_size_t),
         ("scratch_bytes", C.c_size_t), ("paper_running_bytes", C.c_size_t), ("n_doubles_per_config", C.c_long),
-        ("updates_per_config", C.c_long), ("updates_per_sweep", C.c_long),
+        ("updates_per_config", C.c_long), ("updates_per_sweep", C.c_long), ("form", C.c_int),
+        ("spectral_bytes", C.c_size_t),
     ]
 
 
@@ -151,6 +153,7 @@ class Spec:
     precision: int = FP64
     n_or: int = 3
     max_configs: int = 1
+    form: int = 0  # FORM_AUTO
     _keep: list = field(default_factory=list, repr=False)
 
     def struct(self) -> _Problem:
@@ -177,6 +180,7 @@ class Spec:
         p.n_probe, p.probes = len(self.probes), pr
         p.n_comp, p.comps = len(self.comps), cp
         p.max_configs = self.max_configs
+        p.form = self.form
         return p
 
     def n_doubles_per_config(self) -> int:

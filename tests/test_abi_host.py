@@ -58,6 +58,9 @@ BAD = [
     ("bad axis", dict(dirs=[3])),
     ("repeated axis", dict(dirs=[0, 0])),
     ("probes without comps", dict(comps=[])),
+    ("bad form", dict(form=3)),
+    # a 66 x 66 plane orthogonal to the x axis holds more than 4096 sites
+    ("spectral plane too large", dict(ens=((2, 66, 66), 4, 1.0), r=[1], form=2)),
 ]
 
 
@@ -110,3 +113,30 @@ def test_workspace_too_small_is_rejected_before_any_device_call(u1):
     st = u1.lib().u1ml_create(C.byref(spec.struct()), C.c_void_p(256), 16, None, C.byref(h))
     assert st == 1 and not h.value
     assert b"workspace too small" in u1.lib().u1ml_last_error(None)
+
+
+def test_contraction_form_selection(u1):
+    """The planner keeps the per-site history form while its averages fit and
+    switches to the spectral form for the full transverse map of the largest
+    preset, whose per-site averages would need about a terabyte."""
+    from paper_1309_3859_amd import configs
+
+    s2, _ = configs.c2_fp32_profiles()
+    p2 = u1.plan(s2)
+    assert p2["form"] == u1.FORM_HISTORY and p2["spectral_bytes"] == 0
+    s5, _ = configs.c5_largest()
+    p5 = u1.plan(s5)
+    assert p5["form"] == u1.FORM_SPECTRAL
+    assert p5["average_bytes"] < 2**30 and p5["ws_bytes"] < 16 * 2**30
+    # the spectral sections: weights W (3 thick slabs) and G (6 thin slabs),
+    # plane spectra of the 19 T fields and 12 O rows, spectral sums of 19 r x 6
+    # components x 2 kinds x 1 probe group over 48 x 48 planes, one link copy
+    nsig, R = 48 ** 3, 19
+    want = 16 * (R * 3 * nsig + R * 6 * nsig + 6 * R * nsig + 6 * 12 * nsig + 6 * R * 6 * 2 * 48 * 48) \
+        + p5["link_bytes"]
+    assert abs(p5["spectral_bytes"] - want) <= 6 * 256
+    s5.form = u1.FORM_HISTORY
+    assert u1.plan(s5)["average_bytes"] > 10 ** 12
+    # forcing the spectral form on a small problem is allowed
+    s2.form = u1.FORM_SPECTRAL
+    assert u1.plan(s2)["form"] == u1.FORM_SPECTRAL
