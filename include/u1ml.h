@@ -157,6 +157,8 @@ typedef struct {
                                  or U1ML_FORM_SPECTRAL)                       */
     size_t spectral_bytes;    /* weights, plane spectra, spectral sums and the
                                  replay copy of the links (SPECTRAL only)    */
+    long launches_per_config; /* kernel launches of one u1ml_multilevel
+                                 (upper bound)                              */
 } u1ml_plan_info;
 
 typedef struct u1ml_ctx u1ml_ctx;
@@ -232,7 +234,9 @@ u1ml_status u1ml_autotune(u1ml_ctx* ctx, u1ml_tune_report* report);
 u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block);
 
 /* 1: capture sweeps and multilevel bodies into HIP graphs (default);
- * 0: launch every kernel directly. */
+ * 0: launch every kernel directly.  A multilevel body of more than 8192
+ * kernel launches (u1ml_plan_info.launches_per_config) is always launched
+ * directly. */
 u1ml_status u1ml_set_graphs(u1ml_ctx* ctx, int enable);
 
 /* Synchronises.  Average device time in microseconds of one launch of the

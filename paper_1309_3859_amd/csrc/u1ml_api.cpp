@@ -188,6 +188,22 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
     return true;
 }
 
+// Kernel launches of one multilevel body (upper bound).  Bodies above
+// kMaxGraphLaunches are launched directly instead of through one captured
+// graph: a single capture of a full configuration of the largest preset
+// (about 275,000 kernel nodes in one chain) ended the process with a
+// segmentation fault, so graphs stay at the sizes that are tested.
+constexpr long long kMaxGraphLaunches = 8192;
+
+long long body_launches(const Problem& P)
+{
+    const long long sweep = (1ll + P.n_or) * 8;
+    long long level = (long long)P.n_o * ((long long)P.k_o * sweep + (long long)P.n_i * (P.k_i * sweep + 1) + 4);
+    if (P.spectral) level += (long long)P.n_o * (1 + 2ll * P.n_i);
+    const long long passes = (P.spectral && P.two) ? 2 : 1;
+    return passes * level + 16;
+}
+
 // probe groups of the slab-product launch: every probe in the history form,
 // one (the correlator only) otherwise; the work-group table, the partial
 // buffer and the launch all use this count
@@ -399,6 +415,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
         info->updates_per_sweep = (long)upd_sweep;
         info->form = spec ? U1ML_FORM_SPECTRAL : U1ML_FORM_HISTORY;
         info->spectral_bytes = Lo->sz_wf + Lo->sz_gf + Lo->sz_sph + Lo->sz_spo + Lo->sz_facc + Lo->sz_saved;
+        info->launches_per_config = (long)body_launches(P);
     }
     return true;
 }
@@ -1071,7 +1088,7 @@ u1ml_status u1ml_multilevel(u1ml_ctx* ctx)
     if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
     if (ctx->ring_count >= ctx->P.max_configs)
         return set_err(ctx, U1ML_ESTATE, "results ring is full: call u1ml_copy_results");
-    if (ctx->use_graphs) {
+    if (ctx->use_graphs && body_launches(ctx->P) <= kMaxGraphLaunches) {
         if (!ctx->g_ml) {
             u1ml_status s = capture(ctx, [&](hipStream_t st) { return enq_multilevel(ctx, st); }, &ctx->g_ml);
             if (s != U1ML_OK) return s;

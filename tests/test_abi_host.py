@@ -140,3 +140,18 @@ def test_contraction_form_selection(u1):
     # forcing the spectral form on a small problem is allowed
     s2.form = u1.FORM_SPECTRAL
     assert u1.plan(s2)["form"] == u1.FORM_SPECTRAL
+
+
+def test_large_bodies_are_launched_directly(u1):
+    """Multilevel bodies above 8192 kernel launches are not captured into a
+    single graph (the planner reports the launch count); the headline batch
+    and the one-level presets stay captured."""
+    from paper_1309_3859_amd import configs
+
+    n = {k: u1.plan(configs.PRESETS[k]()[0])["launches_per_config"] for k in ("c1", "c2", "c3", "c4", "c5")}
+    # C4: 50 measurements x (1 sweep of 4 passes x 8 phases + 1 measurement) + contraction and products
+    assert 50 * 33 < n["c4"] <= 8192
+    assert n["c2"] <= 8192 and n["c1"] <= 8192
+    assert n["c3"] > 8192
+    # C5 (two levels, spectral, replayed): two passes of 40 x (32 + 100 x 33) launches
+    assert n["c5"] > 2 * 40 * (32 + 100 * 33)
