@@ -233,6 +233,16 @@ u1ml_status u1ml_autotune(u1ml_ctx* ctx, u1ml_tune_report* report);
 /* Sets the update kernels' work-group size (64, 128, 256, 512 or 1024). */
 u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block);
 
+/* Synchronises.  n_lanes = 2 (the default for two or more ensembles) runs
+ * u1ml_sweeps and u1ml_multilevel as two lanes of about equal volume on two
+ * streams at once (the context's stream and an internal one, joined back
+ * into the context's stream by events), so the arithmetic-bound heatbath
+ * phases of one lane overlap the memory-bound overrelaxation phases of the
+ * other; n_lanes = 1 runs the whole batch on the context's stream.  Every
+ * ensemble's links and estimates are bit-identical either way.  EINVAL for
+ * n_lanes other than 1 or 2, or 2 with a single ensemble. */
+u1ml_status u1ml_set_lanes(u1ml_ctx* ctx, int n_lanes);
+
 /* 1: capture sweeps and multilevel bodies into HIP graphs (default);
  * 0: launch every kernel directly.  A multilevel body of more than 8192
  * kernel launches (u1ml_plan_info.launches_per_config) is always launched

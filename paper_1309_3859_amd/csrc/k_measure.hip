@@ -703,7 +703,7 @@ __global__ void __launch_bounds__(64) k_product_final(const EnsDesc* __restrict_
         const double* src = part + ((size_t)(b0 + c) * kProdQ + q) * 2;
         a = dd_add(a, dd{src[0], src[1]});
     }
-    double* out = results + ((size_t)(*ring) * n_ens + e) * O.n_doubles_per_config;
+    double* out = results + ((size_t)(*ring) * O.n_ens_total + E.res_index) * O.n_doubles_per_config;
     const double nC = 1.0 / ((double)E.nsig * O.n_dirs);
     if (q < 2) {
         out[2 * ir + q] = (a.hi + a.lo) * nC;
@@ -757,7 +757,7 @@ __global__ void __launch_bounds__(256) k_vac_final(const EnsDesc* __restrict__ e
     if (threadIdx.x == 0) {
         const ObsDesc& O = *obs;
         const long long base_v = 2ll * O.n_r + 4ll * O.n_r * O.n_probe * O.n_comp;
-        double* out = results + ((size_t)(*ring) * n_ens + e) * O.n_doubles_per_config;
+        double* out = results + ((size_t)(*ring) * O.n_ens_total + E.res_index) * O.n_doubles_per_config;
         // accumulator order is (o, kind); output order is sq[6] then lin[6]
         const int o = k >> 1, kind = k & 1;
         out[base_v + kind * 6 + o] = (shh[0] + shl[0]) / ((double)n_meas * 2.0 * (double)E.vh);

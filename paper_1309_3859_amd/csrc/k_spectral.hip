@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(64) k_spec_final(const EnsDesc* __restrict__ e
     }
     if (!valid) return;
     const double scale = 1.0 / ((double)nsig * O.n_dirs * E.nt * n_meas_total);
-    double* out = results + ((size_t)(*ring) * n_ens + e) * O.n_doubles_per_config;
+    double* out = results + ((size_t)(*ring) * O.n_ens_total + E.res_index) * O.n_doubles_per_config;
     const long long idx = (((long long)ir * Np + p) * Nc + ic) * 2 + kind;
     out[2ll * R + 2 * idx] = (are.hi + are.lo) * scale;
     out[2ll * R + 2 * idx + 1] = (aim.hi + aim.lo) * scale;

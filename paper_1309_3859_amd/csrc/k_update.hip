@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
             const real R = M<real>::sqrt_(ar * ar + ai * ai);
             const real kappa = (real)E.beta * R;
             const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
-            const uint32_t ctr = upd[e] + (uint32_t)pass_offset;
+            const uint32_t ctr = upd[E.res_index] + (uint32_t)pass_offset;
             if constexpr (kQueue) {
                 // theta = psi - arg A as one angle: exp(i theta) is proportional to
                 // exp(i psi) conj(A), so a single atan2 replaces arccos, atan2 and wrap
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
             queue[pos] = RetryQ{q_kappa, q_ar, q_ai, q_lid, q_off};
         }
         __syncthreads();
-        const uint32_t ctr = upd[e] + (uint32_t)pass_offset;
+        const uint32_t ctr = upd[E.res_index] + (uint32_t)pass_offset;
         for (int i = threadIdx.x; i < total; i += blockDim.x) {
             const RetryQ r = queue[i];
             const float rm1 = bf_rm1_f32(r.kappa);
@@ -537,15 +537,16 @@ hipError_t launch_vonmises_fill(double kappa, int precision, uint32_t seed, uint
     return hipGetLastError();
 }
 
-__global__ void k_advance(uint32_t* __restrict__ upd, int n_ens, int delta)
+// advances the counters of the n_ens ensembles described by ens[]
+__global__ void k_advance(const EnsDesc* __restrict__ ens, uint32_t* __restrict__ upd, int n_ens, int delta)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n_ens) upd[e] += (uint32_t)delta;
+    if (e < n_ens) upd[ens[e].res_index] += (uint32_t)delta;
 }
 
-hipError_t launch_advance_counters(uint32_t* d_upd, int n_ens, int delta, hipStream_t st)
+hipError_t launch_advance_counters(const EnsDesc* d_ens, uint32_t* d_upd, int n_ens, int delta, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_advance, dim3((n_ens + 63) / 64), dim3(64), 0, st, d_upd, n_ens, delta);
+    hipLaunchKernelGGL(k_advance, dim3((n_ens + 63) / 64), dim3(64), 0, st, d_ens, d_upd, n_ens, delta);
     return hipGetLastError();
 }
 

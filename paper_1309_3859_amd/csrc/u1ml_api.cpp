@@ -41,6 +41,8 @@ struct Layout {
     // scratch sub-offsets (bytes from off_scr)
     size_t s_ens, s_obs, s_r, s_probe, s_comp, s_bstart, s_upd, s_ring, s_vpart, s_ppart, s_pout, s_count,
         s_stage, s_bmap, s_mmap, s_prodpart, s_pgroup, s_gdesc;
+    // the two lanes' descriptors and tables (each sized for the whole batch)
+    size_t s_lens[2], s_lbstart[2], s_lbmap[2], s_lmmap[2], s_lring[2];
     size_t bmap_stride;  // entries per update class (blocks of 64 threads)
     int n_bstart_tables;
 };
@@ -366,6 +368,13 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     Lo->s_bmap = take(sizeof(int2) * kUpdateClasses * blocks64);
     Lo->s_mmap = take(sizeof(int2) * mblocks);
     Lo->s_prodpart = take(sizeof(double) * PP);
+    for (int l = 0; l < 2; ++l) {
+        Lo->s_lens[l] = take(sizeof(EnsDesc) * n);
+        Lo->s_lbstart[l] = take(sizeof(int) * (n + 1) * kNumTabs);
+        Lo->s_lbmap[l] = take(sizeof(int2) * kUpdateClasses * blocks64);
+        Lo->s_lmmap[l] = take(sizeof(int2) * mblocks);
+        Lo->s_lring[l] = take(sizeof(int) * 4);
+    }
     Lo->s_pgroup = take(sizeof(int) * std::max<size_t>(Np, 1));
     Lo->s_gdesc = take(sizeof(int) * std::max<size_t>(2 * NG, 2));
     Lo->sz_scr = s;
@@ -422,6 +431,37 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
 
 }  // namespace
 
+// A lane: a subset of the problem's ensembles with its own descriptors,
+// launch tables, results-ring counter, stream and graphs.  The whole batch
+// is one lane (used by every call); a batch of two or more ensembles is also
+// split into two lanes of about equal volume that run sweeps and multilevel
+// configurations on two streams at once, so the heatbath phases (bound by
+// arithmetic) of one lane overlap the overrelaxation phases (bound by memory
+// latency) of the other.  Each ensemble's arithmetic is the same either way.
+struct Lane {
+    int n = 0;
+    std::vector<int> idx;        // problem indices of the lane's ensembles
+    std::vector<EnsDesc> h_ens;  // their descriptors, lane order
+    std::vector<int> h_bstart;   // kNumTabs x (n + 1)
+    std::vector<int2> h_bmap;    // kUpdateClasses x bmap_stride
+    std::vector<int2> h_mmap;    // measurement block -> (lane ensemble, block)
+    EnsDesc* d_ens = nullptr;
+    int* d_bstart = nullptr;
+    int2* d_bmap = nullptr;
+    int2* d_mmap = nullptr;
+    int* d_ring = nullptr;
+    double* prodpart = nullptr;
+    size_t bmap_stride = 0;
+    int upd_grid[kUpdateClasses] = {0, 0, 0, 0};  // grid size of each update class (multiple of 8)
+    int max_s_in = 1;                              // largest number of inner slabs in the lane
+    hipStream_t stream = nullptr;
+    hipGraphExec_t g_sweep = nullptr, g_ml = nullptr;
+
+    int tab_total(int tab) const { return h_bstart[(size_t)tab * (n + 1) + n]; }
+    const int* tab_dev(int tab) const { return d_bstart + (size_t)tab * (n + 1); }
+    const int2* bmap_dev(int cls) const { return d_bmap + (size_t)cls * bmap_stride; }
+};
+
 struct u1ml_ctx {
     Problem P;
     Sizes S;
@@ -430,6 +470,8 @@ struct u1ml_ctx {
     char* ws = nullptr;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
+    hipStream_t lane_stream = nullptr;  // second lane's stream
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
     // device pointers
     void* links = nullptr;
@@ -437,16 +479,10 @@ struct u1ml_ctx {
     void* ho = nullptr;
     double *res = nullptr, *vpart = nullptr, *ppart = nullptr, *pout = nullptr,
            *stage = nullptr;
-    EnsDesc* d_ens = nullptr;
     ObsDesc* d_obs = nullptr;
-    int *d_r = nullptr, *d_probe = nullptr, *d_comp = nullptr, *d_bstart = nullptr, *d_ring = nullptr;
-    int2* d_bmap = nullptr;
-    int2* d_mmap = nullptr;
-    int upd_grid[kUpdateClasses] = {0, 0, 0, 0};  // grid size of each update class (multiple of 8)
-    int max_s_in = 1;                              // largest number of inner slabs in the batch
+    int *d_r = nullptr, *d_probe = nullptr, *d_comp = nullptr;
     int con_block = 64;                            // contraction work-group size
     size_t con_lds = 0;                            // contraction dynamic LDS per work-group
-    double* prodpart = nullptr;                    // slab-product partials
     double2 *wf = nullptr, *gf = nullptr, *sph = nullptr, *spo = nullptr, *facc = nullptr;  // spectral form
     void* saved = nullptr;                         // replay copy of the links
     int spec_npm = 0;                              // largest lattice extent (spectral launches)
@@ -455,20 +491,15 @@ struct u1ml_ctx {
     int *d_pgroup = nullptr, *d_gdesc = nullptr;
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
-    // host mirrors
-    std::vector<EnsDesc> h_ens;
-    std::vector<int> h_bstart;  // kNumTabs x (n_ens + 1)
-    std::vector<int2> h_bmap;   // kUpdateClasses x bmap_stride: block -> (ensemble, local block)
+    std::vector<EnsDesc> h_ens;  // descriptors in problem order
+    Lane whole;                  // every ensemble
+    Lane split[2];               // two lanes (batches of two or more ensembles)
+    bool lanes = false;          // sweeps and configurations run on the two lanes
     int block = 256;
     bool initialised = false;
     int ring_count = 0;
     bool use_graphs = true;
-    hipGraphExec_t g_sweep = nullptr, g_ml = nullptr;
     std::string err;
-
-    int tab_total(int tab) const { return h_bstart[(size_t)tab * (P.n_ens + 1) + P.n_ens]; }
-    const int* tab_dev(int tab) const { return d_bstart + (size_t)tab * (P.n_ens + 1); }
-    const int2* bmap_dev(int cls) const { return d_bmap + (size_t)cls * Lo.bmap_stride; }
 };
 
 namespace {
@@ -489,50 +520,128 @@ u1ml_status set_err(u1ml_ctx* c, u1ml_status s, const std::string& m)
             return set_err((ctx), U1ML_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));          \
     } while (0)
 
-void build_tab(u1ml_ctx* c, int tab, const std::vector<long long>& items, int block)
+void build_tab(Lane& L, int tab, const std::vector<long long>& items, int block)
 {
-    const int n = c->P.n_ens;
-    int* b = &c->h_bstart[(size_t)tab * (n + 1)];
+    int* b = &L.h_bstart[(size_t)tab * (L.n + 1)];
     b[0] = 0;
-    for (int e = 0; e < n; ++e) b[e + 1] = b[e] + (int)((items[e] + block - 1) / block);
+    for (int e = 0; e < L.n; ++e) b[e + 1] = b[e] + (int)((items[e] + block - 1) / block);
 }
 
-void build_update_tabs(u1ml_ctx* c)
+void build_update_tabs(const u1ml_ctx* c, Lane& L)
 {
     const Problem& P = c->P;
-    const int n = P.n_ens;
+    const int n = L.n;
     std::vector<long long> it0(n), it1(n), it2(n), it3(n);
     for (int e = 0; e < n; ++e) {
-        const EnsDesc& E = c->h_ens[e];
+        const EnsDesc& E = L.h_ens[e];
         const long long slice = (long long)E.nxh * E.ny * E.nz;
         it0[e] = (long long)E.vh;
         it1[e] = (long long)E.vh;
         it2[e] = slice * (P.tau_i > 1 ? E.nt - E.nt / P.tau_i : E.nt);
         it3[e] = slice * (P.tau_o > 1 ? E.nt - E.nt / P.tau_o : E.nt);
     }
-    build_tab(c, kTabUpd + 0, it0, c->block);
-    build_tab(c, kTabUpd + 1, it1, c->block);
-    build_tab(c, kTabUpd + 2, it2, c->block);
-    build_tab(c, kTabUpd + 3, it3, c->block);
+    build_tab(L, kTabUpd + 0, it0, c->block);
+    build_tab(L, kTabUpd + 1, it1, c->block);
+    build_tab(L, kTabUpd + 2, it2, c->block);
+    build_tab(L, kTabUpd + 3, it3, c->block);
     // Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8),
     // and each XCD has its own L2.  Logical block L(b) = (b mod 8) per + b / 8
     // gives every XCD one contiguous stretch of the lattice, so neighbouring
     // rows shared by adjacent blocks are fetched into one L2 instead of
     // several.  Launches have 8 per blocks; entries past the end are idle.
-    c->h_bmap.assign((size_t)kUpdateClasses * c->Lo.bmap_stride, make_int2(-1, 0));
+    L.h_bmap.assign((size_t)kUpdateClasses * L.bmap_stride, make_int2(-1, 0));
     for (int cls = 0; cls < kUpdateClasses; ++cls) {
-        const int* b = &c->h_bstart[(size_t)(kTabUpd + cls) * (n + 1)];
+        const int* b = &L.h_bstart[(size_t)(kTabUpd + cls) * (n + 1)];
         const int total = b[n];
         const int per = (total + kXcds - 1) / kXcds;
         std::vector<int2> logical(total);
         for (int e = 0; e < n; ++e)
             for (int k = b[e]; k < b[e + 1]; ++k) logical[k] = make_int2(e, k - b[e]);
         for (int phys = 0; phys < per * kXcds; ++phys) {
-            const int L = (phys % kXcds) * per + phys / kXcds;
-            c->h_bmap[(size_t)cls * c->Lo.bmap_stride + phys] = L < total ? logical[L] : make_int2(-1, 0);
+            const int lg = (phys % kXcds) * per + phys / kXcds;
+            L.h_bmap[(size_t)cls * L.bmap_stride + phys] = lg < total ? logical[lg] : make_int2(-1, 0);
         }
-        c->upd_grid[cls] = per * kXcds;
+        L.upd_grid[cls] = per * kXcds;
     }
+}
+
+// Every launch table of a lane, from its ensembles' descriptors (whose
+// contraction and product fields are already set).
+void build_lane_tables(const u1ml_ctx* c, Lane& L)
+{
+    const Problem& P = c->P;
+    const int n = L.n;
+    L.h_bstart.assign((size_t)kNumTabs * (n + 1), 0);
+    build_update_tabs(c, L);
+    const size_t R = P.r.size(), NG = P.gdesc.size() / 2;
+    std::vector<long long> all(n), meas(n), con(n), comb(n), prod(n), site(n), plane(n), mac(n);
+    L.max_s_in = 1;
+    for (int e = 0; e < n; ++e) {
+        const EnsDesc& E = L.h_ens[e];
+        const int n3[3] = {E.nx, E.ny, E.nz};
+        int lines = 0;
+        long long n12max = 0;
+        for (int i = 0; i < P.n_dirs; ++i) {
+            lines = std::max(lines, E.nsig / n3[P.dirs[i]]);
+            n12max = std::max<long long>(n12max, E.nsig / n3[P.dirs[i]]);
+        }
+        const long long npm = std::max(E.nx, std::max(E.ny, E.nz));
+        all[e] = 8ll * E.vh;
+        meas[e] = (long long)E.nsig * E.s_in;
+        con[e] = (lines + E.con_lpb - 1) / E.con_lpb;
+        comb[e] = (long long)P.n_dirs * R * E.s_out * E.nsig;
+        prod[e] = (long long)R * prod_groups(P) * E.prod_nch;
+        site[e] = (long long)P.n_dirs * R * E.nsig;
+        plane[e] = P.spectral ? (long long)P.n_dirs * E.s_in * ((long long)R + 12) * npm : 0;
+        mac[e] = P.spectral ? (long long)P.n_dirs * E.s_in * R * P.comps.size() * 2 * NG * n12max : 0;
+        L.max_s_in = std::max(L.max_s_in, E.s_in);
+    }
+    build_tab(L, kTabAll, all, 256);
+    build_tab(L, kTabMeas, meas, 256);
+    build_tab(L, kTabCon, con, 1);
+    build_tab(L, kTabComb, comb, 256);
+    build_tab(L, kTabProd, prod, 1);
+    build_tab(L, kTabSite, site, 256);
+    build_tab(L, kTabPlane, plane, 1);
+    build_tab(L, kTabMac, mac, 256);
+    L.h_mmap.clear();
+    const int* b = &L.h_bstart[(size_t)kTabMeas * (n + 1)];
+    for (int e = 0; e < n; ++e)
+        for (int k = b[e]; k < b[e + 1]; ++k) L.h_mmap.push_back(make_int2(e, k - b[e]));
+}
+
+hipError_t upload_lane(const Lane& L)
+{
+    const int ring0[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpy(L.d_ens, L.h_ens.data(), sizeof(EnsDesc) * L.n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(L.d_bstart, L.h_bstart.data(), sizeof(int) * L.h_bstart.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(L.d_bmap, L.h_bmap.data(), sizeof(int2) * L.h_bmap.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !L.h_mmap.empty())
+        e = hipMemcpy(L.d_mmap, L.h_mmap.data(), sizeof(int2) * L.h_mmap.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(L.d_ring, ring0, sizeof ring0, hipMemcpyHostToDevice);
+    return e;
+}
+
+// Bytes [begin, end) of ensemble k's share of a section whose per-ensemble
+// element offsets are off[] (elements of `elem` bytes, `total` bytes in all).
+void ens_range(const std::vector<size_t>& off, int k, size_t elem, size_t total, size_t* begin, size_t* end)
+{
+    *begin = off[k] * elem;
+    *end = k + 1 < (int)off.size() ? off[k + 1] * elem : total;
+}
+
+// Fill with zeros the shares of the lane's ensembles (a whole-array fill
+// would race with the other lane).
+hipError_t zero_lane(const Lane& L, void* base, const std::vector<size_t>& off, size_t elem, size_t total,
+                     hipStream_t st)
+{
+    for (int e = 0; e < L.n; ++e) {
+        size_t b, en;
+        ens_range(off, L.idx[e], elem, total, &b, &en);
+        hipError_t r = launch_fill_zero((char*)base + b, en - b, st);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
 }
 
 int update_class(const u1ml_ctx* c, int mu, int tau, bool* ok)
@@ -546,31 +655,31 @@ int update_class(const u1ml_ctx* c, int mu, int tau, bool* ok)
     return -1;
 }
 
-hipError_t enq_phase(u1ml_ctx* c, hipStream_t st, int kind, int mu, int parity, int tau, int pass_offset,
-                     hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr)
+hipError_t enq_phase(u1ml_ctx* c, const Lane& L, hipStream_t st, int kind, int mu, int parity, int tau,
+                     int pass_offset, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr)
 {
     bool ok;
     const int cls = update_class(c, mu, tau, &ok);
     if (!ok) return hipErrorInvalidValue;
-    return launch_update(c->d_ens, c->bmap_dev(cls), c->upd_grid[cls], c->block, c->P.precision, c->links, c->d_upd,
+    return launch_update(L.d_ens, L.bmap_dev(cls), L.upd_grid[cls], c->block, c->P.precision, c->links, c->d_upd,
                          pass_offset, kind, mu, parity, (mu < 3 && tau > 1) ? tau : 0, st, ev_start, ev_stop);
 }
 
-hipError_t enq_pass(u1ml_ctx* c, hipStream_t st, int kind, int tau, int pass_offset)
+hipError_t enq_pass(u1ml_ctx* c, const Lane& L, hipStream_t st, int kind, int tau, int pass_offset)
 {
     for (int mu = 0; mu < 4; ++mu)
         for (int p = 0; p < 2; ++p) {
-            hipError_t e = enq_phase(c, st, kind, mu, p, tau, pass_offset);
+            hipError_t e = enq_phase(c, L, st, kind, mu, p, tau, pass_offset);
             if (e != hipSuccess) return e;
         }
     return hipSuccess;
 }
 
 // one sweep: heatbath pass with counter offset hb, then n_or overrelaxation passes
-hipError_t enq_sweep(u1ml_ctx* c, hipStream_t st, int tau, int hb)
+hipError_t enq_sweep(u1ml_ctx* c, const Lane& L, hipStream_t st, int tau, int hb)
 {
-    hipError_t e = enq_pass(c, st, U1ML_HEATBATH, tau, hb);
-    for (int k = 0; e == hipSuccess && k < c->P.n_or; ++k) e = enq_pass(c, st, U1ML_OVERRELAX, tau, hb);
+    hipError_t e = enq_pass(c, L, st, U1ML_HEATBATH, tau, hb);
+    for (int k = 0; e == hipSuccess && k < c->P.n_or; ++k) e = enq_pass(c, L, st, U1ML_OVERRELAX, tau, hb);
     return e;
 }
 
@@ -580,43 +689,44 @@ hipError_t enq_sweep(u1ml_ctx* c, hipStream_t st, int tau, int hb)
 //   spec_acc: spectral form: after each inner level, weights G_k and the
 //             plane transforms of every stored measurement into the sums
 // *hb returns the number of heatbath counter offsets used.
-hipError_t enq_levels(u1ml_ctx* c, hipStream_t st, bool store_o, bool ins_hist, bool spec_acc, int* hb_out)
+hipError_t enq_levels(u1ml_ctx* c, const Lane& L, hipStream_t st, bool store_o, bool ins_hist, bool spec_acc,
+                      int* hb_out)
 {
     const Problem& P = c->P;
-    const int n = P.n_ens;
+    const int n = L.n;
     hipError_t e = hipSuccess;
     if (P.two && !spec_acc) {
-        e = launch_fill_zero(c->ot, c->Lo.sz_ot, st);
-        if (e == hipSuccess && ins_hist && c->Lo.sz_oto) e = launch_fill_zero(c->oto, c->Lo.sz_oto, st);
+        e = zero_lane(L, c->ot, c->S.ot, 16, c->Lo.sz_ot, st);
+        if (e == hipSuccess && ins_hist) e = zero_lane(L, c->oto, c->S.oto, 16, c->Lo.sz_oto, st);
     }
     int hb = 0;
     for (int ko = 0; e == hipSuccess && ko < P.n_o; ++ko) {
         if (P.two)
-            for (int k = 0; e == hipSuccess && k < P.k_o; ++k) e = enq_sweep(c, st, P.tau_o, hb++);
+            for (int k = 0; e == hipSuccess && k < P.k_o; ++k) e = enq_sweep(c, L, st, P.tau_o, hb++);
         for (int m = 0; e == hipSuccess && m < P.n_i; ++m) {
-            for (int k = 0; e == hipSuccess && k < P.k_i; ++k) e = enq_sweep(c, st, P.tau_i, hb++);
+            for (int k = 0; e == hipSuccess && k < P.k_i; ++k) e = enq_sweep(c, L, st, P.tau_i, hb++);
             if (e == hipSuccess)
-                e = launch_measure(c->d_ens, c->d_mmap, c->tab_total(kTabMeas), P.precision, c->links, c->hc, c->ho,
+                e = launch_measure(L.d_ens, L.d_mmap, L.tab_total(kTabMeas), P.precision, c->links, c->hc, c->ho,
                                    c->vpart, m, ko * P.n_i + m, P.tau_i, store_o ? 1 : 0, st);
         }
         if (e == hipSuccess)
-            e = launch_contract(c->d_ens, c->tab_dev(kTabCon), n, c->tab_total(kTabCon), c->con_block, c->con_lds,
+            e = launch_contract(L.d_ens, L.tab_dev(kTabCon), n, L.tab_total(kTabCon), c->con_block, c->con_lds,
                                 c->d_obs, c->d_r, c->d_probe, c->d_comp, c->hc, ins_hist ? c->ho : nullptr, c->at,
-                                c->ato, P.n_i, P.precision, c->max_s_in, P.n_dirs, st);
+                                c->ato, P.n_i, P.precision, L.max_s_in, P.n_dirs, st);
         if (e == hipSuccess && P.two && !spec_acc)
-            e = launch_combine(c->d_ens, c->tab_dev(kTabComb), n, c->tab_total(kTabComb), c->d_obs, c->at,
+            e = launch_combine(L.d_ens, L.tab_dev(kTabComb), n, L.tab_total(kTabComb), c->d_obs, c->at,
                                ins_hist ? c->ato : nullptr, c->ot, ins_hist ? c->oto : nullptr, P.tau_o / P.tau_i, st);
         if (spec_acc) {
             if (e == hipSuccess)
-                e = launch_gfac(c->d_ens, c->tab_dev(kTabSite), n, c->tab_total(kTabSite), c->d_obs, c->at,
+                e = launch_gfac(L.d_ens, L.tab_dev(kTabSite), n, L.tab_total(kTabSite), c->d_obs, c->at,
                                 P.two ? c->wf : nullptr, P.two ? P.tau_o / P.tau_i : 0, c->gf, st);
             const size_t lds = (2 * (size_t)c->spec_n12max + 2 * (size_t)c->spec_npm) * sizeof(double2);
             for (int m = 0; e == hipSuccess && m < P.n_i; ++m) {
-                e = launch_dft_planes(c->d_ens, c->tab_dev(kTabPlane), n, c->tab_total(kTabPlane), lds, c->d_obs,
+                e = launch_dft_planes(L.d_ens, L.tab_dev(kTabPlane), n, L.tab_total(kTabPlane), lds, c->d_obs,
                                       c->d_r, c->hc, c->ho, c->gf, c->sph, c->spo, m, P.precision, c->spec_tile,
                                       st);
                 if (e == hipSuccess)
-                    e = launch_spec_mac(c->d_ens, c->tab_dev(kTabMac), n, c->tab_total(kTabMac), c->d_obs, c->d_r,
+                    e = launch_spec_mac(L.d_ens, L.tab_dev(kTabMac), n, L.tab_total(kTabMac), c->d_obs, c->d_r,
                                         c->d_comp, c->d_gdesc, c->sph, c->spo, c->facc, st);
             }
         }
@@ -625,7 +735,20 @@ hipError_t enq_levels(u1ml_ctx* c, hipStream_t st, bool store_o, bool ins_hist, 
     return e;
 }
 
-// Body of Algorithm 1 for one configuration.
+// copies the links of the lane's ensembles (replay of two-level spectral configurations)
+hipError_t copy_lane_links(u1ml_ctx* c, const Lane& L, const void* src, void* dst, hipStream_t st)
+{
+    const size_t word = c->P.precision == U1ML_FP64 ? 8 : 4;
+    for (int e = 0; e < L.n; ++e) {
+        size_t b, en;
+        ens_range(c->S.links, L.idx[e], word, c->Lo.sz_links, &b, &en);
+        hipError_t r = launch_copy((const char*)src + b, (char*)dst + b, en - b, st);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
+// Body of Algorithm 1 for one configuration of the lane's ensembles.
 //  history form: one pass; per-site averages of every probe, then products.
 //  spectral form, one level: one pass; after the level the weights
 //    W_s = prod_{s' != s} [T] are known and the stored measurements are
@@ -635,10 +758,10 @@ hipError_t enq_levels(u1ml_ctx* c, hipStream_t st, bool store_o, bool ins_hist, 
 //    to the configuration's start and pass 2 repeats the same updates with
 //    the same counters (so the same trajectory, bit for bit), forming the
 //    spectral sums with G_k = W_S prod [T]_k after every inner level.
-hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
+hipError_t enq_multilevel(u1ml_ctx* c, const Lane& L, hipStream_t st)
 {
     const Problem& P = c->P;
-    const int n = P.n_ens;
+    const int n = L.n;
     const bool probes = !P.probes.empty();
     const int npg = prod_groups(P);
     const int R = (int)P.r.size();
@@ -646,57 +769,85 @@ hipError_t enq_multilevel(u1ml_ctx* c, hipStream_t st)
     int hb = 0;
     auto product = [&](bool ins) {  // ins only in the history form, where npg = number of probes
         if (P.two)
-            return launch_product(c->d_ens, c->tab_dev(kTabProd), n, c->tab_total(kTabProd), c->d_obs, R, npg, c->ot,
-                                  ins ? c->oto : nullptr, 1, 1.0 / P.n_o, c->prodpart, c->res, c->d_ring, st);
-        return launch_product(c->d_ens, c->tab_dev(kTabProd), n, c->tab_total(kTabProd), c->d_obs, R, npg, c->at,
-                              ins ? c->ato : nullptr, 0, 1.0, c->prodpart, c->res, c->d_ring, st);
+            return launch_product(L.d_ens, L.tab_dev(kTabProd), n, L.tab_total(kTabProd), c->d_obs, R, npg, c->ot,
+                                  ins ? c->oto : nullptr, 1, 1.0 / P.n_o, L.prodpart, c->res, L.d_ring, st);
+        return launch_product(L.d_ens, L.tab_dev(kTabProd), n, L.tab_total(kTabProd), c->d_obs, R, npg, c->at,
+                              ins ? c->ato : nullptr, 0, 1.0, L.prodpart, c->res, L.d_ring, st);
     };
     const long long n_out = (long long)R * P.probes.size() * P.comps.size() * 2;
     if (!P.spectral) {
-        e = enq_levels(c, st, probes, probes, false, &hb);
+        e = enq_levels(c, L, st, probes, probes, false, &hb);
         if (e == hipSuccess) e = product(probes);
-        if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, c->d_ring, st);
+        if (e == hipSuccess) e = launch_vac_final(L.d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, L.d_ring, st);
     } else if (!P.two) {
-        e = launch_fill_zero(c->facc, c->Lo.sz_facc, st);
-        if (e == hipSuccess) e = enq_levels(c, st, true, false, true, &hb);
+        e = zero_lane(L, c->facc, c->S.facc, 16, c->Lo.sz_facc, st);
+        if (e == hipSuccess) e = enq_levels(c, L, st, true, false, true, &hb);
         if (e == hipSuccess) e = product(false);
         if (e == hipSuccess)
-            e = launch_spec_final(c->d_ens, n, c->d_obs, n_out, c->spec_npm, c->d_probe, c->d_pgroup, c->facc,
-                                  (double)P.n_i, c->res, c->d_ring, st);
-        if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vpart, P.n_i, c->res, c->d_ring, st);
+            e = launch_spec_final(L.d_ens, n, c->d_obs, n_out, c->spec_npm, c->d_probe, c->d_pgroup, c->facc,
+                                  (double)P.n_i, c->res, L.d_ring, st);
+        if (e == hipSuccess) e = launch_vac_final(L.d_ens, n, c->d_obs, c->vpart, P.n_i, c->res, L.d_ring, st);
     } else {
-        e = launch_copy(c->links, c->saved, c->Lo.sz_links, st);
-        if (e == hipSuccess) e = enq_levels(c, st, false, false, false, &hb);
+        e = copy_lane_links(c, L, c->links, c->saved, st);
+        if (e == hipSuccess) e = enq_levels(c, L, st, false, false, false, &hb);
         if (e == hipSuccess) e = product(false);
-        if (e == hipSuccess) e = launch_vac_final(c->d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, c->d_ring, st);
+        if (e == hipSuccess) e = launch_vac_final(L.d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, L.d_ring, st);
         if (e == hipSuccess)
-            e = launch_wfac(c->d_ens, c->tab_dev(kTabSite), n, c->tab_total(kTabSite), c->d_obs, c->ot, 1.0 / P.n_o,
+            e = launch_wfac(L.d_ens, L.tab_dev(kTabSite), n, L.tab_total(kTabSite), c->d_obs, c->ot, 1.0 / P.n_o,
                             c->wf, st);
-        if (e == hipSuccess) e = launch_copy(c->saved, c->links, c->Lo.sz_links, st);
-        if (e == hipSuccess) e = launch_fill_zero(c->facc, c->Lo.sz_facc, st);
+        if (e == hipSuccess) e = copy_lane_links(c, L, c->saved, c->links, st);
+        if (e == hipSuccess) e = zero_lane(L, c->facc, c->S.facc, 16, c->Lo.sz_facc, st);
         int hb2 = 0;
-        if (e == hipSuccess) e = enq_levels(c, st, true, false, true, &hb2);
+        if (e == hipSuccess) e = enq_levels(c, L, st, true, false, true, &hb2);
         if (e == hipSuccess)
-            e = launch_spec_final(c->d_ens, n, c->d_obs, n_out, c->spec_npm, c->d_probe, c->d_pgroup, c->facc,
-                                  (double)P.n_o * P.n_i, c->res, c->d_ring, st);
+            e = launch_spec_final(L.d_ens, n, c->d_obs, n_out, c->spec_npm, c->d_probe, c->d_pgroup, c->facc,
+                                  (double)P.n_o * P.n_i, c->res, L.d_ring, st);
     }
-    if (e == hipSuccess) e = launch_ring_advance(c->d_ring, st);
-    if (e == hipSuccess && hb > 0) e = launch_advance_counters(c->d_upd, n, hb, st);
+    if (e == hipSuccess) e = launch_ring_advance(L.d_ring, st);
+    if (e == hipSuccess && hb > 0) e = launch_advance_counters(L.d_ens, c->d_upd, n, hb, st);
     return e;
 }
 
-hipError_t enq_sweep_with_counter(u1ml_ctx* c, hipStream_t st)
+hipError_t enq_sweep_with_counter(u1ml_ctx* c, const Lane& L, hipStream_t st)
 {
-    hipError_t e = enq_sweep(c, st, 0, 0);
-    if (e == hipSuccess) e = launch_advance_counters(c->d_upd, c->P.n_ens, 1, st);
+    hipError_t e = enq_sweep(c, L, st, 0, 0);
+    if (e == hipSuccess) e = launch_advance_counters(L.d_ens, c->d_upd, L.n, 1, st);
     return e;
 }
 
 void drop_graphs(u1ml_ctx* c)
 {
-    if (c->g_sweep) (void)hipGraphExecDestroy(c->g_sweep);
-    if (c->g_ml) (void)hipGraphExecDestroy(c->g_ml);
-    c->g_sweep = c->g_ml = nullptr;
+    for (Lane* L : {&c->whole, &c->split[0], &c->split[1]}) {
+        if (L->g_sweep) (void)hipGraphExecDestroy(L->g_sweep);
+        if (L->g_ml) (void)hipGraphExecDestroy(L->g_ml);
+        L->g_sweep = L->g_ml = nullptr;
+    }
+}
+
+// graphs, streams and events of a context, then the context
+void release(u1ml_ctx* c)
+{
+    drop_graphs(c);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->lane_stream) (void)hipStreamDestroy(c->lane_stream);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    delete c;
+}
+
+// Runs body(lane, stream) for the two lanes at once: the second lane's
+// stream waits for the context's stream, and the context's stream waits for
+// the second lane at the end.
+template <typename F>
+hipError_t on_lanes(u1ml_ctx* c, F&& body)
+{
+    hipError_t e = hipEventRecord(c->ev_fork, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->lane_stream, c->ev_fork, 0);
+    if (e == hipSuccess) e = body(c->split[0]);
+    hipError_t e2 = e == hipSuccess ? body(c->split[1]) : hipSuccess;
+    hipError_t e3 = hipEventRecord(c->ev_join, c->lane_stream);
+    if (e3 == hipSuccess) e3 = hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3);
 }
 
 template <typename F>
@@ -836,22 +987,16 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     c->oto = (double2*)(w + Lo.off_oto);
     c->res = (double*)(w + Lo.off_res);
     char* s = w + Lo.off_scr;
-    c->d_ens = (EnsDesc*)(s + Lo.s_ens);
     c->d_obs = (ObsDesc*)(s + Lo.s_obs);
     c->d_r = (int*)(s + Lo.s_r);
     c->d_probe = (int*)(s + Lo.s_probe);
     c->d_comp = (int*)(s + Lo.s_comp);
-    c->d_bstart = (int*)(s + Lo.s_bstart);
     c->d_upd = (uint32_t*)(s + Lo.s_upd);
-    c->d_ring = (int*)(s + Lo.s_ring);
     c->vpart = (double*)(s + Lo.s_vpart);
     c->ppart = (double*)(s + Lo.s_ppart);
     c->pout = (double*)(s + Lo.s_pout);
     c->d_count = (unsigned long long*)(s + Lo.s_count);
     c->stage = (double*)(s + Lo.s_stage);
-    c->d_bmap = (int2*)(s + Lo.s_bmap);
-    c->d_mmap = (int2*)(s + Lo.s_mmap);
-    c->prodpart = (double*)(s + Lo.s_prodpart);
     c->d_pgroup = (int*)(s + Lo.s_pgroup);
     c->d_gdesc = (int*)(s + Lo.s_gdesc);
     c->wf = (double2*)(w + Lo.off_wf);
@@ -916,10 +1061,6 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         probe_flat.push_back(p.p2);
         probe_flat.push_back(p.mode);
     }
-    // tables
-    c->h_bstart.assign((size_t)kNumTabs * (n + 1), 0);
-    build_update_tabs(c);
-    std::vector<long long> all(n), meas(n), con(n), comb(n), prod(n);
     // Contraction shape: a line of N sites along a charge axis has N * n_r
     // pairs (x, r), one thread each; a work-group of con_block threads holds
     // con_lpb such lines, and stages con_mc measurements at a time in LDS.
@@ -945,42 +1086,63 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         const size_t fit = (size_t)kConLds / ((size_t)E.con_lpb * nmax * per);
         E.con_mc = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)P.n_i));
         c->con_lds = std::max(c->con_lds, (size_t)E.con_lpb * E.con_mc * nmax * per);
-        int lines = 0;
-        for (int i = 0; i < P.n_dirs; ++i) lines = std::max(lines, E.nsig / n3[P.dirs[i]]);
-        con[e] = (lines + E.con_lpb - 1) / E.con_lpb;
         E.prod_nch = (P.n_dirs * E.nsig + kProdChunk - 1) / kProdChunk;
-        prod[e] = (long long)R * prod_groups(P) * E.prod_nch;
-        all[e] = 8ll * E.vh;
-        meas[e] = (long long)E.nsig * E.s_in;
-        c->max_s_in = std::max(c->max_s_in, E.s_in);
-        comb[e] = (long long)P.n_dirs * P.r.size() * E.s_out * E.nsig;
+        E.res_index = e;
+        long long n12max = 0;
+        for (int i = 0; i < P.n_dirs; ++i) n12max = std::max<long long>(n12max, E.nsig / n3[P.dirs[i]]);
+        c->spec_npm = std::max(c->spec_npm, std::max(E.nx, std::max(E.ny, E.nz)));
+        c->spec_n12max = std::max(c->spec_n12max, n12max);
+        for (int i = 0; i < P.n_dirs; ++i)
+            for (int k = 1; k < 3; ++k)
+                if (n3[(P.dirs[i] + k) % 3] % 4 != 0) c->spec_tile = 2;
     }
-    build_tab(c, kTabAll, all, 256);
-    build_tab(c, kTabMeas, meas, 256);
-    build_tab(c, kTabCon, con, 1);
-    build_tab(c, kTabComb, comb, 256);
-    build_tab(c, kTabProd, prod, 1);
+    // the whole batch, and (two or more ensembles) two lanes of about equal
+    // volume, largest ensembles first; each lane keeps the problem order
     {
-        std::vector<long long> site(n), plane(n), mac(n);
-        const size_t NG = P.gdesc.size() / 2;
-        for (int e = 0; e < n; ++e) {
-            const EnsDesc& E = c->h_ens[e];
-            const int n3[3] = {E.nx, E.ny, E.nz};
-            const long long npm = std::max(E.nx, std::max(E.ny, E.nz));
-            long long n12max = 0;
-            for (int i = 0; i < P.n_dirs; ++i) n12max = std::max<long long>(n12max, E.nsig / n3[P.dirs[i]]);
-            site[e] = (long long)P.n_dirs * P.r.size() * E.nsig;
-            plane[e] = P.spectral ? (long long)P.n_dirs * E.s_in * ((long long)P.r.size() + 12) * npm : 0;
-            mac[e] = P.spectral ? (long long)P.n_dirs * E.s_in * P.r.size() * P.comps.size() * 2 * NG * n12max : 0;
-            c->spec_npm = std::max<int>(c->spec_npm, (int)npm);
-            for (int i = 0; i < P.n_dirs; ++i)
-                for (int k = 1; k < 3; ++k)
-                    if (n3[(P.dirs[i] + k) % 3] % 4 != 0) c->spec_tile = 2;
-            c->spec_n12max = std::max<long long>(c->spec_n12max, n12max);
+        std::vector<int> all_idx(n);
+        for (int e = 0; e < n; ++e) all_idx[e] = e;
+        std::vector<int> order(all_idx);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return c->h_ens[a].vh > c->h_ens[b].vh; });
+        std::vector<int> parts[2];
+        long long load[2] = {0, 0};
+        for (int e : order) {
+            const int l = load[1] < load[0] ? 1 : 0;
+            parts[l].push_back(e);
+            load[l] += c->h_ens[e].vh;
         }
-        build_tab(c, kTabSite, site, 256);
-        build_tab(c, kTabPlane, plane, 1);
-        build_tab(c, kTabMac, mac, 256);
+        Lane* lanes[3] = {&c->whole, &c->split[0], &c->split[1]};
+        const std::vector<int>* idxs[3] = {&all_idx, &parts[0], &parts[1]};
+        size_t pp_off = 0;
+        for (int l = 0; l < 3; ++l) {
+            Lane& L = *lanes[l];
+            L.idx = *idxs[l];
+            std::sort(L.idx.begin(), L.idx.end());
+            L.n = (int)L.idx.size();
+            L.h_ens.clear();
+            for (int e : L.idx) L.h_ens.push_back(c->h_ens[e]);
+            L.bmap_stride = Lo.bmap_stride;
+            if (l == 0) {
+                L.d_ens = (EnsDesc*)(s + Lo.s_ens);
+                L.d_bstart = (int*)(s + Lo.s_bstart);
+                L.d_bmap = (int2*)(s + Lo.s_bmap);
+                L.d_mmap = (int2*)(s + Lo.s_mmap);
+                L.d_ring = (int*)(s + Lo.s_ring);
+                L.prodpart = (double*)(s + Lo.s_prodpart);
+                L.stream = c->stream;
+            } else {
+                L.d_ens = (EnsDesc*)(s + Lo.s_lens[l - 1]);
+                L.d_bstart = (int*)(s + Lo.s_lbstart[l - 1]);
+                L.d_bmap = (int2*)(s + Lo.s_lbmap[l - 1]);
+                L.d_mmap = (int2*)(s + Lo.s_lmmap[l - 1]);
+                L.d_ring = (int*)(s + Lo.s_lring[l - 1]);
+                // the two lanes use disjoint parts of the slab-product partials
+                L.prodpart = (double*)(s + Lo.s_prodpart) + pp_off;
+            }
+            build_lane_tables(c, L);
+            if (l > 0) pp_off += (size_t)L.tab_total(kTabProd) * kProdQ * 2;
+        }
+        c->lanes = n >= 2;
     }
     {
         // every dynamic LDS request must fit the device's limit per work-group
@@ -989,42 +1151,41 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         const size_t plane_lds = P.spectral ? (2 * (size_t)c->spec_n12max + 2 * (size_t)c->spec_npm) * sizeof(double2) : 0;
         const size_t need = std::max(c->con_lds, plane_lds);
         if (ea != hipSuccess || (size_t)lds_max < need) {
-            (void)hipStreamDestroy(c->cap);
-            delete c;
+            release(c);
             return set_err(nullptr, ea != hipSuccess ? U1ML_EDEVICE : U1ML_ENOTSUP,
                            "work-group LDS of " + std::to_string(need) + " bytes exceeds the device limit of " +
                                std::to_string(lds_max));
         }
     }
     std::vector<uint32_t> zeros(n, 0u);
-    int ring0[4] = {0, 0, 0, 0};
     u1ml_status st = U1ML_OK;
     auto up = [&](void* dst, const void* src, size_t bytes) {
         if (st != U1ML_OK || bytes == 0) return;
         hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) st = set_err(nullptr, U1ML_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
     };
-    up(c->d_ens, c->h_ens.data(), sizeof(EnsDesc) * n);
     up(c->d_obs, &O, sizeof O);
     up(c->d_r, P.r.data(), sizeof(int) * P.r.size());
     up(c->d_probe, probe_flat.data(), sizeof(int) * probe_flat.size());
     up(c->d_comp, P.comps.data(), sizeof(int) * P.comps.size());
     up(c->d_pgroup, P.pgroup.data(), sizeof(int) * P.pgroup.size());
     up(c->d_gdesc, P.gdesc.data(), sizeof(int) * P.gdesc.size());
-    up(c->d_bstart, c->h_bstart.data(), sizeof(int) * c->h_bstart.size());
-    up(c->d_bmap, c->h_bmap.data(), sizeof(int2) * c->h_bmap.size());
-    std::vector<int2> mmap;
-    {
-        const int* b = &c->h_bstart[(size_t)kTabMeas * (n + 1)];
-        for (int e = 0; e < n; ++e)
-            for (int k = b[e]; k < b[e + 1]; ++k) mmap.push_back(make_int2(e, k - b[e]));
-    }
-    up(c->d_mmap, mmap.data(), sizeof(int2) * mmap.size());
     up(c->d_upd, zeros.data(), sizeof(uint32_t) * n);
-    up(c->d_ring, ring0, sizeof ring0);
+    for (Lane* L : {&c->whole, &c->split[0], &c->split[1]}) {
+        if (st != U1ML_OK || L->n == 0) continue;
+        hipError_t e = upload_lane(*L);
+        if (e != hipSuccess) st = set_err(nullptr, U1ML_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    if (st == U1ML_OK) {
+        hipError_t e = hipStreamCreateWithFlags(&c->lane_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) st = set_err(nullptr, U1ML_EDEVICE, std::string("lane stream: ") + hipGetErrorString(e));
+        c->split[0].stream = c->stream;
+        c->split[1].stream = c->lane_stream;
+    }
     if (st != U1ML_OK) {
-        (void)hipStreamDestroy(c->cap);
-        delete c;
+        release(c);
         return st;
     }
     *out = c;
@@ -1034,9 +1195,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
 u1ml_status u1ml_destroy(u1ml_ctx* ctx)
 {
     if (!ctx) return U1ML_OK;
-    drop_graphs(ctx);
-    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
-    delete ctx;
+    release(ctx);
     return U1ML_OK;
 }
 
@@ -1044,7 +1203,7 @@ u1ml_status u1ml_init_links(u1ml_ctx* ctx, int start)
 {
     if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
     if (start != U1ML_COLD && start != U1ML_HOT) return set_err(ctx, U1ML_EINVAL, "start must be 0 (cold) or 1 (hot)");
-    HIPCHK(ctx, launch_init_links(ctx->d_ens, ctx->tab_dev(kTabAll), ctx->P.n_ens, ctx->tab_total(kTabAll),
+    HIPCHK(ctx, launch_init_links(ctx->whole.d_ens, ctx->whole.tab_dev(kTabAll), ctx->P.n_ens, ctx->whole.tab_total(kTabAll),
                                   ctx->P.precision, ctx->links, start, ctx->stream));
     HIPCHK(ctx, launch_fill_zero(ctx->d_upd, align_up(sizeof(uint32_t) * ctx->P.n_ens), ctx->stream));
     ctx->initialised = true;
@@ -1057,15 +1216,29 @@ u1ml_status u1ml_sweeps(u1ml_ctx* ctx, int n)
     if (n < 0) return set_err(ctx, U1ML_EINVAL, "n must be >= 0");
     if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
     if (n == 0) return U1ML_OK;
-    if (ctx->use_graphs) {
-        if (!ctx->g_sweep) {
-            u1ml_status s = capture(ctx, [&](hipStream_t st) { return enq_sweep_with_counter(ctx, st); }, &ctx->g_sweep);
-            if (s != U1ML_OK) return s;
+    // one lane's n sweeps on its stream (graph of one sweep, launched n times)
+    auto lane_sweeps = [&](Lane& L) -> hipError_t {
+        if (ctx->use_graphs) {
+            if (!L.g_sweep &&
+                capture(ctx, [&](hipStream_t st) { return enq_sweep_with_counter(ctx, L, st); }, &L.g_sweep) != U1ML_OK)
+                return hipErrorUnknown;
+            for (int i = 0; i < n; ++i) {
+                hipError_t e = hipGraphLaunch(L.g_sweep, L.stream);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
         }
-        for (int i = 0; i < n; ++i) HIPCHK(ctx, hipGraphLaunch(ctx->g_sweep, ctx->stream));
-    } else {
-        for (int i = 0; i < n; ++i) HIPCHK(ctx, enq_sweep_with_counter(ctx, ctx->stream));
-    }
+        for (int i = 0; i < n; ++i) {
+            hipError_t e = enq_sweep_with_counter(ctx, L, L.stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    const std::string before = ctx->err;
+    hipError_t e = ctx->lanes ? on_lanes(ctx, lane_sweeps) : lane_sweeps(ctx->whole);
+    if (e != hipSuccess)
+        return ctx->err != before && e == hipErrorUnknown ? U1ML_EDEVICE
+                                                          : set_err(ctx, U1ML_EDEVICE, std::string("sweeps: ") + hipGetErrorString(e));
     return U1ML_OK;
 }
 
@@ -1078,7 +1251,7 @@ u1ml_status u1ml_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int
     bool ok;
     update_class(ctx, mu, tau, &ok);
     if (!ok) return set_err(ctx, U1ML_EINVAL, "tau must be <= 1 or one of the problem's level thicknesses");
-    HIPCHK(ctx, enq_phase(ctx, ctx->stream, kind, mu, parity, tau, pass_offset));
+    HIPCHK(ctx, enq_phase(ctx, ctx->whole, ctx->stream, kind, mu, parity, tau, pass_offset));
     return U1ML_OK;
 }
 
@@ -1088,15 +1261,19 @@ u1ml_status u1ml_multilevel(u1ml_ctx* ctx)
     if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
     if (ctx->ring_count >= ctx->P.max_configs)
         return set_err(ctx, U1ML_ESTATE, "results ring is full: call u1ml_copy_results");
-    if (ctx->use_graphs && body_launches(ctx->P) <= kMaxGraphLaunches) {
-        if (!ctx->g_ml) {
-            u1ml_status s = capture(ctx, [&](hipStream_t st) { return enq_multilevel(ctx, st); }, &ctx->g_ml);
-            if (s != U1ML_OK) return s;
-        }
-        HIPCHK(ctx, hipGraphLaunch(ctx->g_ml, ctx->stream));
-    } else {
-        HIPCHK(ctx, enq_multilevel(ctx, ctx->stream));
-    }
+    const bool graph = ctx->use_graphs && body_launches(ctx->P) <= kMaxGraphLaunches;
+    auto lane_config = [&](Lane& L) -> hipError_t {
+        if (!graph) return enq_multilevel(ctx, L, L.stream);
+        if (!L.g_ml && capture(ctx, [&](hipStream_t st) { return enq_multilevel(ctx, L, st); }, &L.g_ml) != U1ML_OK)
+            return hipErrorUnknown;
+        return hipGraphLaunch(L.g_ml, L.stream);
+    };
+    const std::string before = ctx->err;
+    hipError_t e = ctx->lanes ? on_lanes(ctx, lane_config) : lane_config(ctx->whole);
+    if (e != hipSuccess)
+        return ctx->err != before && e == hipErrorUnknown
+                   ? U1ML_EDEVICE
+                   : set_err(ctx, U1ML_EDEVICE, std::string("multilevel: ") + hipGetErrorString(e));
     ctx->ring_count++;
     return U1ML_OK;
 }
@@ -1110,7 +1287,8 @@ u1ml_status u1ml_copy_results(u1ml_ctx* ctx, double* host, size_t n_doubles, siz
     const size_t nw = std::min(avail, n_doubles);
     if (nw) HIPCHK(ctx, hipMemcpy(host, ctx->res, nw * sizeof(double), hipMemcpyDeviceToHost));
     int zero[4] = {0, 0, 0, 0};
-    HIPCHK(ctx, hipMemcpy(ctx->d_ring, zero, sizeof zero, hipMemcpyHostToDevice));
+    for (Lane* L : {&ctx->whole, &ctx->split[0], &ctx->split[1]})
+        if (L->n) HIPCHK(ctx, hipMemcpy(L->d_ring, zero, sizeof zero, hipMemcpyHostToDevice));
     ctx->ring_count = 0;
     if (n_written) *n_written = nw;
     return U1ML_OK;
@@ -1122,7 +1300,7 @@ u1ml_status u1ml_get_links(u1ml_ctx* ctx, int ens, double* host, size_t n)
     if (ens < 0 || ens >= ctx->P.n_ens) return set_err(ctx, U1ML_EINVAL, "ensemble index out of range");
     const long long V = 2ll * ctx->h_ens[ens].vh;
     if (!host || n != (size_t)(4 * V)) return set_err(ctx, U1ML_EINVAL, "host buffer must hold exactly 4 V doubles");
-    HIPCHK(ctx, launch_gather_links(ctx->d_ens, ens, ctx->P.precision, ctx->links, ctx->stage, V, ctx->stream));
+    HIPCHK(ctx, launch_gather_links(ctx->whole.d_ens, ens, ctx->P.precision, ctx->links, ctx->stage, V, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipMemcpy(host, ctx->stage, sizeof(double) * 4 * V, hipMemcpyDeviceToHost));
     return U1ML_OK;
@@ -1136,7 +1314,7 @@ u1ml_status u1ml_set_links(u1ml_ctx* ctx, int ens, const double* host, size_t n)
     if (!host || n != (size_t)(4 * V)) return set_err(ctx, U1ML_EINVAL, "host buffer must hold exactly 4 V doubles");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipMemcpy(ctx->stage, host, sizeof(double) * 4 * V, hipMemcpyHostToDevice));
-    HIPCHK(ctx, launch_scatter_links(ctx->d_ens, ens, ctx->P.precision, ctx->links, ctx->stage, V, ctx->stream));
+    HIPCHK(ctx, launch_scatter_links(ctx->whole.d_ens, ens, ctx->P.precision, ctx->links, ctx->stage, V, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->initialised = true;
     return U1ML_OK;
@@ -1165,7 +1343,7 @@ u1ml_status u1ml_plaquette(u1ml_ctx* ctx, double* out)
     if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
     if (!out) return set_err(ctx, U1ML_EINVAL, "out is NULL");
     if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
-    HIPCHK(ctx, launch_plaquette(ctx->d_ens, ctx->P.n_ens, 0, ctx->P.precision, ctx->links, ctx->ppart, ctx->pout,
+    HIPCHK(ctx, launch_plaquette(ctx->whole.d_ens, ctx->P.n_ens, 0, ctx->P.precision, ctx->links, ctx->ppart, ctx->pout,
                                  ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipMemcpy(out, ctx->pout, sizeof(double) * 6 * ctx->P.n_ens, hipMemcpyDeviceToHost));
@@ -1177,7 +1355,7 @@ u1ml_status u1ml_health(u1ml_ctx* ctx, uint64_t* n_bad)
     if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
     if (!n_bad) return set_err(ctx, U1ML_EINVAL, "n_bad is NULL");
     HIPCHK(ctx, launch_fill_zero(ctx->d_count, 16, ctx->stream));
-    HIPCHK(ctx, launch_health(ctx->d_ens, ctx->tab_dev(kTabAll), ctx->P.n_ens, ctx->tab_total(kTabAll),
+    HIPCHK(ctx, launch_health(ctx->whole.d_ens, ctx->whole.tab_dev(kTabAll), ctx->P.n_ens, ctx->whole.tab_total(kTabAll),
                               ctx->P.precision, ctx->links, ctx->d_count, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     unsigned long long v = 0;
@@ -1193,11 +1371,27 @@ u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block)
         return set_err(ctx, U1ML_EINVAL, "block must be 64, 128, 256, 512 or 1024");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->block = block;
-    build_update_tabs(ctx);
-    HIPCHK(ctx, hipMemcpy(ctx->d_bstart, ctx->h_bstart.data(), sizeof(int) * 4 * (ctx->P.n_ens + 1),
-                          hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(ctx->d_bmap, ctx->h_bmap.data(), sizeof(int2) * ctx->h_bmap.size(), hipMemcpyHostToDevice));
+    for (Lane* L : {&ctx->whole, &ctx->split[0], &ctx->split[1]}) {
+        if (!L->n) continue;
+        build_update_tabs(ctx, *L);
+        HIPCHK(ctx, hipMemcpy(L->d_bstart, L->h_bstart.data(), sizeof(int) * 4 * (L->n + 1), hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipMemcpy(L->d_bmap, L->h_bmap.data(), sizeof(int2) * L->h_bmap.size(), hipMemcpyHostToDevice));
+    }
     drop_graphs(ctx);
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_set_lanes(u1ml_ctx* ctx, int n_lanes)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (n_lanes != 1 && n_lanes != 2) return set_err(ctx, U1ML_EINVAL, "n_lanes must be 1 or 2");
+    if (n_lanes == 2 && ctx->P.n_ens < 2) return set_err(ctx, U1ML_EINVAL, "two lanes need two or more ensembles");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->lanes = n_lanes == 2;
+    // the lanes now in use continue the results ring where it stands
+    const int ring[4] = {ctx->ring_count, 0, 0, 0};
+    for (Lane* L : {&ctx->whole, &ctx->split[0], &ctx->split[1]})
+        if (L->n) HIPCHK(ctx, hipMemcpy(L->d_ring, ring, sizeof ring, hipMemcpyHostToDevice));
     return U1ML_OK;
 }
 
@@ -1223,7 +1417,7 @@ u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau
     for (auto& x : ev) HIPCHK(ctx, hipEventCreate(&x));
     hipError_t he = hipSuccess;
     for (int i = 0; i < n_rep && he == hipSuccess; ++i)
-        he = enq_phase(ctx, ctx->stream, kind, mu, parity, tau, 0, ev[2 * i], ev[2 * i + 1]);
+        he = enq_phase(ctx, ctx->whole, ctx->stream, kind, mu, parity, tau, 0, ev[2 * i], ev[2 * i + 1]);
     if (he == hipSuccess) he = hipEventSynchronize(ev.back());
     double total = 0.0;
     for (int i = 0; i < n_rep && he == hipSuccess; ++i) {
@@ -1290,9 +1484,9 @@ u1ml_status u1ml_autotune(u1ml_ctx* ctx, u1ml_tune_report* report)
             st = set_err(ctx, U1ML_EDEVICE, "event creation failed");
             break;
         }
-        hipError_t e = enq_sweep(ctx, ctx->stream, tau, 0);  // warm-up
+        hipError_t e = enq_sweep(ctx, ctx->whole, ctx->stream, tau, 0);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
-        for (int k = 0; k < 5 && e == hipSuccess; ++k) e = enq_sweep(ctx, ctx->stream, tau, 0);
+        for (int k = 0; k < 5 && e == hipSuccess; ++k) e = enq_sweep(ctx, ctx->whole, ctx->stream, tau, 0);
         if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float ms = 0.f;

@@ -14,7 +14,9 @@ struct EnsDesc {
     int nxh, nsig, vh, s_in;  // s_in: slabs of the innermost level
     int s_out, n_vac_blocks;
     int con_lpb, con_mc;  // contraction: lines per work-group, measurements per LDS chunk
-    int prod_nch, pad0, pad1, pad2;  // slab products: site chunks per (r, probe)
+    int prod_nch;   // slab products: site chunks per (r, probe)
+    int res_index;  // index of the ensemble in the problem (counters, results)
+    int pad0, pad1;
     float inv_nxh, inv_ny, inv_slice, pad3;  // 1/(Nx/2), 1/Ny, 1/((Nx/2) Ny Nz) for division-free decode
     double beta, sqrt_beta;
     uint32_t seed, key_id;
@@ -34,6 +36,7 @@ struct ObsDesc {
     int n_r, n_probe, n_comp;
     int store_o;  // 1 if insertions are requested (history keeps O sums)
     int n_groups;  // probe groups sharing (l, mode) (spectral form)
+    int n_ens_total;  // ensembles of the problem (rows of a results record)
     long long n_doubles_per_config;
 };
 
@@ -58,7 +61,7 @@ hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1
                               uint32_t* d_out, hipStream_t st);
 hipError_t launch_vonmises_fill(double kappa, int precision, uint32_t seed, uint32_t key_id, uint32_t c0, uint32_t c1,
                                 size_t n, double* d_out, int* d_att, hipStream_t st);
-hipError_t launch_advance_counters(uint32_t* d_upd, int n_ens, int delta, hipStream_t st);
+hipError_t launch_advance_counters(const EnsDesc* d_ens, uint32_t* d_upd, int n_ens, int delta, hipStream_t st);
 hipError_t launch_gather_links(const EnsDesc* d_ens, int ens, int precision, const void* links, double* d_canon,
                                long long n_sites, hipStream_t st);
 hipError_t launch_scatter_links(const EnsDesc* d_ens, int ens, int precision, void* links, const double* d_canon,

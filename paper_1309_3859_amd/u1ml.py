@@ -100,6 +100,7 @@ def lib():
         "u1ml_autotune": [vp, C.POINTER(_TuneReport)],
         "u1ml_set_block": [vp, i32],
         "u1ml_set_graphs": [vp, i32],
+        "u1ml_set_lanes": [vp, i32],
         "u1ml_time_phase": [vp, i32, i32, i32, i32, i32, pd],
         "u1ml_phase_bytes": [vp, i32, i32, i32, i32, pd, C.POINTER(C.c_long)],
         "u1ml_philox_fill": [u32, u32, u32, u32, u32, u32, sz, vp, vp],
@@ -302,6 +303,9 @@ class Context:
 
     def set_graphs(self, enable: bool):
         self._c(lib().u1ml_set_graphs(self._h, int(bool(enable))))
+
+    def set_lanes(self, n_lanes: int):
+        self._c(lib().u1ml_set_lanes(self._h, int(n_lanes)))
 
     def time_phase(self, kind: int, mu: int, parity: int, tau: int, n_rep: int) -> float:
         us = C.c_double()

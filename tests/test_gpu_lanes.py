@@ -1,0 +1,72 @@
+"""A batch run as two lanes on two streams (the default for two or more
+ensembles) gives the same links, counters and estimates, bit for bit, as the
+whole batch on one stream: one and two levels, history and spectral forms
+(the spectral two-level replay copies and clears only its own lane's
+ensembles)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def u1():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1309_3859_amd import u1ml
+
+    u1ml.lib()
+    return u1ml
+
+
+def _disk1():
+    return [(0, 0, 0, 1), (0, 1, 0, 1), (0, -1, 0, 1), (0, 0, 1, 1), (0, 0, -1, 1)]
+
+
+def _spec(u1, levels, form):
+    return u1.Spec(ensembles=[u1.Ens((6, 6, 6), 8, 1.0, seed=41), u1.Ens((4, 4, 4), 8, 0.95, seed=42, key_id=1),
+                              u1.Ens((8, 6, 6), 8, 1.02, seed=43, key_id=2)],
+                   levels=levels, r=[1, 2], dirs=[0, 1], probes=_disk1(), comps=[0, 3], precision=u1.FP32, n_or=2,
+                   form=form, max_configs=2)
+
+
+def _run(u1, spec, lanes):
+    ctx = u1.Context(spec)
+    ctx.set_lanes(lanes)
+    ctx.init_links(u1.HOT)
+    ctx.sweeps(3)
+    ctx.multilevel()
+    ctx.multilevel()
+    res = ctx.results()
+    links = [ctx.links(e) for e in range(len(spec.ensembles))]
+    cnt = [ctx.counter(e) for e in range(len(spec.ensembles))]
+    return res, links, cnt
+
+
+@pytest.mark.parametrize("levels", [[(2, 3, 1)], [(4, 2, 1), (2, 2, 1)]], ids=["one_level", "two_levels"])
+@pytest.mark.parametrize("form", [1, 2], ids=["history", "spectral"])
+def test_two_lanes_bit_identical(u1, levels, form):
+    say("lanes", levels, "form", form)
+    r1, l1, c1 = _run(u1, _spec(u1, levels, form), 1)
+    r2, l2, c2 = _run(u1, _spec(u1, levels, form), 2)
+    assert c1 == c2
+    for a, b in zip(l1, l2):
+        assert np.array_equal(a, b)
+    assert np.array_equal(r1, r2)
+
+
+def test_set_lanes_rejects_single_ensemble(u1):
+    spec = u1.Spec(ensembles=[u1.Ens((4, 4, 4), 4, 1.0)], levels=[(2, 1, 1)], r=[1])
+    ctx = u1.Context(spec)
+    with pytest.raises(u1.U1MLError):
+        ctx.set_lanes(2)
+    ctx.set_lanes(1)
