@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
+    ap.add_argument("--block", type=int, default=256,
+                    help="work-group size of the update kernels (0: autotune; candidates differ by about 2 percent, "
+                         "so a fixed size keeps profiled and unprofiled runs on the same launch shape)")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: one 256 MiB device copy (calibration of the byte counters), "
                          "then 20 launches each of the heatbath and overrelaxation phases of the dominant kernel")
@@ -179,7 +182,11 @@ def main():
     spec.max_configs = max(1, args.steps + args.warmup)
     ctx = u1ml.Context(spec)
     ctx.init_links(sched["start"])
-    tune = ctx.autotune()
+    if args.block:
+        ctx.set_block(args.block)
+        block = args.block
+    else:
+        block = ctx.autotune()["chosen_block"]
     ctx.sweeps(20)
     upd = ctx.plan["updates_per_config"]
     ms = time_steps(ctx, args.steps, args.warmup)
@@ -210,7 +217,7 @@ def main():
         "config": {"workload": make.__name__, "ensembles": len(spec.ensembles),
                    "lattices": sorted({f"{e.ns[0]}^3x{e.nt}" for e in spec.ensembles}),
                    "levels": spec.levels, "n_or": spec.n_or, "updates_per_step": upd,
-                   "block": tune["chosen_block"]},
+                   "block": block},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counter_traffic() if args.workload == "c4" else None,
@@ -226,7 +233,7 @@ def main():
         del ctx
         ctx64 = u1ml.Context(spec64)
         ctx64.init_links(sched["start"])
-        ctx64.set_block(tune["chosen_block"])
+        ctx64.set_block(block)
         ctx64.sweeps(5)
         ms64 = time_steps(ctx64, args.steps, args.warmup)
         line["plain_fp64"] = {"value": upd * args.steps / (ms64 / 1e3), "unit": "link updates/s",
