@@ -11,7 +11,7 @@ reported as a check.)  Errors are delete-one jackknife over configurations.
 """
 from __future__ import annotations
 
-from typing import Callable, Sequence
+from typing import Callable, Optional, Sequence
 
 import numpy as np
 
@@ -72,3 +72,133 @@ def flux_tube_width2(profile: np.ndarray, p1: Sequence[int], p2: Sequence[int]):
     (Sec. II.B, eq. for w^2(r/2)), over the probe positions given."""
     x2 = np.asarray(p1, float) ** 2 + np.asarray(p2, float) ** 2
     return float(np.sum(x2 * profile) / np.sum(profile))
+
+
+# ---------------------------------------------------------------------------
+# Potential, Sommer scale, profile ansatz and effective-string width
+# (arXiv 1309.3859: eq. for V(r), Sec. II.A; r_0, Sec. II.D "Scale setting";
+# profile ansatz and width, Sec. III.C; tree-level widening, Sec. I.B).
+# ---------------------------------------------------------------------------
+def potential(records: Sequence[dict], nt: int):
+    """V(r) = -ln <P^dagger P>(r) / N_t with jackknife errors (the Polyakov
+    correlator at temperature 1/N_t decays as exp(-N_t V))."""
+    C = np.array([rec["C"].real for rec in records])
+    return jackknife(C, lambda x: -np.log(x.mean(axis=0)) / nt)
+
+
+def fit_potential(r, V, err=None, gamma: Optional[float] = None):
+    """Weighted least squares of V(r) = V_0 + sigma r - gamma / r; gamma free,
+    or fixed (for d = 4 the Luscher value is pi / 12).  Returns a dict with
+    V0, sigma, gamma."""
+    r = np.asarray(r, float)
+    V = np.asarray(V, float)
+    w = np.ones_like(r) if err is None else 1.0 / np.asarray(err, float)
+    if gamma is None:
+        A = np.stack([np.ones_like(r), r, -1.0 / r], axis=1)
+        coef = np.linalg.lstsq(A * w[:, None], V * w, rcond=None)[0]
+        return {"V0": coef[0], "sigma": coef[1], "gamma": coef[2]}
+    A = np.stack([np.ones_like(r), r], axis=1)
+    coef = np.linalg.lstsq(A * w[:, None], (V + gamma / r) * w, rcond=None)[0]
+    return {"V0": coef[0], "sigma": coef[1], "gamma": float(gamma)}
+
+
+def lattice_green(r: int) -> float:
+    """Lattice Coulomb Green function on the cubic lattice,
+    G(r) = int d^3k/(2 pi)^3 cos(k_1 r) / (4 sum_j sin^2(k_j/2)).  With
+    1/D = int_0^inf exp(-t D) dt the Brillouin-zone integral factorises into
+    modified Bessel functions: G(r) = int_0^inf exp(-6t) I_r(2t) I_0(2t)^2 dt,
+    evaluated with the exponentially scaled ive.  G(r) -> 1/(4 pi r) at large r."""
+    from scipy.integrate import quad
+    from scipy.special import ive
+
+    f = lambda t: ive(abs(r), 2 * t) * ive(0, 2 * t) ** 2
+    return float(quad(f, 0, 50, limit=400)[0] + quad(f, 50, np.inf, limit=400)[0])
+
+
+def rbar_tree(r: int) -> float:
+    """Tree-level improved distance of the force F(rbar) = V(r) - V(r-1):
+    rbar = [4 pi (G(r-1) - G(r))]^(-1/2), so that the lattice Coulomb force is
+    exactly 1/(4 pi rbar^2).  (The printed formula's sign and prefactor are
+    read so that rbar -> r - 1/2 at large r.)"""
+    return float((4 * np.pi * (lattice_green(r - 1) - lattice_green(r))) ** -0.5)
+
+
+def sommer_r0(r, V, rbar: Optional[Callable[[int], float]] = None, c: float = 1.65):
+    """Sommer scale r_0 with r_0^2 F(r_0) = c: for consecutive pairs of
+    forces F(rbar_r) = V(r) - V(r-1), F(rbar_{r+1}) = V(r+1) - V(r), solve
+    F = f1 + f2 / rbar^2 and take the pair whose interval contains r_0.
+    rbar defaults to r - 1/2; pass rbar_tree for the tree-level choice."""
+    r = [int(x) for x in r]
+    V = np.asarray(V, float)
+    rb = rbar or (lambda x: x - 0.5)
+    best = None
+    for i in range(1, len(r) - 1):
+        if r[i] - r[i - 1] != 1 or r[i + 1] - r[i] != 1:
+            continue
+        a, b = rb(r[i]), rb(r[i + 1])
+        Fa, Fb = V[i] - V[i - 1], V[i + 1] - V[i]
+        f2 = (Fa - Fb) / (1 / a ** 2 - 1 / b ** 2)
+        f1 = Fa - f2 / a ** 2
+        if f1 <= 0 or c <= f2:
+            continue
+        r0 = float(np.sqrt((c - f2) / f1))
+        if best is None or (a <= r0 <= b):
+            best = r0
+            if a <= r0 <= b:
+                break
+    return best
+
+
+def profile_ansatz(x2, C1, C2, C3, s):
+    """C_1 exp(-x^2/s) (1 + C_2 exp(-x^2/s)) / (1 + C_3 exp(-x^2/s))."""
+    g = np.exp(-np.asarray(x2, float) / s)
+    return C1 * g * (1 + C2 * g) / (1 + C3 * g)
+
+
+def fit_profile(x2, y, err=None, p0=(1.0, 0.0, 0.0, 4.0)):
+    """Least-squares fit of the profile ansatz to a transverse profile."""
+    from scipy.optimize import curve_fit
+
+    popt, _ = curve_fit(profile_ansatz, np.asarray(x2, float), np.asarray(y, float), p0=p0,
+                        sigma=None if err is None else np.asarray(err, float), maxfev=20000)
+    return popt
+
+
+def width2_from_ansatz(C1, C2, C3, s):
+    """w^2 = int d^2x x^2 f / int d^2x f for the ansatz f over the whole
+    transverse plane; with t = x^2, d^2x = pi dt, so w^2 = int t f dt / int f dt."""
+    from scipy.integrate import quad
+
+    f = lambda t: profile_ansatz(t, C1, C2, C3, s)
+    top = quad(lambda t: t * f(t), 0, np.inf, limit=200)[0]
+    bot = quad(f, 0, np.inf, limit=200)[0]
+    return top / bot
+
+
+def log_eta_ratio(u: float, terms: int = 200) -> float:
+    """log( eta(2 i u) / eta(i u)^2 ) with the Dedekind eta function
+    eta(tau) = q^(1/24) prod_n (1 - q^n), q = exp(2 pi i tau), for u > 0."""
+    q1 = np.exp(-2 * np.pi * u)
+    n = np.arange(1, terms + 1)
+    log_eta = lambda q, lq: lq / 24 + np.sum(np.log1p(-q ** n))
+    return float(log_eta(q1 ** 2, -4 * np.pi * u) - 2 * log_eta(q1, -2 * np.pi * u))
+
+
+def width2_string(r, sigma, rho0, T, d: int = 4):
+    """Tree-level effective-string width at the mid-plane,
+    w^2(r/2) = (d-2)/(2 pi sigma) log(r/rho0) + (d-2)/(pi sigma) log(eta(2iu)/eta(iu)^2),
+    u = 1/(2 T r)."""
+    r = np.atleast_1d(np.asarray(r, float))
+    out = np.array([(d - 2) / (2 * np.pi * sigma) * np.log(x / rho0)
+                    + (d - 2) / (np.pi * sigma) * log_eta_ratio(1.0 / (2 * T * x)) for x in r])
+    return out if out.size > 1 else float(out[0])
+
+
+def fit_width(r, w2, T, err=None, d: int = 4, p0=(0.2, 0.5)):
+    """Fit sigma and rho0 of width2_string to measured widths at temperature T."""
+    from scipy.optimize import curve_fit
+
+    f = lambda x, sigma, rho0: width2_string(x, sigma, rho0, T, d)
+    popt, _ = curve_fit(f, np.asarray(r, float), np.asarray(w2, float), p0=p0,
+                        sigma=None if err is None else np.asarray(err, float), maxfev=20000)
+    return {"sigma": popt[0], "rho0": popt[1]}
