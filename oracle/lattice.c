@@ -26,7 +26,9 @@ struct orc_lattice {
     long V;
     double beta;
     uint32_t key[2];
-    uint32_t upd;      /* heatbath pass counter (second Philox counter word) */
+    uint32_t upd;      /* stochastic pass counter (second Philox counter word) */
+    int stoch;         /* stochastic update of a sweep: 0 heatbath, 2 Metropolis */
+    double delta;      /* Metropolis step */
     long n_cap;        /* heatbath draws that hit the attempt cap */
     double* th;        /* th[mu + d*site] */
 };
@@ -253,6 +255,36 @@ void orc_heatbath_link(orc_lattice* lat, long site, int mu)
     lat->th[mu + (long)lat->d * site] = wrap(psi - phiA);
 }
 
+/* Metropolis (the paper's update, Sec. II): propose theta' = theta + delta
+ * (2 U1 - 1) and accept with probability min(1, exp(-dS)), where the local
+ * action is -beta Re(e^{i theta} A) (the staple sum A collects every
+ * plaquette containing the link), so
+ *   -dS = beta [Re(e^{i theta'} A) - Re(e^{i theta} A)].
+ * Random words: the Philox block (link id, counter, 0, ORC_DOM_METRO);
+ * U1 = ((w0 >> 1) + 1/2) 2^-31 sets the proposal, U2 = (w1 + 1/2) 2^-32 the
+ * decision: accept if -dS >= 0 or U2 < exp(-dS). */
+void orc_metropolis_link(orc_lattice* lat, long site, int mu)
+{
+    double ar, ai;
+    orc_staple(lat, site, mu, &ar, &ai);
+    uint32_t lid = (uint32_t)(mu + (long)lat->d * site);
+    uint32_t ctr[4] = {lid, lat->upd, 0u, ORC_DOM_METRO};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, lat->key, w);
+    double u1 = ((double)(w[0] >> 1) + 0.5) * (1.0 / 2147483648.0);
+    double u2 = ((double)w[1] + 0.5) * (1.0 / 4294967296.0);
+    double th = lat->th[mu + (long)lat->d * site];
+    double thn = wrap(th + lat->delta * (2.0 * u1 - 1.0));
+    double dl = lat->beta * ((ar * cos(thn) - ai * sin(thn)) - (ar * cos(th) - ai * sin(th)));
+    if (dl >= 0.0 || u2 < exp(dl)) lat->th[mu + (long)lat->d * site] = thn;
+}
+
+void orc_set_update(orc_lattice* lat, int kind, double delta)
+{
+    lat->stoch = kind;
+    lat->delta = delta;
+}
+
 void orc_overrelax_link(orc_lattice* lat, long site, int mu)
 {
     double ar, ai;
@@ -283,6 +315,8 @@ void orc_phase(orc_lattice* lat, int kind, int mu, int parity, int tau)
         if (frozen(lat, site, mu, tau)) continue;
         if (kind == 0)
             orc_heatbath_link(lat, site, mu);
+        else if (kind == 2)
+            orc_metropolis_link(lat, site, mu);
         else
             orc_overrelax_link(lat, site, mu);
     }
@@ -293,14 +327,15 @@ void orc_pass(orc_lattice* lat, int kind, int tau)
 {
     for (int mu = 0; mu < lat->d; ++mu)
         for (int p = 0; p < 2; ++p) orc_phase(lat, kind, mu, p, tau);
-    if (kind == 0) lat->upd++;
+    if (kind == 0 || kind == 2) lat->upd++;
 }
 
-/* One sweep: a heatbath pass followed by n_or overrelaxation passes. */
+/* One sweep: a stochastic pass (heatbath, or Metropolis after
+ * orc_set_update) followed by n_or overrelaxation passes. */
 void orc_sweeps(orc_lattice* lat, int n, int n_or, int tau)
 {
     for (int i = 0; i < n; ++i) {
-        orc_pass(lat, 0, tau);
+        orc_pass(lat, lat->stoch, tau);
         for (int k = 0; k < n_or; ++k) orc_pass(lat, 1, tau);
     }
 }

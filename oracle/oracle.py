@@ -73,6 +73,8 @@ def lib():
         L.orc_staple.argtypes = [vp, lng, i32, pd, pd]
         L.orc_heatbath_link.argtypes = [vp, lng, i32]
         L.orc_overrelax_link.argtypes = [vp, lng, i32]
+        L.orc_metropolis_link.argtypes = [vp, lng, i32]
+        L.orc_set_update.argtypes = [vp, i32, dbl]
         L.orc_phase.argtypes = [vp, i32, i32, i32, i32]
         L.orc_pass.argtypes = [vp, i32, i32]
         L.orc_sweeps.argtypes = [vp, i32, i32, i32]
@@ -212,6 +214,14 @@ class Lattice:
 
     def overrelax_link(self, site: int, mu: int):
         lib().orc_overrelax_link(self._h, site, mu)
+
+    def metropolis_link(self, site: int, mu: int):
+        lib().orc_metropolis_link(self._h, site, mu)
+
+    def set_update(self, kind: int, delta: float = 0.0):
+        """Stochastic update of sweeps and multilevel: 0 heatbath, 2 Metropolis
+        with proposal step delta (the paper's update, Sec. II)."""
+        lib().orc_set_update(self._h, kind, delta)
 
     def phase(self, kind: int, mu: int, parity: int, tau: int = 0):
         lib().orc_phase(self._h, kind, mu, parity, tau)

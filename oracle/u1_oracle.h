@@ -63,14 +63,21 @@ void orc_staple(const orc_lattice* lat, long site, int mu, double* are, double* 
 /* Single-link updates (heatbath uses the lattice's current update counter). */
 void orc_heatbath_link(orc_lattice* lat, long site, int mu);
 void orc_overrelax_link(orc_lattice* lat, long site, int mu);
+/* Metropolis with step delta (the lattice's current counter, domain METRO). */
+void orc_metropolis_link(orc_lattice* lat, long site, int mu);
+/* Stochastic update of sweeps: kind 0 heatbath (default), 2 Metropolis with
+ * proposal step delta. */
+void orc_set_update(orc_lattice* lat, int kind, double delta);
 
 /* One checkerboard phase: all links of direction mu and the given parity that
  * are not frozen at slab thickness tau (tau <= 1: nothing frozen).
- * kind 0 = heatbath, 1 = overrelaxation.  Does not touch the counter. */
+ * kind 0 = heatbath, 1 = overrelaxation, 2 = Metropolis.  Does not touch the
+ * counter. */
 void orc_phase(orc_lattice* lat, int kind, int mu, int parity, int tau);
 
-/* One pass (8 phases in d = 4) and one sweep (heatbath pass, then n_or
- * overrelaxation passes).  A heatbath pass increments the update counter. */
+/* One pass (8 phases in d = 4) and one sweep (stochastic pass, then n_or
+ * overrelaxation passes).  A heatbath or Metropolis pass increments the
+ * update counter. */
 void orc_pass(orc_lattice* lat, int kind, int tau);
 void orc_sweeps(orc_lattice* lat, int n, int n_or, int tau);
 

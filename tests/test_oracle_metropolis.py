@@ -1,0 +1,110 @@
+"""Oracle Metropolis update (the paper's own update, Sec. II), pinned to what
+the mathematics fixes:
+ - the single-link chain in a frozen environment has the von Mises
+   stationary law exp(beta |A| cos(theta + arg A)) (chi^2 on thinned samples);
+ - at beta = 0 every proposal is accepted;
+ - gauge covariance of a pass (decisions depend on gauge-invariant
+   Re(e^{i theta} A) only);
+ - full chains of Metropolis + 3 overrelaxation passes reproduce the exact 2D
+   torus plaquette (Bessel sums) and the 4D strong-coupling plaquette.
+"""
+import numpy as np
+import pytest
+from scipy import integrate, special
+from scipy.stats import chi2
+
+from helpers import exact2d as E
+from helpers.stats import batch_mean_err, circ_dist
+from test_oracle_update import _all_plaquettes, _gauge_transform
+
+
+def _lat(orc, d, L, beta, seed, delta, key_id=0):
+    lat = orc.Lattice(d, L, beta, seed=seed, key_id=key_id)
+    lat.init(1)
+    lat.set_update(2, delta)
+    return lat
+
+
+def test_metropolis_single_link_stationary_law(orc):
+    beta, delta = 1.1, np.pi
+    lat = _lat(orc, 4, [4, 4, 4, 4], beta, 41, delta)
+    site, mu = 53, 1
+    A = lat.staple(site, mu)
+    kappa = beta * abs(A)
+    lid = mu + 4 * site
+    n, thin = 120_000, 6
+    vals = []
+    for i in range(n):
+        lat.counter = i
+        lat.metropolis_link(site, mu)
+        if i % thin == 0 and i >= 1000:
+            vals.append(lat.links()[lid])
+    psi = (np.array(vals) + np.angle(A) + np.pi) % (2 * np.pi) - np.pi
+    edges = np.linspace(-np.pi, np.pi, 25)
+    norm = 2 * np.pi * special.ive(0, kappa)
+    f = lambda x: np.exp(kappa * (np.cos(x) - 1.0)) / norm
+    p = np.array([integrate.quad(f, edges[i], edges[i + 1])[0] for i in range(24)])
+    counts, _ = np.histogram(psi, bins=edges)
+    N = len(psi)
+    keep = p * N > 5
+    stat = np.sum((counts[keep] - p[keep] * N) ** 2 / (p[keep] * N))
+    assert chi2.sf(stat, keep.sum() - 1) > 1e-4, (stat, keep.sum())
+
+
+def test_metropolis_accepts_everything_at_beta_zero(orc):
+    lat = _lat(orc, 4, [4, 4, 4, 4], 0.0, 42, 0.7)
+    th0 = lat.links()
+    lat.phase(2, 0, 0)
+    changed = circ_dist(lat.links(), th0) > 0
+    # direction 0, even parity: exactly those links move, by at most delta
+    idx = np.arange(th0.size)
+    site, mu = idx // 4, idx % 4
+    L = 4
+    par = np.array([(s % L + (s // L) % L + (s // L**2) % L + s // L**3) % 2 for s in site])
+    target = (mu == 0) & (par == 0)
+    assert np.array_equal(changed, target)
+    assert np.max(circ_dist(lat.links(), th0)[target]) <= 0.7 + 1e-12
+
+
+@pytest.mark.parametrize("tau", [0, 2])
+def test_metropolis_gauge_covariance(orc, tau):
+    d, L, beta = 4, [4, 4, 4, 4], 1.0
+    lat1 = _lat(orc, d, L, beta, 43, 1.5, key_id=2)
+    lat1.sweeps(2)
+    th = lat1.links()
+    alpha = np.random.default_rng(5).uniform(-np.pi, np.pi, int(np.prod(L)))
+    lat2 = _lat(orc, d, L, beta, 43, 1.5, key_id=2)
+    lat2.set_links(_gauge_transform(d, L, th, alpha))
+    lat2.counter = lat1.counter
+    assert np.max(circ_dist(_all_plaquettes(lat2), _all_plaquettes(lat1))) < 1e-12
+    lat1.pass_(2, tau)
+    lat2.pass_(2, tau)
+    assert np.max(circ_dist(lat2.links(), _gauge_transform(d, L, lat1.links(), alpha))) < 1e-11
+
+
+def _series(orc, d, L, beta, delta, n_therm, n_meas, seed):
+    lat = orc.Lattice(d, L, beta, seed=seed)
+    lat.init(1)
+    lat.set_update(2, delta)
+    lat.sweeps(n_therm, 3)
+    vals = []
+    for _ in range(n_meas):
+        lat.sweeps(1, 3)
+        vals.append(lat.plaquette_means())
+    return np.array(vals)
+
+
+@pytest.mark.parametrize("L,beta", [([4, 4], 2.0), ([6, 4], 1.0)])
+def test_metropolis_2d_plaquette_exact(orc, L, beta):
+    vals = _series(orc, 2, L, beta, 1.5, 200, 20000, seed=44)[:, 0]
+    m, e = batch_mean_err(vals)
+    exact = E.plaquette(beta, L[0], L[1])
+    assert abs(m - exact) < 4 * e, (m, e, exact)
+
+
+def test_metropolis_4d_strong_coupling(orc):
+    beta = 0.2
+    vals = _series(orc, 4, [4, 4, 4, 4], beta, 2.0, 50, 1500, seed=45)
+    m, e = batch_mean_err(vals.mean(axis=1))
+    u = special.iv(1, beta) / special.iv(0, beta)
+    assert abs(m - u) < max(4 * e, 10 * u**5), (m, e, u)
