@@ -54,7 +54,14 @@ typedef enum {
 
 enum { U1ML_FP64 = 0, U1ML_FP32 = 1 };         /* link storage / update arithmetic */
 enum { U1ML_COLD = 0, U1ML_HOT = 1 };          /* start of u1ml_init_links         */
-enum { U1ML_HEATBATH = 0, U1ML_OVERRELAX = 1 }; /* update kind of u1ml_phase        */
+enum { U1ML_HEATBATH = 0, U1ML_OVERRELAX = 1, U1ML_METROPOLIS = 2 }; /* kind of u1ml_phase */
+
+/* Stochastic update of every sweep (u1ml_problem.update); the paper uses
+ * Metropolis (Sec. II).  Metropolis: one hit per link, proposal
+ * theta' = theta + metro_delta (2 U1 - 1), accepted when U2 < exp(beta
+ * (Re(e^{i theta'} A) - Re(e^{i theta} A))) with A the staple sum; U1, U2 from
+ * the Philox block (link id, counter, 0, 2) of the ensemble's key. */
+enum { U1ML_UPDATE_HEATBATH = 0, U1ML_UPDATE_METROPOLIS = 1 };
 
 /* How the insertion estimators are contracted (Sec. II.C.3 defines what is
  * computed; both forms give the same estimator up to FP64 rounding):
@@ -133,6 +140,8 @@ typedef struct {
     const int* comps;
     int max_configs;
     int form;
+    int update;          /* U1ML_UPDATE_* (0: heatbath)                      */
+    double metro_delta;  /* Metropolis proposal step, 0 < delta <= pi         */
 } u1ml_problem;
 
 /* Planner output (bytes of each workspace section, 256-byte aligned). */
@@ -188,8 +197,9 @@ u1ml_status u1ml_sweeps(u1ml_ctx* ctx, int n);
 
 /* Async.  One checkerboard phase: the links of direction mu and the given
  * parity that are not frozen at slab thickness tau (tau <= 1: none frozen),
- * updated with kind U1ML_HEATBATH or U1ML_OVERRELAX, using heatbath pass
- * counter (device counter + pass_offset).  Does not advance the counter. */
+ * updated with kind U1ML_HEATBATH, U1ML_OVERRELAX or U1ML_METROPOLIS (step
+ * metro_delta of the problem), using the stochastic pass counter (device
+ * counter + pass_offset).  Does not advance the counter. */
 u1ml_status u1ml_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int pass_offset);
 
 /* Async.  One multilevel configuration: the body of Algorithm 1 with the
@@ -258,7 +268,8 @@ u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau
 
 /* Algorithmic bytes moved by one launch of that phase under the streaming
  * model: every distinct link angle the phase reads once, every link it writes
- * once (heatbath 8 words per update, overrelaxation 9), all ensembles. */
+ * once (heatbath 8 words per update, overrelaxation and Metropolis 9), all
+ * ensembles. */
 u1ml_status u1ml_phase_bytes(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, double* bytes,
                              long* updates);
 

@@ -89,6 +89,7 @@ struct M<double> {
     __device__ static inline double atan2_(double y, double x) { return atan2(y, x); }
     __device__ static inline double acos_(double x) { return acos(x); }
     __device__ static inline double log_(double x) { return log(x); }
+    __device__ static inline double exp_(double x) { return exp(x); }
     __device__ static inline double sqrt_(double x) { return sqrt(x); }
     __device__ static inline double div_(double a, double b) { return a / b; }
     __device__ static inline double floor_(double x) { return floor(x); }
@@ -112,6 +113,7 @@ struct M<float> {
     __device__ static inline float atan2_(float y, float x) { return atan2_fast(y, x); }
     __device__ static inline float acos_(float x) { return acosf(x); }
     __device__ static inline float log_(float x) { return __logf(x); }
+    __device__ static inline float exp_(float x) { return __expf(x); }
     __device__ static inline float sqrt_(float x) { return __builtin_sqrtf(x); }
     __device__ static inline float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     __device__ static inline float floor_(float x) { return floorf(x); }

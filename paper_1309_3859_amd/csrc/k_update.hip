@@ -62,7 +62,8 @@ struct Nu {  // K-th direction other than MU, ascending
 };
 
 // kind 0: heatbath theta = wrap(psi - arg A), psi ~ vonMises(0, beta |A|);
-// kind 1: overrelaxation theta = wrap(-theta - 2 arg A) (unchanged if A = 0).
+// kind 1: overrelaxation theta = wrap(-theta - 2 arg A) (unchanged if A = 0);
+// kind 2: Metropolis (the paper's update), one hit per link.
 // Staple sum A = sum_{nu != mu} exp(i phi_f) + exp(i phi_b), nu ascending,
 // forward before backward, phi_f = v0 - v1 - v2, phi_b = v3 - v4 - v5.
 //
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
         gather_plane<real, MU, Nu<MU, 2>::v>(lb, vh, g, c, cpm, parity, v[2]);
         const unsigned self = ((MU * 2 + parity) * vh + (unsigned)(xh + c.hrow)) * (unsigned)sizeof(real);
         real old = real(0);
-        if (KIND == 1) old = ldo(lb, self);
+        if (KIND != 0) old = ldo(lb, self);
         real* dst = reinterpret_cast<real*>(reinterpret_cast<char*>(lb) + self);
 
         real ar = real(0), ai = real(0);
@@ -171,6 +172,19 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
                 if (na < 0) return;
                 *dst = wrap_angle<real>(psi - phiA);
             }
+        } else if (KIND == 2) {
+            // Metropolis: theta' = theta + delta (2 U1 - 1), accepted when
+            // U2 < exp(beta (Re(e^{i theta'} A) - Re(e^{i theta} A)))
+            const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
+            const uint32_t ctr = upd[E.res_index] + (uint32_t)pass_offset;
+            const Block4 b = philox4x32_10(lid, ctr, 0u, DOM_METRO, E.seed, E.key_id);
+            using m = M<real>;
+            const real thn = wrap_angle<real>(old + (real)E.metro_delta * (real(2) * m::u1(b.w[0]) - real(1)));
+            real sn, cn, so, co;
+            m::sincos_(thn, &sn, &cn);
+            m::sincos_(old, &so, &co);
+            const real dl = (real)E.beta * ((ar * cn - ai * sn) - (ar * co - ai * so));
+            if (dl >= real(0) || m::u2(b.w[1]) < m::exp_(dl)) *dst = thn;
         } else {
             if (ar == real(0) && ai == real(0)) return;
             const real phiA = M<real>::atan2_(ai, ar);
@@ -251,16 +265,23 @@ hipError_t launch_update(const EnsDesc* d_ens, const int2* d_bmap, int total_blo
     if ((ev_start == nullptr) != (ev_stop == nullptr)) return hipErrorInvalidValue;
     const dim3 g(total_blocks), b(block);
     const float inv_tm1 = tau > 1 ? 1.0f / (float)(tau - 1) : 1.0f;
+    if (kind < 0 || kind > 2) return hipErrorInvalidValue;
     if (precision == 0) {
+        double* lk = (double*)links;
         if (kind == 0)
-            launch_update_t<double, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, (double*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<double, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+        else if (kind == 1)
+            launch_update_t<double, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else
-            launch_update_t<double, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, (double*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<double, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
     } else {
+        float* lk = (float*)links;
         if (kind == 0)
-            launch_update_t<float, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, (float*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<float, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+        else if (kind == 1)
+            launch_update_t<float, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else
-            launch_update_t<float, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, (float*)links, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<float, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
     }
     return hipGetLastError();
 }

@@ -71,6 +71,8 @@ struct Problem {
     std::vector<int> comps;
     int max_configs = 1;
     int form_req = U1ML_FORM_AUTO;
+    int update = U1ML_UPDATE_HEATBATH;
+    double metro_delta = 1.0;
     // derived
     int tau_i = 2, n_i = 1, k_i = 1, tau_o = 2, n_o = 1, k_o = 0;
     bool two = false;
@@ -92,6 +94,12 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
     if (p->n_ens < 1 || !p->ens) return fail(err, "n_ens must be >= 1 with a non-NULL ensemble array");
     if (p->precision != U1ML_FP64 && p->precision != U1ML_FP32) return fail(err, "precision must be 0 (FP64) or 1 (FP32)");
     if (p->n_or < 0) return fail(err, "n_or must be >= 0");
+    if (p->update != U1ML_UPDATE_HEATBATH && p->update != U1ML_UPDATE_METROPOLIS)
+        return fail(err, "update must be 0 (heatbath) or 1 (Metropolis)");
+    if (p->update == U1ML_UPDATE_METROPOLIS && !(p->metro_delta > 0.0 && p->metro_delta <= M_PI))
+        return fail(err, "metro_delta must satisfy 0 < delta <= pi");
+    P->update = p->update;
+    P->metro_delta = p->metro_delta;
     if (p->n_levels < 1 || p->n_levels > 2) return fail(err, "n_levels must be 1 or 2");
     if (p->max_configs < 1) return fail(err, "max_configs must be >= 1");
     P->n_ens = p->n_ens;
@@ -675,10 +683,12 @@ hipError_t enq_pass(u1ml_ctx* c, const Lane& L, hipStream_t st, int kind, int ta
     return hipSuccess;
 }
 
-// one sweep: heatbath pass with counter offset hb, then n_or overrelaxation passes
+// one sweep: stochastic pass (heatbath or Metropolis) with counter offset hb,
+// then n_or overrelaxation passes
 hipError_t enq_sweep(u1ml_ctx* c, const Lane& L, hipStream_t st, int tau, int hb)
 {
-    hipError_t e = enq_pass(c, L, st, U1ML_HEATBATH, tau, hb);
+    const int stoch = c->P.update == U1ML_UPDATE_METROPOLIS ? U1ML_METROPOLIS : U1ML_HEATBATH;
+    hipError_t e = enq_pass(c, L, st, stoch, tau, hb);
     for (int k = 0; e == hipSuccess && k < c->P.n_or; ++k) e = enq_pass(c, L, st, U1ML_OVERRELAX, tau, hb);
     return e;
 }
@@ -884,7 +894,7 @@ void phase_words(const u1ml_ensemble& E, int kind, int mu, int parity, int tau, 
                     if (mu < 3 && tau > 1 && t % tau == 0) continue;
                     ++u;
                     int c[4] = {x, y, z, t};
-                    if (kind == 1) rd[(size_t)(mu + 4 * sid(c))] = 1;
+                    if (kind != 0) rd[(size_t)(mu + 4 * sid(c))] = 1;
                     for (int nu = 0; nu < 4; ++nu) {
                         if (nu == mu) continue;
                         int a[4], b[4], d[4], f[4];
@@ -1028,6 +1038,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         E.inv_slice = 1.0f / (float)(E.nxh * E.ny * E.nz);
         E.beta = U.beta;
         E.sqrt_beta = std::sqrt(U.beta);
+        E.metro_delta = P.metro_delta;
         E.seed = U.seed;
         E.key_id = U.key_id;
         E.link_off = (long long)c->S.links[e];
@@ -1246,7 +1257,7 @@ u1ml_status u1ml_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int
 {
     if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
     if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
-    if ((kind != 0 && kind != 1) || mu < 0 || mu > 3 || (parity != 0 && parity != 1) || pass_offset < 0)
+    if ((kind < 0 || kind > 2) || mu < 0 || mu > 3 || (parity != 0 && parity != 1) || pass_offset < 0)
         return set_err(ctx, U1ML_EINVAL, "bad phase arguments");
     bool ok;
     update_class(ctx, mu, tau, &ok);
@@ -1434,7 +1445,7 @@ u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau
 u1ml_status u1ml_phase_bytes(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, double* bytes, long* updates)
 {
     if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
-    if (!bytes || !updates || mu < 0 || mu > 3 || (parity & ~1) || (kind & ~1))
+    if (!bytes || !updates || mu < 0 || mu > 3 || (parity & ~1) || kind < 0 || kind > 2)
         return set_err(ctx, U1ML_EINVAL, "bad arguments");
     const double word = ctx->P.precision == U1ML_FP64 ? 8.0 : 4.0;
     double b = 0;

@@ -19,6 +19,7 @@ struct EnsDesc {
     int pad0, pad1;
     float inv_nxh, inv_ny, inv_slice, pad3;  // 1/(Nx/2), 1/Ny, 1/((Nx/2) Ny Nz) for division-free decode
     double beta, sqrt_beta;
+    double metro_delta;  // Metropolis proposal step
     uint32_t seed, key_id;
     long long link_off;
     long long hc_off, ho_off;

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libu1ml.so")
 
 FP64, FP32 = 0, 1
 COLD, HOT = 0, 1
-HEATBATH, OVERRELAX = 0, 1
+HEATBATH, OVERRELAX, METROPOLIS = 0, 1, 2
+UPDATE_HEATBATH, UPDATE_METROPOLIS = 0, 1
 FORM_AUTO, FORM_HISTORY, FORM_SPECTRAL = 0, 1, 2
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENOTSUP"}
 
@@ -51,6 +52,7 @@ class _Problem(C.Structure):
         ("n_levels", C.c_int), ("levels", _Level * 2), ("n_dirs", C.c_int), ("dirs", C.c_int * 3),
         ("n_r", C.c_int), ("r", C.POINTER(C.c_int)), ("n_probe", C.c_int), ("probes", C.POINTER(_Probe)),
         ("n_comp", C.c_int), ("comps", C.POINTER(C.c_int)), ("max_configs", C.c_int), ("form", C.c_int),
+        ("update", C.c_int), ("metro_delta", C.c_double),
     ]
 
 
@@ -155,6 +157,8 @@ class Spec:
     n_or: int = 3
     max_configs: int = 1
     form: int = 0  # FORM_AUTO
+    update: int = 0  # UPDATE_HEATBATH
+    metro_delta: float = 1.0
     _keep: list = field(default_factory=list, repr=False)
 
     def struct(self) -> _Problem:
@@ -182,6 +186,8 @@ class Spec:
         p.n_comp, p.comps = len(self.comps), cp
         p.max_configs = self.max_configs
         p.form = self.form
+        p.update = self.update
+        p.metro_delta = self.metro_delta
         return p
 
     def n_doubles_per_config(self) -> int:
