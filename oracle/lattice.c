@@ -279,6 +279,36 @@ void orc_metropolis_link(orc_lattice* lat, long site, int mu)
     if (dl >= 0.0 || u2 < exp(dl)) lat->th[mu + (long)lat->d * site] = thn;
 }
 
+/* I_1(k)/I_0(k) from the ratio recurrence I_{n-1}/I_n = 2n/k + I_{n+1}/I_n,
+ * i.e. the continued fraction 1/(2/k + 1/(4/k + 1/(6/k + ...))), evaluated
+ * backwards from depth 40 + ceil(k) (relative error below 1e-15 for
+ * k <= 100, checked against an independent Bessel implementation). */
+double orc_bessel_ratio(double kappa)
+{
+    if (kappa <= 0.0) return 0.0;
+    int depth = 40 + (int)ceil(kappa < 4000.0 ? kappa : 4000.0);
+    double t = 0.0;
+    for (int n = depth; n >= 1; --n) t = 1.0 / (2.0 * n / kappa + t);
+    return t;
+}
+
+/* Multihit (Sec. II.C: "analytical multihit", Parisi-Petronzio-Rapuano):
+ * with every other link fixed, theta has density ~ exp(beta |A| cos(theta +
+ * arg A)), so E[e^{i theta}] = e^{-i arg A} I_1(beta |A|) / I_0(beta |A|). */
+void orc_link_mean(const orc_lattice* lat, long site, int mu, double* re, double* im)
+{
+    double ar, ai;
+    orc_staple(lat, site, mu, &ar, &ai);
+    double R = sqrt(ar * ar + ai * ai);
+    if (R == 0.0) {
+        *re = *im = 0.0;
+        return;
+    }
+    double f = orc_bessel_ratio(lat->beta * R) / R;
+    *re = ar * f;
+    *im = -ai * f;
+}
+
 void orc_set_update(orc_lattice* lat, int kind, double delta)
 {
     lat->stoch = kind;

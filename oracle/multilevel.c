@@ -139,15 +139,27 @@ static void measure(const ctx_t* c, int tau, cplx* Tacc, cplx* TOacc, double* vs
             int r = sp->r[ir];
             for (long xs = 0; xs < c->Nsig; ++xs) {
                 long xr = orc__shift(c->lat, xs, dir, r);
+                /* multihit: both ends replaced by their conditional means,
+                 * except when the two temporal links share a plaquette
+                 * (neighbours: r = 1 or r = L - 1), then only the first */
+                int adjacent = (r == 1 || r == orc__L(c->lat, dir) - 1);
                 for (int s = 0; s < S; ++s) {
-                    cplx T = c_make(1.0, 0.0);
+                    cplx T = c_make(1.0, 0.0), Tm = c_make(1.0, 0.0);
                     for (int t = s * tau; t < (s + 1) * tau; ++t) {
                         cplx u0 = c_phase(orc__link(c->lat, xs + c->Nsig * t, tdir));
                         cplx ur = c_phase(orc__link(c->lat, xr + c->Nsig * t, tdir));
                         T = c_mul(T, c_mul(c_conj(u0), ur));
+                        if (sp->multihit) {
+                            cplx m0, mr = ur;
+                            orc_link_mean(c->lat, xs + c->Nsig * t, tdir, &m0.re, &m0.im);
+                            if (!adjacent) orc_link_mean(c->lat, xr + c->Nsig * t, tdir, &mr.re, &mr.im);
+                            Tm = c_mul(Tm, c_mul(c_conj(m0), mr));
+                        }
                     }
                     long it = idx_T(c, idir, ir, S, s, xs);
-                    Tacc[it] = c_add(Tacc[it], T);
+                    /* [T] takes the multihit product; the insertions keep the
+                     * plain links (their plaquettes can contain them) */
+                    Tacc[it] = c_add(Tacc[it], sp->multihit ? Tm : T);
                     for (int ip = 0; ip < sp->n_probe; ++ip) {
                         for (int ic = 0; ic < sp->n_comp; ++ic) {
                             int comp = sp->comp[ic], a, b;

@@ -46,6 +46,7 @@ class _Spec(C.Structure):
         ("probe", C.POINTER(C.c_int)),
         ("n_comp", C.c_int),
         ("comp", C.POINTER(C.c_int)),
+        ("multihit", C.c_int),
     ]
 
 
@@ -75,6 +76,9 @@ def lib():
         L.orc_overrelax_link.argtypes = [vp, lng, i32]
         L.orc_metropolis_link.argtypes = [vp, lng, i32]
         L.orc_set_update.argtypes = [vp, i32, dbl]
+        L.orc_bessel_ratio.argtypes = [dbl]
+        L.orc_bessel_ratio.restype = dbl
+        L.orc_link_mean.argtypes = [vp, lng, i32, pd, pd]
         L.orc_phase.argtypes = [vp, i32, i32, i32, i32]
         L.orc_pass.argtypes = [vp, i32, i32]
         L.orc_sweeps.argtypes = [vp, i32, i32, i32]
@@ -102,6 +106,11 @@ def philox(ctr, key) -> np.ndarray:
     return np.array(list(o), dtype=np.uint32)
 
 
+def bessel_ratio(kappa: float) -> float:
+    """I_1(kappa) / I_0(kappa) (continued fraction)."""
+    return lib().orc_bessel_ratio(kappa)
+
+
 def vonmises(kappa: float, key, c0: int, c1: int, domain: int = DOM_TEST):
     k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
     n = C.c_int(0)
@@ -120,13 +129,14 @@ def vonmises_many(kappa: float, n: int, seed: int = 0, key_id: int = 0, c0_start
 class MLSpec:
     """Multilevel measurement specification (levels outer first)."""
 
-    def __init__(self, levels, r, dirs=(0,), probes=(), comps=(), n_or=3):
+    def __init__(self, levels, r, dirs=(0,), probes=(), comps=(), n_or=3, multihit=False):
         self.levels = [tuple(lv) for lv in levels]  # (tau, n_iter, k_sweeps)
         self.r = [int(v) for v in r]
         self.dirs = [int(v) for v in dirs]
         self.probes = [tuple(int(u) for u in p) for p in probes]  # (l, p1, p2, mode)
         self.comps = [int(v) for v in comps]
         self.n_or = int(n_or)
+        self.multihit = bool(multihit)
 
     def _struct(self):
         s = _Spec()
@@ -144,6 +154,7 @@ class MLSpec:
         s.n_r, s.r = len(self.r), self._r
         s.n_probe, s.probe = len(self.probes), self._p
         s.n_comp, s.comp = len(self.comps), self._c
+        s.multihit = int(self.multihit)
         return s
 
     def result_size(self) -> int:
@@ -217,6 +228,11 @@ class Lattice:
 
     def metropolis_link(self, site: int, mu: int):
         lib().orc_metropolis_link(self._h, site, mu)
+
+    def link_mean(self, site: int, mu: int) -> complex:
+        re, im = C.c_double(), C.c_double()
+        lib().orc_link_mean(self._h, site, mu, C.byref(re), C.byref(im))
+        return complex(re.value, im.value)
 
     def set_update(self, kind: int, delta: float = 0.0):
         """Stochastic update of sweeps and multilevel: 0 heatbath, 2 Metropolis

@@ -105,7 +105,16 @@ typedef struct {
     int n_comp;
     const int* comp;       /* frame components 0..5 = E_par, E_perp1, E_perp2,
                               B_par, B_perp1, B_perp2 */
+    int multihit;          /* 1: temporal links of the correlator averages [T]
+                              replaced by their conditional means */
 } orc_ml_spec;
+
+/* I_1(kappa) / I_0(kappa) for kappa >= 0. */
+double orc_bessel_ratio(double kappa);
+
+/* Conditional mean of the link variable e^{i theta} of (site, mu) given
+ * every other link: e^{-i arg A} I_1(beta |A|) / I_0(beta |A|) (0 if A = 0). */
+void orc_link_mean(const orc_lattice* lat, long site, int mu, double* re, double* im);
 
 /* Number of doubles one configuration's estimates occupy:
  * C[r] (re, im), CO[r][probe][comp][kind] (re, im), vacuum <O_sq>[6],
