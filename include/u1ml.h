@@ -142,6 +142,13 @@ typedef struct {
     int form;
     int update;          /* U1ML_UPDATE_* (0: heatbath)                      */
     double metro_delta;  /* Metropolis proposal step, 0 < delta <= pi         */
+    int multihit;        /* 1: analytic multihit (Sec. II.C) of the temporal
+                            links in the correlator averages [T]: each link
+                            replaced by its conditional mean
+                            e^{-i arg A} I_1(beta|A|)/I_0(beta|A|); at
+                            separations whose temporal links share a
+                            plaquette (r = 1 or Ns - 1) only the first end;
+                            the insertion averages keep the plain links     */
 } u1ml_problem;
 
 /* Planner output (bytes of each workspace section, 256-byte aligned). */

@@ -117,6 +117,7 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st)
 // Measurement m of a configuration (one work-item per spatial site x and slab s
 // of the innermost level):
 //   hist_c[m_in][s][x]       = exp(i Theta_s(x)), Theta_s(x) = sum_{t in s} theta_t(x, t)
+//   (multihit) at hcm_off: prod_{t in s} of the temporal links' conditional means
 //   hist_o[m_in][s][2o+k][x] = sum_{t in s} O_k(P_o(x, t)); k = 0: 2 beta (1 - cos),
 //                              k = 1: sqrt(beta) sin, orientations o = P_xt, P_yt,
 //                              P_zt, P_yz, P_zx, P_xy
@@ -173,7 +174,7 @@ __device__ inline void block_sum12(const double* v, double* acc, int first)
     }
 }
 
-template <typename real>
+template <typename real, bool MULTIHIT>
 __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens, const int2* __restrict__ bmap,
                                                  const real* __restrict__ links, double2* __restrict__ hist_c,
                                                  real* __restrict__ hist_o, double* __restrict__ vac_part, int m_in,
@@ -198,6 +199,7 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
         const int z = yz / E.ny;
         const int y = yz - z * E.ny;
         double Th = 0.0;
+        double2 cm = make_double2(1.0, 0.0);  // multihit slab phase
         double os[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) os[k] = 0.0;
@@ -215,6 +217,15 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
             const real xz = L(0, q, cz), zx = L(2, q, cx);
             const real yx = L(1, q, cx), xy = L(0, q, cy);
             Th += (double)ut;
+            if (MULTIHIT) {
+                // conditional mean of the temporal link: e^{-i arg A} I1/I0(beta |A|)
+                real ar, ai;
+                staple_sum<real, 3>(lb, vh, g, c, (int)p, &ar, &ai);
+                const double R = sqrt((double)ar * (double)ar + (double)ai * (double)ai);
+                const double f = R > 0.0 ? bessel_ratio(E.beta * R) / R : 0.0;
+                const double ur = (double)ar * f, ui = -(double)ai * f;
+                cm = make_double2(cm.x * ur - cm.y * ui, cm.x * ui + cm.y * ur);
+            }
             real th[6];
             th[0] = ux + tx_x - xt - ut;  // P_xt
             th[1] = uy + tx_y - yt - ut;  // P_yt
@@ -234,6 +245,7 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
         double sn, cs;
         sincos(Th, &sn, &cs);
         hist_c[E.hc_off + ((size_t)m_in * S + s) * nsig + xs] = make_double2(cs, sn);
+        if (MULTIHIT) hist_c[E.hcm_off + ((size_t)m_in * S + s) * nsig + xs] = cm;
         if (store_o) {
             // per-measurement slab sums are stored in the link precision; the sums
             // over measurements are formed in FP64 by the contraction
@@ -249,14 +261,26 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
 
 hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int precision, const void* links,
                           double2* hist_c, void* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
-                          hipStream_t st)
+                          int multihit, hipStream_t st)
 {
-    if (precision == 0)
-        hipLaunchKernelGGL(k_measure<double>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bmap,
-                           (const double*)links, hist_c, (double*)hist_o, vac_part, m_in, m, tau, store_o);
-    else
-        hipLaunchKernelGGL(k_measure<float>, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bmap,
-                           (const float*)links, hist_c, (float*)hist_o, vac_part, m_in, m, tau, store_o);
+    const dim3 g(total_blocks), b(256);
+    if (precision == 0) {
+        const double* l = (const double*)links;
+        if (multihit)
+            hipLaunchKernelGGL((k_measure<double, true>), g, b, 0, st, d_ens, d_bmap, l, hist_c, (double*)hist_o,
+                               vac_part, m_in, m, tau, store_o);
+        else
+            hipLaunchKernelGGL((k_measure<double, false>), g, b, 0, st, d_ens, d_bmap, l, hist_c, (double*)hist_o,
+                               vac_part, m_in, m, tau, store_o);
+    } else {
+        const float* l = (const float*)links;
+        if (multihit)
+            hipLaunchKernelGGL((k_measure<float, true>), g, b, 0, st, d_ens, d_bmap, l, hist_c, (float*)hist_o,
+                               vac_part, m_in, m, tau, store_o);
+        else
+            hipLaunchKernelGGL((k_measure<float, false>), g, b, 0, st, d_ens, d_bmap, l, hist_c, (float*)hist_o,
+                               vac_part, m_in, m, tau, store_o);
+    }
     return hipGetLastError();
 }
 
@@ -303,8 +327,11 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
     const int mc = E.con_mc;
     const int nmax = max(E.nx, max(E.ny, E.nz));
     const int row_len = mc * nmax;  // LDS elements per staged row of one line
+    const int nc_rows = O.multihit ? 2 : 1;  // plain phases, and multihit phases
     double2* cl = reinterpret_cast<double2*>(lds_raw) + (size_t)grp * row_len;
-    ot* ol = reinterpret_cast<ot*>(lds_raw + (size_t)lpb * row_len * sizeof(double2)) + (size_t)grp * 12 * row_len;
+    double2* clm = reinterpret_cast<double2*>(lds_raw) + (size_t)(lpb + grp) * row_len;
+    ot* ol = reinterpret_cast<ot*>(lds_raw + (size_t)nc_rows * lpb * row_len * sizeof(double2)) +
+             (size_t)grp * 12 * row_len;
 
     // transverse coordinates of the line; sites along it are `stride` apart
     const int a1 = line_ok ? line % n3[d1] : 0, a2 = line_ok ? line / n3[d1] : 0;
@@ -319,6 +346,7 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
     const int base = site0(0, 0);
     const size_t mstride = (size_t)S * nsig;
     const double2* hc = hist_c + E.hc_off + (size_t)s * nsig + base;
+    const double2* hcm = hist_c + E.hcm_off + (size_t)s * nsig + base;
     const double inv = 1.0 / (double)n_meas;
     const int nr = O.n_r, pairs = N * nr;
     const int npass = (pairs + G - 1) / G;
@@ -327,10 +355,10 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
     // carried from lane to lane + G without a division per element
     const int g_q = G / N, g_k = G - (G / N) * N;
     const int l_q = lane / N, l_k = lane - (lane / N) * N;
-    auto stage_c = [&](int m0, int mm) {
+    auto stage_rows = [&](const double2* src, double2* dst, int m0, int mm) {
         int q = l_q, k = l_k;
         for (int j = lane; j < mm * N; j += G) {
-            cl[q * N + k] = hc[(size_t)(m0 + q) * mstride + (size_t)k * stride];
+            dst[q * N + k] = src[(size_t)(m0 + q) * mstride + (size_t)k * stride];
             q += g_q;
             k += g_k;
             if (k >= N) {
@@ -339,19 +367,29 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
             }
         }
     };
+    auto stage_c = [&](int m0, int mm) { stage_rows(hc, cl, m0, mm); };
 
     for (int pass = 0; !INS && pass < npass; ++pass) {
         const int pr = pass * G + lane;
         const bool act = line_ok && pr < pairs;
         const int ir = act ? pr / N : 0;
         const int x = act ? pr - ir * N : 0;
-        int xr = x + rlist[ir];  // 1 <= r < N
+        const int r_ir = rlist[ir];  // 1 <= r < N
+        int xr = x + r_ir;
         if (xr >= N) xr -= N;
+        // multihit: both ends from the multihit phases, except neighbours on
+        // the periodic axis (their temporal links share plaquettes): there
+        // the far end keeps the plain phase
+        const double2* ca = O.multihit ? clm : cl;
+        const double2* cb = (O.multihit && r_ir != 1 && r_ir != N - 1) ? clm : cl;
         double tre = 0.0, tim = 0.0;
         for (int m0 = 0; m0 < n_meas; m0 += mc) {
             const int mm = min(mc, n_meas - m0);
             __syncthreads();
-            if (line_ok) stage_c(m0, mm);
+            if (line_ok) {
+                stage_c(m0, mm);
+                if (O.multihit) stage_rows(hcm, clm, m0, mm);
+            }
             __syncthreads();
             if (act) {
                 int q = 0;
@@ -359,8 +397,8 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
                     double2 a[4], b[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        a[u] = cl[(q + u) * N + x];
-                        b[u] = cl[(q + u) * N + xr];
+                        a[u] = ca[(q + u) * N + x];
+                        b[u] = cb[(q + u) * N + xr];
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -369,8 +407,8 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
                     }
                 }
                 for (; q < mm; ++q) {
-                    const double2 a = cl[q * N + x];
-                    const double2 b = cl[q * N + xr];
+                    const double2 a = ca[q * N + x];
+                    const double2 b = cb[q * N + xr];
                     tre += a.x * b.x + a.y * b.y;
                     tim += a.x * b.y - a.y * b.x;
                 }

@@ -35,32 +35,6 @@ struct LinkView {
     }
 };
 
-// The six angles of the two staples of link (x, MU) in the plane (MU, NU):
-//   v[0..2] = th_nu(x+mu), th_mu(x+nu), th_nu(x)          (forward)
-//   v[3..5] = th_nu(x-nu), th_nu(x+mu-nu), th_mu(x-nu)    (backward)
-// The angles of direction d and parity par start at element (2 d + par) vh.
-template <typename real, int MU, int NU>
-__device__ inline void gather_plane(const real* __restrict__ lb, unsigned vh, const Geo& g, const Site& c,
-                                    const Site& cpm, int p, real* v)
-{
-    const unsigned q = p ^ 1;
-    const Site cpn = mv<NU, +1>(c, g);
-    const Site cmn = mv<NU, -1>(c, g);
-    const Site cpmmn = mv<NU, -1>(cpm, g);
-    constexpr unsigned w = sizeof(real);
-    v[0] = ldo(lb, ((NU * 2 + q) * vh + hidx(cpm)) * w);
-    v[1] = ldo(lb, ((MU * 2 + q) * vh + hidx(cpn)) * w);
-    v[2] = ldo(lb, ((NU * 2 + p) * vh + hidx(c)) * w);
-    v[3] = ldo(lb, ((NU * 2 + q) * vh + hidx(cmn)) * w);
-    v[4] = ldo(lb, ((NU * 2 + p) * vh + hidx(cpmmn)) * w);
-    v[5] = ldo(lb, ((MU * 2 + q) * vh + hidx(cmn)) * w);
-}
-
-template <int MU, int K>
-struct Nu {  // K-th direction other than MU, ascending
-    static constexpr int v = K < MU ? K : K + 1;
-};
-
 // kind 0: heatbath theta = wrap(psi - arg A), psi ~ vonMises(0, beta |A|);
 // kind 1: overrelaxation theta = wrap(-theta - 2 arg A) (unchanged if A = 0);
 // kind 2: Metropolis (the paper's update), one hit per link.

@@ -72,6 +72,7 @@ struct Problem {
     int max_configs = 1;
     int form_req = U1ML_FORM_AUTO;
     int update = U1ML_UPDATE_HEATBATH;
+    bool multihit = false;
     double metro_delta = 1.0;
     // derived
     int tau_i = 2, n_i = 1, k_i = 1, tau_o = 2, n_o = 1, k_o = 0;
@@ -99,6 +100,8 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
     if (p->update == U1ML_UPDATE_METROPOLIS && !(p->metro_delta > 0.0 && p->metro_delta <= M_PI))
         return fail(err, "metro_delta must satisfy 0 < delta <= pi");
     P->update = p->update;
+    if (p->multihit != 0 && p->multihit != 1) return fail(err, "multihit must be 0 or 1");
+    P->multihit = p->multihit == 1;
     P->metro_delta = p->metro_delta;
     if (p->n_levels < 1 || p->n_levels > 2) return fail(err, "n_levels must be 1 or 2");
     if (p->max_configs < 1) return fail(err, "max_configs must be >= 1");
@@ -276,7 +279,9 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
         S->links.push_back(L / word);
         L = align_up(L + v);
         S->hc.push_back(HC);
-        if (!mul_ok((size_t)P.n_i * si, nsig, &t) || !add_ok(HC, t, &HC)) return fail(err, "size overflow (history)");
+        // plain slab phases, then (multihit) the multihit ones
+        if (!mul_ok((size_t)P.n_i * si * (P.multihit ? 2 : 1), nsig, &t) || !add_ok(HC, t, &HC))
+            return fail(err, "size overflow (history)");
         HC = align_up(HC * 16) / 16;
         S->ho.push_back(HO);
         if (store_o) {
@@ -717,7 +722,7 @@ hipError_t enq_levels(u1ml_ctx* c, const Lane& L, hipStream_t st, bool store_o, 
             for (int k = 0; e == hipSuccess && k < P.k_i; ++k) e = enq_sweep(c, L, st, P.tau_i, hb++);
             if (e == hipSuccess)
                 e = launch_measure(L.d_ens, L.d_mmap, L.tab_total(kTabMeas), P.precision, c->links, c->hc, c->ho,
-                                   c->vpart, m, ko * P.n_i + m, P.tau_i, store_o ? 1 : 0, st);
+                                   c->vpart, m, ko * P.n_i + m, P.tau_i, store_o ? 1 : 0, P.multihit ? 1 : 0, st);
         }
         if (e == hipSuccess)
             e = launch_contract(L.d_ens, L.tab_dev(kTabCon), n, L.tab_total(kTabCon), c->con_block, c->con_lds,
@@ -1043,6 +1048,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         E.key_id = U.key_id;
         E.link_off = (long long)c->S.links[e];
         E.hc_off = (long long)c->S.hc[e];
+        E.hcm_off = E.hc_off + (long long)P.n_i * E.s_in * E.nsig;
         E.ho_off = (long long)c->S.ho[e];
         E.at_off = (long long)c->S.at[e];
         E.ato_off = (long long)c->S.ato[e];
@@ -1064,6 +1070,8 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     O.n_comp = (int)P.comps.size();
     O.store_o = P.probes.empty() ? 0 : 1;
     O.n_groups = (int)(P.gdesc.size() / 2);
+    O.n_ens_total = n;
+    O.multihit = P.multihit ? 1 : 0;
     O.n_doubles_per_config = P.nd_cfg;
     std::vector<int> probe_flat;
     for (const u1ml_probe& p : P.probes) {
@@ -1092,7 +1100,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         EnsDesc& E = c->h_ens[e];
         const int n3[3] = {E.nx, E.ny, E.nz};
         const size_t nmax = (size_t)std::max(E.nx, std::max(E.ny, E.nz));
-        const size_t per = 16 + 12 * o_word;  // LDS bytes per (measurement, line site)
+        const size_t per = (P.multihit ? 32 : 16) + 12 * o_word;  // LDS bytes per (measurement, line site)
         E.con_lpb = c->con_block / group[e];
         const size_t fit = (size_t)kConLds / ((size_t)E.con_lpb * nmax * per);
         E.con_mc = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)P.n_i));

@@ -23,6 +23,7 @@ struct EnsDesc {
     uint32_t seed, key_id;
     long long link_off;
     long long hc_off, ho_off;
+    long long hcm_off;  // multihit slab phases (double2), [m][s][site], when multihit
     long long at_off, ato_off;
     long long ot_off, oto_off;
     long long vac_part_off;  // double, [n_vac_blocks][12][hi, lo]: running sums over the configuration's measurements
@@ -38,6 +39,7 @@ struct ObsDesc {
     int store_o;  // 1 if insertions are requested (history keeps O sums)
     int n_groups;  // probe groups sharing (l, mode) (spectral form)
     int n_ens_total;  // ensembles of the problem (rows of a results record)
+    int multihit;     // correlator averages from multihit slab phases
     long long n_doubles_per_config;
 };
 
@@ -72,7 +74,7 @@ hipError_t launch_scatter_links(const EnsDesc* d_ens, int ens, int precision, vo
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int precision, const void* links,
                           double2* hist_c, void* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
-                          hipStream_t st);
+                          int multihit, hipStream_t st);
 // work-groups of `block` threads, each holding E.con_lpb lines; lds_bytes of dynamic LDS
 hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
                            size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_probe,

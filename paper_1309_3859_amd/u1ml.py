@@ -52,7 +52,7 @@ class _Problem(C.Structure):
         ("n_levels", C.c_int), ("levels", _Level * 2), ("n_dirs", C.c_int), ("dirs", C.c_int * 3),
         ("n_r", C.c_int), ("r", C.POINTER(C.c_int)), ("n_probe", C.c_int), ("probes", C.POINTER(_Probe)),
         ("n_comp", C.c_int), ("comps", C.POINTER(C.c_int)), ("max_configs", C.c_int), ("form", C.c_int),
-        ("update", C.c_int), ("metro_delta", C.c_double),
+        ("update", C.c_int), ("metro_delta", C.c_double), ("multihit", C.c_int),
     ]
 
 
@@ -159,6 +159,7 @@ class Spec:
     form: int = 0  # FORM_AUTO
     update: int = 0  # UPDATE_HEATBATH
     metro_delta: float = 1.0
+    multihit: bool = False
     _keep: list = field(default_factory=list, repr=False)
 
     def struct(self) -> _Problem:
@@ -188,6 +189,7 @@ class Spec:
         p.form = self.form
         p.update = self.update
         p.metro_delta = self.metro_delta
+        p.multihit = int(bool(self.multihit))
         return p
 
     def n_doubles_per_config(self) -> int:

@@ -70,3 +70,32 @@ def test_set_lanes_rejects_single_ensemble(u1):
     with pytest.raises(u1.U1MLError):
         ctx.set_lanes(2)
     ctx.set_lanes(1)
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_results_ring_keeps_every_configuration(u1, lanes):
+    """Three configurations left in the device ring equal the same three
+    configurations copied out one at a time (every ring slot holds its own
+    record, for every ensemble of the batch)."""
+    mk = lambda cap: _spec(u1, [(2, 2, 1)], 1)
+    a = mk(3)
+    a.max_configs = 3
+    ca = u1.Context(a)
+    ca.set_lanes(lanes)
+    ca.init_links(u1.HOT)
+    for _ in range(3):
+        ca.multilevel()
+    ring = ca.results()
+    b = mk(1)
+    b.max_configs = 1
+    cb = u1.Context(b)
+    cb.set_lanes(lanes)
+    cb.init_links(u1.HOT)
+    one = []
+    for _ in range(3):
+        cb.multilevel()
+        one.append(cb.results()[0])
+    assert ring.shape[0] == 3
+    for k in range(3):
+        assert np.array_equal(ring[k], one[k]), k
+    assert not np.array_equal(one[0], one[1])
