@@ -202,3 +202,36 @@ def fit_width(r, w2, T, err=None, d: int = 4, p0=(0.2, 0.5)):
     popt, _ = curve_fit(f, np.asarray(r, float), np.asarray(w2, float), p0=p0,
                         sigma=None if err is None else np.asarray(err, float), maxfev=20000)
     return {"sigma": popt[0], "rho0": popt[1]}
+
+
+# ---------------------------------------------------------------------------
+# Plaquette susceptibility and its peak (the paper locates beta_c at the peak
+# of the plaquette susceptibility on 24^3 x 4, Sec. II.D and III.A).
+# ---------------------------------------------------------------------------
+def plaquette_susceptibility(series, n_plaquettes: int, n_blocks: int = 20):
+    """chi = N_P (<P^2> - <P>^2) of the lattice-averaged plaquette P of each
+    configuration (series[i]), with a blocked jackknife error (blocks of
+    consecutive configurations absorb the autocorrelation)."""
+    x = np.asarray(series, float)
+    n = len(x) // n_blocks * n_blocks
+    blocks = x[:n].reshape(n_blocks, -1)
+
+    def est(b):
+        v = b.reshape(-1)
+        return n_plaquettes * (np.mean(v * v) - np.mean(v) ** 2)
+
+    return jackknife(blocks, est)
+
+
+def peak_position(betas, chi, n_points: int = 5):
+    """Vertex of the parabola fitted (least squares) through the n_points
+    values of chi(beta) around its largest one."""
+    b = np.asarray(betas, float)
+    c = np.asarray(chi, float)
+    order = np.argsort(b)
+    b, c = b[order], c[order]
+    i = int(np.argmax(c))
+    lo = max(0, min(i - n_points // 2, len(b) - n_points))
+    bb, cc = b[lo:lo + n_points], c[lo:lo + n_points]
+    a2, a1, _ = np.polyfit(bb, cc, 2)
+    return float(-a1 / (2 * a2))

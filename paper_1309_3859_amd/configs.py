@@ -75,4 +75,24 @@ def c5_largest(n_outer: int = 40, n_inner: int = 100, full_map: bool = True, max
     return spec, {"start": HOT, "therm": 2000}
 
 
+def in_plane_map(r: int = 6, margin: int = 3, width: int = 4, ns: int = 24, nt: int = 8, beta: float = 0.99,
+                 n_inner: int = 100, max_configs: int = 1):
+    """The field in the plane containing the charges (the paper's Fig. 1):
+    probes (l, p1, 0) for l = -margin .. r + margin along the axis and
+    p1 = -width .. width across it, E_par and E_perp1, one level tau = 2,
+    FP32 links.  Every l is its own probe group in the spectral form."""
+    probes = [(l, p1, 0, 0) for l in range(-margin, r + margin + 1) for p1 in range(-width, width + 1)]
+    spec = Spec(ensembles=[Ens((ns, ns, ns), nt, beta, seed=6, key_id=0)], levels=[(2, n_inner, 1)], r=[r],
+                dirs=[0], probes=probes, comps=[0, 1], precision=FP32, n_or=3, max_configs=max_configs)
+    return spec, {"start": HOT, "therm": 500}
+
+
+def beta_scan(betas, ns: int = 24, nt: int = 4, precision: int = FP32):
+    """One batch of ensembles Ns^3 x Nt at the given couplings (plaquette
+    susceptibility scan for beta_c); ensemble j has Philox key (7, j)."""
+    ens = [Ens((ns, ns, ns), nt, float(b), seed=7, key_id=j) for j, b in enumerate(betas)]
+    spec = Spec(ensembles=ens, levels=[(2, 1, 1)], r=[1], precision=precision, n_or=3)
+    return spec, {"start": HOT, "therm": 500}
+
+
 PRESETS = {"c1": c1_plain_fp64, "c2": c2_fp32_profiles, "c3": c3_precision, "c4": c4_batched, "c5": c5_largest}

@@ -118,3 +118,20 @@ def test_string_width_limits():
     w2 = A.width2_string(rr, 0.18, 0.4, 1 / 8.0)
     fit = A.fit_width(rr, w2, 1 / 8.0)
     assert abs(fit["sigma"] - 0.18) < 1e-6 and abs(fit["rho0"] - 0.4) < 1e-6
+
+
+def test_plaquette_susceptibility_estimator():
+    rng = np.random.default_rng(3)
+    x = rng.normal(0.6, 0.01, 4000)
+    chi, err = A.plaquette_susceptibility(x, 1000, n_blocks=20)
+    assert abs(chi - 1000 * x.var()) < 1e-9
+    assert 0 < err < 0.2 * chi
+    # the sample variance of i.i.d. draws estimates sigma^2: chi ~ N sigma^2
+    assert abs(chi - 1000 * 1e-4) < 5 * err
+
+
+def test_peak_position():
+    b = np.linspace(0.95, 1.05, 11)
+    assert abs(A.peak_position(b, 3.0 - 40 * (b - 1.003) ** 2) - 1.003) < 1e-12
+    g = np.exp(-((b - 1.012) / 0.03) ** 2)
+    assert abs(A.peak_position(b, g, n_points=3) - 1.012) < 2e-3
