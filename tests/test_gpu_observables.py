@@ -4,8 +4,10 @@
    spectral forms, one measurement without updates, against the oracle on the
    same links (FP64 1e-12);
  - a batched coupling scan: the plaquette susceptibility of each ensemble of
-   one batch from the per-sweep plaquettes; at beta = 1 it agrees with the
-   oracle's own chain within 4 combined standard errors.
+   one batch from the per-sweep plaquettes; at beta = 0.9 (away from the
+   small volume's pseudo-critical region, where tunnelling makes short-chain
+   estimates of chi unreliable) it agrees with the oracle's own chain within
+   4 combined standard errors.
 """
 import sys
 
@@ -66,14 +68,14 @@ def test_beta_scan_susceptibility(env):
     ctx = u1.Context(spec)
     ctx.init_links(u1.HOT)
     ctx.sweeps(100)
-    n, n_plaq = 800, 6 * 4 ** 4
+    n, n_plaq = 1500, 6 * 4 ** 4
     series = np.empty((n, len(betas)))
     for i in range(n):
         ctx.sweeps(1)
         series[i] = ctx.plaquette().mean(axis=1)
     chi = [A.plaquette_susceptibility(series[:, j], n_plaq) for j in range(len(betas))]
     say("GPU chi", chi)
-    ref = O.Lattice(4, [4, 4, 4, 4], 1.0, seed=7, key_id=1)
+    ref = O.Lattice(4, [4, 4, 4, 4], 0.9, seed=7, key_id=0)
     ref.init(1)
     ref.sweeps(100)
     os_ = np.empty(n)
@@ -81,7 +83,7 @@ def test_beta_scan_susceptibility(env):
         ref.sweeps(1)
         os_[i] = ref.plaquette_means().mean()
     c_ref, e_ref = A.plaquette_susceptibility(os_, n_plaq)
-    say("oracle chi(1.0)", c_ref, e_ref)
-    c_gpu, e_gpu = chi[1]
+    say("oracle chi(0.9)", c_ref, e_ref)
+    c_gpu, e_gpu = chi[0]
     assert abs(c_gpu - c_ref) < 4 * np.hypot(e_gpu, e_ref)
     assert all(c > 0 for c, _ in chi)
