@@ -138,6 +138,28 @@ def time_steps(ctx, steps: int, warmup: int):
     return ms
 
 
+def copy_reference(nbytes: float, reps: int = 50):
+    """A plain device copy moving the same number of bytes as one launch of
+    the dominant kernel (half read, half written), timed with events: the
+    bandwidth a kernel of this size can reach on the part, for context."""
+    import torch
+
+    n = int(nbytes // 2)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) * 1e3 / reps
+    return {"bytes": 2 * n, "us_per_copy": us, "GB/s": 2 * n / (us * 1e-6) / 1e9}
+
+
 def run_counter_workload(spec, sched):
     """Kernels for rocprofv3 --pmc runs: a plain copy of 2^28 bytes (its
     FETCH_SIZE / WRITE_SIZE give the counters' scale), then the inner-slab
@@ -226,6 +248,7 @@ def main():
         # per launch of each phase over the whole batch; MET = the paper's Metropolis update
         "phases_us": {f"{('HB', 'OR', 'MET')[k]}_mu{m}": v[0] for (k, m), v in per_phase.items()},
     }
+    line["roofline"]["copy_reference"] = copy_reference(b)
     if not args.no_fp64 and spec.precision == u1ml.FP32:
         # the same workload with FP64 link storage and update arithmetic
         spec64, _ = make()

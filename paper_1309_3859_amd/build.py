@@ -3,7 +3,8 @@
     python -m paper_1309_3859_amd.build        # or build() from Python
 
 Every source is compiled for gfx950 only, with packed-FP32 instruction
-selection disabled, and linked into paper_1309_3859_amd/libu1ml.so.
+selection disabled and floating-point contraction limited to single source
+expressions, and linked into paper_1309_3859_amd/libu1ml.so.
 """
 from __future__ import annotations
 
@@ -24,6 +25,9 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Wall",
+    # multiply-adds fused only within one source expression, so every
+    # instantiation of a kernel template rounds the same way
+    "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
