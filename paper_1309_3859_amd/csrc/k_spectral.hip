@@ -40,6 +40,22 @@ __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x *
 __device__ inline int orient_of(int c, int dir) { return c < 3 ? (dir + c) % 3 : 3 + (dir + c - 3) % 3; }
 __device__ inline bool spans_axis(int c) { return c == 0 || c == 4 || c == 5; }
 
+// Position of site xs = x + nx (y + ny z) in the plane-major order of charge
+// axis dir: (x_par n1 + u) n2 + v, with (x_par, u, v) the coordinates along
+// (dir, d1, d2), d1 = dir + 1 and d2 = dir + 2 (mod 3); each plane x_par is
+// then one contiguous run of n1 n2 sites.
+__device__ inline int plane_index(int xs, int dir, int nx, int ny, int nz)
+{
+    const int x = xs % nx, yz = xs / nx;
+    const int y = yz % ny, z = yz / ny;
+    const int xp = dir == 0 ? x : dir == 1 ? y : z;
+    const int u = dir == 0 ? y : dir == 1 ? z : x;
+    const int v = dir == 0 ? z : dir == 1 ? x : y;
+    const int n1 = dir == 0 ? ny : dir == 1 ? nz : nx;
+    const int n2 = dir == 0 ? nz : dir == 1 ? nx : ny;
+    return (xp * n1 + u) * n2 + v;
+}
+
 struct dds {
     double hi, lo;
 };
@@ -59,7 +75,8 @@ __device__ inline dds dds_add(dds a, double b)
 // Weights.  One work-item per (ensemble, axis, r, x); it writes every slab.
 //   k_wfac: W[axis, r][S][x] = prod_{S' != S} scale * out_t[axis, r][S'][x]
 //   k_gfac: G[axis, r][s][x] = W_S(x) prod_{s' in S, s' != s} avg_t[axis, r][s'][x]
-//           (q thin slabs per thick slab, q = 0 for all slabs; W = 1 when wf is null)
+//           (q thin slabs per thick slab, q = 0 for all slabs; W = 1 when wf is null),
+//           stored in the plane-major order of the axis (plane_index)
 // Products run over ascending slab index.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_wfac(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
@@ -100,6 +117,7 @@ __global__ void __launch_bounds__(256) k_gfac(const EnsDesc* __restrict__ ens, c
     const int xs = (int)(item % nsig);
     const long long idr = item / nsig;
     const int qq = q > 0 ? q : Si;  // q = 0: one thick slab of every slab (one level)
+    const int pidx = plane_index(xs, obs->dirs[idr / obs->n_r], E.nx, E.ny, E.nz);
     for (int s = 0; s < Si; ++s) {
         const int S = s / qq;
         double2 g = wf ? wf[E.wf_off + ((size_t)idr * So + S) * nsig + xs] : make_double2(1.0, 0.0);
@@ -107,7 +125,7 @@ __global__ void __launch_bounds__(256) k_gfac(const EnsDesc* __restrict__ ens, c
             if (s2 == s) continue;
             g = cmul(g, avg_t[E.at_off + ((size_t)idr * Si + s2) * nsig + xs]);
         }
-        gf[E.gf_off + ((size_t)idr * Si + s) * nsig + xs] = g;
+        gf[E.gf_off + ((size_t)idr * Si + s) * nsig + pidx] = g;
     }
 }
 
@@ -157,21 +175,229 @@ __device__ inline void dft_axis(const double2* __restrict__ in, int na, int nc, 
 }
 
 // ---------------------------------------------------------------------------
+// Mixed-radix FFT along one axis of a plane in LDS (Stockham autosort, radices
+// 4, 2, 3, 5 in that order; Cooley & Tukey 1965, Stockham 1966).  Stage with
+// radix R after the radices so far have product Ns: butterfly j of a sequence
+// of length n takes the R inputs j + r n/R, multiplies input r by
+// w^(r (j mod Ns) n/(Ns R)), forms their length-R transform and writes output
+// q to (j div Ns) Ns R + (j mod Ns) + q Ns; after the last stage the sequence
+// holds its transform in natural order.  w = exp(sg 2 pi i / n) comes from the
+// table tw (n entries), so the forward and the conjugate kernel share the
+// code.  Results differ from the direct sum only by rounding, and are the same
+// for every launch shape.
+// ---------------------------------------------------------------------------
+struct FftPlan {
+    int c4, c2, c3, c5;  // stages of each radix, applied in this order
+    int n_st;            // total, 0 if n has a prime factor above 5
+};
+
+__device__ inline FftPlan fft_plan(int n)
+{
+    FftPlan p{0, 0, 0, 0, 0};
+    while (n % 4 == 0) { ++p.c4; n /= 4; }
+    while (n % 2 == 0) { ++p.c2; n /= 2; }
+    while (n % 3 == 0) { ++p.c3; n /= 3; }
+    while (n % 5 == 0) { ++p.c5; n /= 5; }
+    p.n_st = n == 1 ? p.c4 + p.c2 + p.c3 + p.c5 : 0;
+    return p;
+}
+
+// One stage over `rows` sequences: element i of sequence q at src[q sq + i se],
+// written to dst[q dq + i de].  Consecutive work-items take consecutive
+// butterflies of one sequence when the elements of a sequence are adjacent
+// (se = 1), else the same butterfly of consecutive sequences (sq = 1), so the
+// 16-byte LDS accesses of a wave stay on distinct banks and the last stage's
+// global stores are contiguous.
+template <int R>
+__device__ inline void fft_stage(const double2* __restrict__ src, int sq, int se, double2* __restrict__ dst, int dq,
+                                 int de, int n, int rows, int Ns, const double2* __restrict__ tw, double sg)
+{
+    const int m = n / R;
+    const int tstep = n / (Ns * R);
+    const int total = rows * m;
+    const bool qfast = se != 1;
+    for (int b = threadIdx.x; b < total; b += blockDim.x) {
+        const int q = qfast ? b % rows : b / m;
+        const int j = qfast ? b / rows : b - q * m;
+        const int k = j % Ns;
+        double2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = src[q * sq + (j + r * m) * se];
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * tstep]);  // r k tstep < n
+        double2 V[R];
+        if (R == 2) {
+            V[0] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
+            V[1] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
+        } else if (R == 4) {
+            // w_4 = sg i: w z = sg (-z.y, z.x)
+            const double2 a = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+            const double2 c = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+            const double2 bb = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+            const double2 d = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+            const double2 wd = make_double2(-sg * d.y, sg * d.x);
+            V[0] = make_double2(a.x + bb.x, a.y + bb.y);
+            V[1] = make_double2(c.x + wd.x, c.y + wd.y);
+            V[2] = make_double2(a.x - bb.x, a.y - bb.y);
+            V[3] = make_double2(c.x - wd.x, c.y - wd.y);
+        } else {
+            const int nr = n / R;
+#pragma unroll
+            for (int qq = 0; qq < R; ++qq) {
+                double2 acc = v[0];
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const double2 w = tw[((r * qq) % R) * nr];
+                    acc.x += v[r].x * w.x - v[r].y * w.y;
+                    acc.y += v[r].x * w.y + v[r].y * w.x;
+                }
+                V[qq] = acc;
+            }
+        }
+        const int idx = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int qq = 0; qq < R; ++qq) dst[q * dq + (idx + qq * Ns) * de] = V[qq];
+    }
+}
+
+// The whole FFT along one axis: input in LDS buffer `cur` (sequence stride sq,
+// element stride se), stages ping-pong between `cur` and `other` (same
+// strides), the last stage writes to out[q oq + k oe] (global memory, or the
+// LDS buffer that the last stage does not read).
+__device__ inline void fft_axis(const FftPlan& P, double2* cur, double2* other, int sq, int se, int n, int rows,
+                                const double2* tw, double sg, double2* out, int oq, int oe)
+{
+    int Ns = 1;
+    for (int st = 0; st < P.n_st; ++st) {
+        const bool last = st == P.n_st - 1;
+        double2* dst = last ? out : other;
+        const int dq = last ? oq : sq, de = last ? oe : se;
+        const int R = st < P.c4 ? 4 : st < P.c4 + P.c2 ? 2 : st < P.c4 + P.c2 + P.c3 ? 3 : 5;
+        switch (R) {
+        case 4: fft_stage<4>(cur, sq, se, dst, dq, de, n, rows, Ns, tw, sg); break;
+        case 2: fft_stage<2>(cur, sq, se, dst, dq, de, n, rows, Ns, tw, sg); break;
+        case 3: fft_stage<3>(cur, sq, se, dst, dq, de, n, rows, Ns, tw, sg); break;
+        default: fft_stage<5>(cur, sq, se, dst, dq, de, n, rows, Ns, tw, sg); break;
+        }
+        __syncthreads();
+        Ns *= R;
+        double2* t = cur;
+        cur = other;
+        other = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Staging of measurement m_in for the plane transforms: the slab phases and
+// the 12 O rows copied to the plane-major order of each charge axis, so that
+// every plane the transforms read is contiguous.
+//   cpl[axis][s][plane_index],  opl[axis][s][row][plane_index]
+// Work-group per (ensemble, axis, slab, tile): the target's fastest
+// coordinate is v (z for the x axis, x for the y axis, y for the z axis); a
+// tile is 32 x values by 32 v values at fixed remaining coordinate, read with
+// x fastest and written with v fastest through LDS (the slab phase and four O
+// rows per pass), so both sides are contiguous.  For the y axis (v = x) the
+// tile is 32 x values of 32 rows, copied directly.
+// ---------------------------------------------------------------------------
+constexpr int kStageTile = 32;
+
+template <typename ot>
+__global__ void __launch_bounds__(256) k_plane_stage(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
+                                                     int n_ens, const ObsDesc* __restrict__ obs,
+                                                     const double2* __restrict__ hist_c, const ot* __restrict__ hist_o,
+                                                     int m_in, double2* __restrict__ cpl, ot* __restrict__ opl)
+{
+    constexpr int TT = kStageTile;
+    __shared__ double2 tc[TT][TT + 1];
+    __shared__ ot to[4][TT][TT + 1];  // four O rows per pass
+    const int e = find_ens_s(bstart, n_ens, blockIdx.x);
+    const EnsDesc& E = ens[e];
+    const ObsDesc& O = *obs;
+    const int nx = E.nx, ny = E.ny, nz = E.nz, nsig = E.nsig, Si = E.s_in;
+    const int npm = max(nx, max(ny, nz));
+    const int tx_n = (nx + TT - 1) / TT, tv_n = (npm + TT - 1) / TT;
+    const int tiles = tx_n * tv_n * npm;  // per (axis, slab), sized for the largest extent
+    int local = blockIdx.x - bstart[e];
+    const int tile = local % tiles;
+    local /= tiles;
+    const int s = local % Si;
+    const int id = local / Si;
+    if (id >= O.n_dirs) return;
+    const int dir = O.dirs[id];
+    // v: the target's fastest axis; w: the remaining one (y axis: v = x, rows y, w = z)
+    const int vax = dir == 0 ? 2 : dir == 1 ? 0 : 1;
+    const int wax = dir == 0 ? 1 : 2;
+    const int n3[3] = {nx, ny, nz};
+    const int nrow = vax == 0 ? ny : n3[vax];  // extent of the tile's second index
+    const int x0 = (tile % tx_n) * TT;
+    const int v0 = ((tile / tx_n) % tv_n) * TT;
+    const int w = tile / (tx_n * tv_n);
+    if (w >= n3[wax] || v0 >= nrow) return;  // uniform for the block
+    const size_t ps = (size_t)id * Si + s;
+    const double2* hc = hist_c + E.hc_off + ((size_t)m_in * Si + s) * nsig;
+    const ot* ho = hist_o + E.ho_off + ((size_t)m_in * Si + s) * 12 * nsig;
+    double2* dc = cpl + E.cpl_off + ps * nsig;
+    ot* dob = opl + E.opl_off + ps * 12 * nsig;
+    const int lx = threadIdx.x % TT, ly = threadIdx.x / TT;  // 32 x 8 work-items
+    if (vax == 0) {
+        // y axis: plane index (y nz + z) nx + x keeps x fastest: a plain copy of 32 rows
+        for (int i = ly; i < TT; i += 8) {
+            const int y = v0 + i, x = x0 + lx;
+            if (y >= ny || x >= nx) continue;
+            const int xs = x + nx * (y + ny * w);
+            const int p = (y * nz + w) * nx + x;
+            dc[p] = hc[xs];
+#pragma unroll
+            for (int row = 0; row < 12; ++row) dob[(size_t)row * nsig + p] = ho[(size_t)row * nsig + xs];
+        }
+        return;
+    }
+    for (int pass = 0; pass < 3; ++pass) {
+        // read with x fastest
+        for (int i = ly; i < TT; i += 8) {
+            const int v = v0 + i, x = x0 + lx;
+            if (v < nrow && x < nx) {
+                const int y = vax == 1 ? v : w, z = vax == 2 ? v : w;
+                const int xs = x + nx * (y + ny * z);
+                if (pass == 0) tc[i][lx] = hc[xs];
+#pragma unroll
+                for (int r4 = 0; r4 < 4; ++r4) to[r4][i][lx] = ho[(size_t)(4 * pass + r4) * nsig + xs];
+            }
+        }
+        __syncthreads();
+        // write with v fastest: x axis p = (x ny + y) nz + z (y = w, z = v); z axis p = (z nx + x) ny + y (z = w, y = v)
+        for (int i = ly; i < TT; i += 8) {
+            const int x = x0 + i, v = v0 + lx;
+            if (v < nrow && x < nx) {
+                const int p = vax == 2 ? (x * ny + w) * nz + v : (w * nx + x) * ny + v;
+                if (pass == 0) dc[p] = tc[lx][i];
+#pragma unroll
+                for (int r4 = 0; r4 < 4; ++r4) dob[(size_t)(4 * pass + r4) * nsig + p] = to[r4][lx][i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Plane transforms of measurement m_in.  Work-group per (ensemble, axis,
 // slab s, field f, axis coordinate x_par); fields f < n_r are
 // h = G(x,s,r) conj(c_m(x)) c_m(x + r e_par) (conjugate kernel), fields
 // n_r .. n_r + 11 the O rows (orientation, kind) (plain kernel).  The plane
-// is staged in LDS, transformed along v, then along u; twiddles
-// exp(2 pi i j / n) come from sincospi in FP64.  Each output is a sum over
-// the axis in ascending order, whatever the tile shape.
+// is staged in LDS, transformed along v, then along u, by the mixed-radix
+// FFT when both extents factor into 2, 3 and 5, else by direct sums over the
+// axis in ascending order; twiddles exp(2 pi i j / n) come from sincospi in
+// FP64.  Either way the outputs are the same for every launch shape.
 //   sph[axis][s][r][x_par][k],  spo[axis][s][row][x_par][k],  k = k1 n2 + k2
 // ---------------------------------------------------------------------------
+constexpr int kPlaneThreads = 512;  // two work-groups fill a CU's LDS; more threads per plane hide latency
+
 template <typename ot, int T>
-__global__ void __launch_bounds__(256) k_dft_planes(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
+__global__ void __launch_bounds__(kPlaneThreads) k_dft_planes(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
                                                     int n_ens, const ObsDesc* __restrict__ obs,
-                                                    const int* __restrict__ rlist, const double2* __restrict__ hist_c,
-                                                    const ot* __restrict__ hist_o, const double2* __restrict__ gf,
-                                                    double2* __restrict__ sph, double2* __restrict__ spo, int m_in)
+                                                    const int* __restrict__ rlist, const double2* __restrict__ cpl,
+                                                    const ot* __restrict__ opl, const double2* __restrict__ gf,
+                                                    double2* __restrict__ sph, double2* __restrict__ spo)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int e = find_ens_s(bstart, n_ens, blockIdx.x);
@@ -208,49 +434,79 @@ __global__ void __launch_bounds__(256) k_dft_planes(const EnsDesc* __restrict__ 
         sincospi(2.0 * (double)j / (double)n2, &sn, &cs);
         w2[j] = make_double2(cs, sg * sn);
     }
-    // stride of each lattice axis in the site index x + nx (y + ny z)
-    const int st3[3] = {1, E.nx, E.nx * E.ny};
-    const int base = xpar * st3[dir];
+    // the staged measurement and G are in plane-major order: plane x_par is
+    // the contiguous run [x_par n12, (x_par + 1) n12)
+    const size_t ps = (size_t)id * Si + s;
     if (f < R) {
         const int r = rlist[f];
-        const int xr_off = ((xpar + r) % N - xpar) * st3[dir];
-        const double2* hc = hist_c + E.hc_off + ((size_t)m_in * Si + s) * nsig;
-        const double2* g = gf + E.gf_off + (((size_t)id * R + f) * Si + s) * nsig;
-        for (int j = threadIdx.x; j < n12; j += blockDim.x) {
-            const int u = j / n2, v = j - u * n2;
-            const int xs = base + u * st3[d1] + v * st3[d2];
-            const double2 a = hc[xs], b = hc[xs + xr_off];
-            const double2 t = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-            X[j] = cmul(g[xs], t);
+        const double2* ca = cpl + E.cpl_off + ps * nsig + (size_t)xpar * n12;
+        const double2* cb = cpl + E.cpl_off + ps * nsig + (size_t)((xpar + r) % N) * n12;
+        const double2* g = gf + E.gf_off + (((size_t)id * R + f) * Si + s) * nsig + (size_t)xpar * n12;
+        // four elements per work-item and round, all loads issued before any use
+        for (int j0 = threadIdx.x; j0 < n12; j0 += 4 * blockDim.x) {
+            double2 a[4], b[4], gg[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = min(j0 + u * (int)blockDim.x, n12 - 1);
+                a[u] = ca[j];
+                b[u] = cb[j];
+                gg[u] = g[j];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u * (int)blockDim.x;
+                const double2 t = make_double2(a[u].x * b[u].x + a[u].y * b[u].y, a[u].x * b[u].y - a[u].y * b[u].x);
+                if (j < n12) X[j] = cmul(gg[u], t);
+            }
         }
     } else {
-        const ot* ho = hist_o + E.ho_off + (((size_t)m_in * Si + s) * 12 + (f - R)) * nsig;
-        for (int j = threadIdx.x; j < n12; j += blockDim.x) {
-            const int u = j / n2, v = j - u * n2;
-            X[j] = make_double2((double)ho[base + u * st3[d1] + v * st3[d2]], 0.0);
+        const ot* op = opl + E.opl_off + (ps * 12 + (f - R)) * nsig + (size_t)xpar * n12;
+        for (int j0 = threadIdx.x; j0 < n12; j0 += 4 * blockDim.x) {
+            ot v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = op[min(j0 + u * (int)blockDim.x, n12 - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j0 + u * (int)blockDim.x < n12) X[j0 + u * blockDim.x] = make_double2((double)v[u], 0.0);
         }
     }
     __syncthreads();
-    // along v, then along u (tiles of T x T outputs per thread)
-    dft_axis<T>(X, n1, n2, n2, 1, w2, Y, n2, 1);
-    __syncthreads();
     double2* out = f < R ? sph + E.sph_off + (((size_t)id * Si + s) * R + f) * nsig + (size_t)xpar * n12
                          : spo + E.spo_off + (((size_t)id * Si + s) * 12 + (f - R)) * nsig + (size_t)xpar * n12;
+    const FftPlan P1 = fft_plan(n1), P2 = fft_plan(n2);
+    if (P1.n_st > 0 && P2.n_st > 0) {
+        // along v (sequences u, contiguous), result left in X or Y, then along u
+        // (sequences k2, stride n2), the last stage writing out[k1 n2 + k2]
+        double2* mid = (P2.n_st & 1) ? Y : X;
+        fft_axis(P2, X, Y, n2, 1, n2, n1, w2, sg, mid, n2, 1);
+        fft_axis(P1, mid, mid == X ? Y : X, 1, n2, n1, n2, w1, sg, out, 1, n2);
+        return;
+    }
+    // an extent with a prime factor above 5: direct sums (tiles of T x T outputs per thread)
+    dft_axis<T>(X, n1, n2, n2, 1, w2, Y, n2, 1);
+    __syncthreads();
     dft_axis<T>(Y, n2, n1, 1, n2, w1, out, 1, n2);
 }
 
 // ---------------------------------------------------------------------------
-// Spectral sums of one measurement.  One work-item per (ensemble, axis, slab,
-// r, component, kind, probe group, k):
-//   F[...][k] += sum_{x_par} O^_{row}(x_par + l) (k) * h^~_r(x_par) (k)
+// Spectral sums of one measurement.  Work-group per (ensemble, axis, slab,
+// probe group, run of kMacK values of k); the 12 O rows of those k for every
+// x_par are staged in LDS once and shared by all separations r:
+//   F[...][c][kind][g][k] += sum_{x_par} O^_{row}(x_par + l) (k) * h^~_r(x_par) (k)
 // with l = l_g + (mode_g ? l_mid(r, c) : 0) and row = 2 o(c, axis) + kind.
+// Work-item (k, r slot) takes r = slot, slot + kMacThreads / kMacK, ...  Every
+// sum runs over x_par in ascending order.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_spec_mac(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
-                                                  int n_ens, const ObsDesc* __restrict__ obs,
-                                                  const int* __restrict__ rlist, const int* __restrict__ comps,
-                                                  const int* __restrict__ gdesc, const double2* __restrict__ sph,
-                                                  const double2* __restrict__ spo, double2* __restrict__ facc)
+__global__ void __launch_bounds__(kMacThreads) k_spec_mac(const EnsDesc* __restrict__ ens,
+                                                          const int* __restrict__ bstart, int n_ens,
+                                                          const ObsDesc* __restrict__ obs,
+                                                          const int* __restrict__ rlist, const int* __restrict__ comps,
+                                                          const int* __restrict__ gdesc, const double2* __restrict__ sph,
+                                                          const double2* __restrict__ spo, double2* __restrict__ facc)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double2* os = reinterpret_cast<double2*>(lds_raw);  // [row][x_par][kk]
+    constexpr int KC = kMacK;
     const int e = find_ens_s(bstart, n_ens, blockIdx.x);
     const EnsDesc& E = ens[e];
     const ObsDesc& O = *obs;
@@ -258,40 +514,71 @@ __global__ void __launch_bounds__(256) k_spec_mac(const EnsDesc* __restrict__ en
     const int n3[3] = {E.nx, E.ny, E.nz};
     int n12max = 0;
     for (int i = 0; i < O.n_dirs; ++i) n12max = max(n12max, nsig / n3[O.dirs[i]]);
-    long long item = (long long)(blockIdx.x - bstart[e]) * blockDim.x + threadIdx.x;
-    const long long total = (long long)O.n_dirs * Si * R * Nc * 2 * NG * n12max;
-    if (item >= total) return;
-    const long long slot = item / n12max;  // ((((id Si + s) R + ir) Nc + ic) 2 + kind) NG + g
-    const int k = (int)(item - slot * n12max);
-    long long t = slot;
-    const int g = (int)(t % NG);
-    t /= NG;
-    const int kind = (int)(t % 2);
-    t /= 2;
-    const int ic = (int)(t % Nc);
-    t /= Nc;
-    const int ir = (int)(t % R);
-    t /= R;
-    const int s = (int)(t % Si);
-    const int id = (int)(t / Si);
+    const int nkc = (n12max + KC - 1) / KC;
+    int local = blockIdx.x - bstart[e];
+    const int kc = local % nkc;
+    local /= nkc;
+    const int g = local % NG;
+    local /= NG;
+    const int s = local % Si;
+    const int id = local / Si;
+    if (id >= O.n_dirs) return;
     const int dir = O.dirs[id];
     const int N = n3[dir], n12 = nsig / N;
-    if (k >= n12) return;
-    const int c = comps[ic], r = rlist[ir];
-    const int l = gdesc[2 * g] + (gdesc[2 * g + 1] ? (spans_axis(c) ? (r - 1) / 2 : r / 2) : 0);
-    const int row = 2 * orient_of(c, dir) + kind;
-    const double2* h = sph + E.sph_off + (((size_t)id * Si + s) * R + ir) * nsig + k;
-    const double2* o = spo + E.spo_off + (((size_t)id * Si + s) * 12 + row) * nsig + k;
-    int xo = ((l % N) + N) % N;
-    double re = 0.0, im = 0.0;
-    for (int xp = 0; xp < N; ++xp) {
-        const double2 a = o[(size_t)xo * n12], b = h[(size_t)xp * n12];
-        re += a.x * b.x - a.y * b.y;
-        im += a.x * b.y + a.y * b.x;
-        if (++xo == N) xo = 0;
+    const int k0 = kc * KC;
+    if (k0 >= n12) return;  // uniform for the block
+    const size_t ps = (size_t)id * Si + s;
+    for (int i = threadIdx.x; i < 12 * N * KC; i += blockDim.x) {
+        const int kk = i % KC, t = i / KC;
+        const int xp = t % N, row = t / N;
+        os[i] = k0 + kk < n12 ? spo[E.spo_off + (ps * 12 + row) * nsig + (size_t)xp * n12 + k0 + kk]
+                              : make_double2(0.0, 0.0);
     }
-    double2* F = facc + E.facc_off + (size_t)slot * n12max + k;
-    *F = make_double2(F->x + re, F->y + im);
+    __syncthreads();
+    const int kk = threadIdx.x % KC, slot = threadIdx.x / KC;
+    const int k = k0 + kk;
+    if (k >= n12) return;
+    for (int ir = slot; ir < R; ir += blockDim.x / KC) {
+        const int r = rlist[ir];
+        const double2* h = sph + E.sph_off + (ps * R + ir) * nsig + k;
+        int xo[kMacComps], orow[kMacComps];
+        double re[kMacComps][2], im[kMacComps][2];
+#pragma unroll
+        for (int ic = 0; ic < kMacComps; ++ic) {
+            const int c = comps[ic < Nc ? ic : 0];
+            const int l = gdesc[2 * g] + (gdesc[2 * g + 1] ? (spans_axis(c) ? (r - 1) / 2 : r / 2) : 0);
+            xo[ic] = ((l % N) + N) % N;
+            orow[ic] = 2 * orient_of(c, dir);
+            re[ic][0] = im[ic][0] = re[ic][1] = im[ic][1] = 0.0;
+        }
+#pragma unroll 4
+        for (int xp = 0; xp < N; ++xp) {
+            const double2 b = h[(size_t)xp * n12];
+#pragma unroll
+            for (int ic = 0; ic < kMacComps; ++ic) {
+                if (ic < Nc) {
+#pragma unroll
+                    for (int kind = 0; kind < 2; ++kind) {
+                        const double2 a = os[((orow[ic] + kind) * N + xo[ic]) * KC + kk];
+                        re[ic][kind] += a.x * b.x - a.y * b.y;
+                        im[ic][kind] += a.x * b.y + a.y * b.x;
+                    }
+                    if (++xo[ic] == N) xo[ic] = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int ic = 0; ic < kMacComps; ++ic) {
+            if (ic < Nc) {
+#pragma unroll
+                for (int kind = 0; kind < 2; ++kind) {
+                    const size_t sl = (((ps * R + ir) * Nc + ic) * 2 + kind) * NG + g;
+                    double2* F = facc + E.facc_off + sl * n12max + k;
+                    *F = make_double2(F->x + re[ic][kind], F->y + im[ic][kind]);
+                }
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -407,36 +694,52 @@ hipError_t launch_gfac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int
 }
 
 // tile: 4 when every transverse extent is a multiple of 4, else 2 (extents are even)
+hipError_t launch_plane_stage(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+                              const ObsDesc* d_obs, const double2* hist_c, const void* hist_o, int m_in,
+                              int precision, double2* cpl, void* opl, hipStream_t st)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    static_assert(kStageTile == 32, "the staging work-group is 32 x 8 threads");
+    if (precision == 0)
+        hipLaunchKernelGGL(k_plane_stage<double>, dim3(total_blocks), dim3(kStageTile * 8), 0, st, d_ens, d_bstart, n_ens, d_obs,
+                           hist_c, (const double*)hist_o, m_in, cpl, (double*)opl);
+    else
+        hipLaunchKernelGGL(k_plane_stage<float>, dim3(total_blocks), dim3(kStageTile * 8), 0, st, d_ens, d_bstart, n_ens, d_obs,
+                           hist_c, (const float*)hist_o, m_in, cpl, (float*)opl);
+    return hipGetLastError();
+}
+
 hipError_t launch_dft_planes(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, size_t lds_bytes,
-                             const ObsDesc* d_obs, const int* d_r, const double2* hist_c, const void* hist_o,
-                             const double2* gf, double2* sph, double2* spo, int m_in, int precision, int tile,
+                             const ObsDesc* d_obs, const int* d_r, const double2* cpl, const void* opl,
+                             const double2* gf, double2* sph, double2* spo, int precision, int tile,
                              hipStream_t st)
 {
-    const dim3 g(total_blocks), b(256);
+    const dim3 g(total_blocks), b(kPlaneThreads);
     if (precision == 0) {
         if (tile == 4)
-            hipLaunchKernelGGL((k_dft_planes<double, 4>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r,
-                               hist_c, (const double*)hist_o, gf, sph, spo, m_in);
+            hipLaunchKernelGGL((k_dft_planes<double, 4>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, cpl,
+                               (const double*)opl, gf, sph, spo);
         else
-            hipLaunchKernelGGL((k_dft_planes<double, 2>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r,
-                               hist_c, (const double*)hist_o, gf, sph, spo, m_in);
+            hipLaunchKernelGGL((k_dft_planes<double, 2>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, cpl,
+                               (const double*)opl, gf, sph, spo);
     } else {
         if (tile == 4)
-            hipLaunchKernelGGL((k_dft_planes<float, 4>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r,
-                               hist_c, (const float*)hist_o, gf, sph, spo, m_in);
+            hipLaunchKernelGGL((k_dft_planes<float, 4>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, cpl,
+                               (const float*)opl, gf, sph, spo);
         else
-            hipLaunchKernelGGL((k_dft_planes<float, 2>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r,
-                               hist_c, (const float*)hist_o, gf, sph, spo, m_in);
+            hipLaunchKernelGGL((k_dft_planes<float, 2>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, cpl,
+                               (const float*)opl, gf, sph, spo);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_spec_mac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+hipError_t launch_spec_mac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int npm,
                            const ObsDesc* d_obs, const int* d_r, const int* d_comp, const int* d_gdesc,
                            const double2* sph, const double2* spo, double2* facc, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_spec_mac, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, d_r, d_comp,
-                       d_gdesc, sph, spo, facc);
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spec_mac, dim3(total_blocks), dim3(kMacThreads), spec_mac_lds(npm), st, d_ens, d_bstart,
+                       n_ens, d_obs, d_r, d_comp, d_gdesc, sph, spo, facc);
     return hipGetLastError();
 }
 

@@ -30,14 +30,15 @@ struct Sizes {
     // per ensemble element offsets
     std::vector<size_t> links, hc, ho, at, ato, ot, oto, vac;
     std::vector<size_t> wf, gf, sph, spo, facc;  // spectral form (double2 elements)
+    std::vector<size_t> cpl, opl;                // plane-major copies (double2, real elements)
 };
 
 struct Layout {
     size_t off_links, off_hc, off_ho, off_at, off_ato, off_ot, off_oto, off_res, off_scr;
     size_t sz_links, sz_hc, sz_ho, sz_at, sz_ato, sz_ot, sz_oto, sz_res, sz_scr;
     // spectral form: weights W, G; plane spectra of T and O; spectral sums; replay copy of the links
-    size_t off_wf, off_gf, off_sph, off_spo, off_facc, off_saved;
-    size_t sz_wf, sz_gf, sz_sph, sz_spo, sz_facc, sz_saved;
+    size_t off_wf, off_gf, off_sph, off_spo, off_facc, off_saved, off_cpl, off_opl;
+    size_t sz_wf, sz_gf, sz_sph, sz_spo, sz_facc, sz_saved, sz_cpl, sz_opl;
     // scratch sub-offsets (bytes from off_scr)
     size_t s_ens, s_obs, s_r, s_probe, s_comp, s_bstart, s_upd, s_ring, s_vpart, s_ppart, s_pout, s_count,
         s_stage, s_bmap, s_mmap, s_prodpart, s_pgroup, s_gdesc;
@@ -55,8 +56,9 @@ constexpr int kTabComb = 7;   // combine items
 constexpr int kTabProd = 8;   // slab-product work-groups
 constexpr int kTabSite = 9;   // spectral weights: (axis, r, site) items
 constexpr int kTabPlane = 10; // spectral plane transforms: work-groups
-constexpr int kTabMac = 11;   // spectral sums: items
-constexpr int kNumTabs = 12;
+constexpr int kTabMac = 11;   // spectral sums: work-groups
+constexpr int kTabStage = 12; // spectral staging: work-groups
+constexpr int kNumTabs = 13;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
 struct Problem {
@@ -212,7 +214,7 @@ long long body_launches(const Problem& P)
 {
     const long long sweep = (1ll + P.n_or) * 8;
     long long level = (long long)P.n_o * ((long long)P.k_o * sweep + (long long)P.n_i * (P.k_i * sweep + 1) + 4);
-    if (P.spectral) level += (long long)P.n_o * (1 + 2ll * P.n_i);
+    if (P.spectral) level += (long long)P.n_o * (1 + 3ll * P.n_i);
     const long long passes = (P.spectral && P.two) ? 2 : 1;
     return passes * level + 16;
 }
@@ -265,7 +267,9 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     S->sph.clear();
     S->spo.clear();
     S->facc.clear();
-    size_t WF = 0, GF = 0, SPH = 0, SPO = 0, FACC = 0;
+    S->cpl.clear();
+    S->opl.clear();
+    size_t WF = 0, GF = 0, SPH = 0, SPO = 0, FACC = 0, CPL = 0, OPL = 0;
     for (const u1ml_ensemble& E : P.ens) {
         const size_t nsig = (size_t)E.ns[0] * E.ns[1] * E.ns[2];
         const size_t V = nsig * E.nt;
@@ -309,7 +313,11 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
         S->sph.push_back(SPH);
         S->spo.push_back(SPO);
         S->facc.push_back(FACC);
+        S->cpl.push_back(CPL);
+        S->opl.push_back(OPL);
         if (spec) {
+            CPL = align_up((CPL + nd * si * nsig) * 16) / 16;
+            OPL = align_up((OPL + nd * si * 12 * nsig) * word) / word;
             size_t n12max = 0;
             for (int i = 0; i < P.n_dirs; ++i) n12max = std::max(n12max, nsig / (size_t)E.ns[P.dirs[i]]);
             if (P.two) WF = align_up((WF + nd * R * so * nsig) * 16) / 16;
@@ -351,6 +359,8 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     Lo->sz_sph = align_up(SPH * 16);
     Lo->sz_spo = align_up(SPO * 16);
     Lo->sz_facc = align_up(FACC * 16);
+    Lo->sz_cpl = align_up(CPL * 16);
+    Lo->sz_opl = align_up(OPL * word);
     Lo->sz_saved = (spec && P.two) ? Lo->sz_links : 0;
     size_t res;
     if (!mul_ok((size_t)P.max_configs * P.n_ens, (size_t)P.nd_cfg * 8, &res)) return fail(err, "size overflow (results)");
@@ -420,6 +430,10 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     off += Lo->sz_facc;
     Lo->off_saved = off;
     off += Lo->sz_saved;
+    Lo->off_cpl = off;
+    off += Lo->sz_cpl;
+    Lo->off_opl = off;
+    off += Lo->sz_opl;
     Lo->off_scr = off;
     off += Lo->sz_scr;
     if (info) {
@@ -436,7 +450,8 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
         info->updates_per_config = (long)upd_cfg;
         info->updates_per_sweep = (long)upd_sweep;
         info->form = spec ? U1ML_FORM_SPECTRAL : U1ML_FORM_HISTORY;
-        info->spectral_bytes = Lo->sz_wf + Lo->sz_gf + Lo->sz_sph + Lo->sz_spo + Lo->sz_facc + Lo->sz_saved;
+        info->spectral_bytes = Lo->sz_wf + Lo->sz_gf + Lo->sz_sph + Lo->sz_spo + Lo->sz_facc + Lo->sz_saved +
+                               Lo->sz_cpl + Lo->sz_opl;
         info->launches_per_config = (long)body_launches(P);
     }
     return true;
@@ -497,6 +512,8 @@ struct u1ml_ctx {
     int con_block = 64;                            // contraction work-group size
     size_t con_lds = 0;                            // contraction dynamic LDS per work-group
     double2 *wf = nullptr, *gf = nullptr, *sph = nullptr, *spo = nullptr, *facc = nullptr;  // spectral form
+    double2* cpl = nullptr;                        // plane-major slab phases of one measurement
+    void* opl = nullptr;                           // plane-major O rows of one measurement
     void* saved = nullptr;                         // replay copy of the links
     int spec_npm = 0;                              // largest lattice extent (spectral launches)
     long long spec_n12max = 0;                     // largest transverse plane (sites)
@@ -587,7 +604,7 @@ void build_lane_tables(const u1ml_ctx* c, Lane& L)
     L.h_bstart.assign((size_t)kNumTabs * (n + 1), 0);
     build_update_tabs(c, L);
     const size_t R = P.r.size(), NG = P.gdesc.size() / 2;
-    std::vector<long long> all(n), meas(n), con(n), comb(n), prod(n), site(n), plane(n), mac(n);
+    std::vector<long long> all(n), meas(n), con(n), comb(n), prod(n), site(n), plane(n), mac(n), stage(n);
     L.max_s_in = 1;
     for (int e = 0; e < n; ++e) {
         const EnsDesc& E = L.h_ens[e];
@@ -606,7 +623,9 @@ void build_lane_tables(const u1ml_ctx* c, Lane& L)
         prod[e] = (long long)R * prod_groups(P) * E.prod_nch;
         site[e] = (long long)P.n_dirs * R * E.nsig;
         plane[e] = P.spectral ? (long long)P.n_dirs * E.s_in * ((long long)R + 12) * npm : 0;
-        mac[e] = P.spectral ? (long long)P.n_dirs * E.s_in * R * P.comps.size() * 2 * NG * n12max : 0;
+        mac[e] = P.spectral ? (long long)P.n_dirs * E.s_in * NG * ((n12max + kMacK - 1) / kMacK) : 0;
+        // staging: work-groups of 32 x 32 tiles per (axis, slab), as k_plane_stage decodes them
+        stage[e] = P.spectral ? (long long)P.n_dirs * E.s_in * ((E.nx + 31) / 32) * ((npm + 31) / 32) * npm : 0;
         L.max_s_in = std::max(L.max_s_in, E.s_in);
     }
     build_tab(L, kTabAll, all, 256);
@@ -616,7 +635,8 @@ void build_lane_tables(const u1ml_ctx* c, Lane& L)
     build_tab(L, kTabProd, prod, 1);
     build_tab(L, kTabSite, site, 256);
     build_tab(L, kTabPlane, plane, 1);
-    build_tab(L, kTabMac, mac, 256);
+    build_tab(L, kTabMac, mac, 1);
+    build_tab(L, kTabStage, stage, 1);
     L.h_mmap.clear();
     const int* b = &L.h_bstart[(size_t)kTabMeas * (n + 1)];
     for (int e = 0; e < n; ++e)
@@ -737,12 +757,15 @@ hipError_t enq_levels(u1ml_ctx* c, const Lane& L, hipStream_t st, bool store_o, 
                                 P.two ? c->wf : nullptr, P.two ? P.tau_o / P.tau_i : 0, c->gf, st);
             const size_t lds = (2 * (size_t)c->spec_n12max + 2 * (size_t)c->spec_npm) * sizeof(double2);
             for (int m = 0; e == hipSuccess && m < P.n_i; ++m) {
-                e = launch_dft_planes(L.d_ens, L.tab_dev(kTabPlane), n, L.tab_total(kTabPlane), lds, c->d_obs,
-                                      c->d_r, c->hc, c->ho, c->gf, c->sph, c->spo, m, P.precision, c->spec_tile,
-                                      st);
+                e = launch_plane_stage(L.d_ens, L.tab_dev(kTabStage), n, L.tab_total(kTabStage), c->d_obs, c->hc,
+                                       c->ho, m, P.precision, c->cpl, c->opl, st);
                 if (e == hipSuccess)
-                    e = launch_spec_mac(L.d_ens, L.tab_dev(kTabMac), n, L.tab_total(kTabMac), c->d_obs, c->d_r,
-                                        c->d_comp, c->d_gdesc, c->sph, c->spo, c->facc, st);
+                    e = launch_dft_planes(L.d_ens, L.tab_dev(kTabPlane), n, L.tab_total(kTabPlane), lds, c->d_obs,
+                                          c->d_r, c->cpl, c->opl, c->gf, c->sph, c->spo, P.precision,
+                                          c->spec_tile, st);
+                if (e == hipSuccess)
+                    e = launch_spec_mac(L.d_ens, L.tab_dev(kTabMac), n, L.tab_total(kTabMac), c->spec_npm, c->d_obs,
+                                        c->d_r, c->d_comp, c->d_gdesc, c->sph, c->spo, c->facc, st);
             }
         }
     }
@@ -1019,6 +1042,8 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     c->sph = (double2*)(w + Lo.off_sph);
     c->spo = (double2*)(w + Lo.off_spo);
     c->facc = (double2*)(w + Lo.off_facc);
+    c->cpl = (double2*)(w + Lo.off_cpl);
+    c->opl = (void*)(w + Lo.off_opl);
     c->saved = (void*)(w + Lo.off_saved);
 
     const Problem& P = c->P;
@@ -1060,6 +1085,8 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         E.sph_off = (long long)c->S.sph[e];
         E.spo_off = (long long)c->S.spo[e];
         E.facc_off = (long long)c->S.facc[e];
+        E.cpl_off = (long long)c->S.cpl[e];
+        E.opl_off = (long long)c->S.opl[e];
     }
     ObsDesc O;
     std::memset(&O, 0, sizeof O);
@@ -1168,7 +1195,8 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         int lds_max = 0;
         hipError_t ea = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
         const size_t plane_lds = P.spectral ? (2 * (size_t)c->spec_n12max + 2 * (size_t)c->spec_npm) * sizeof(double2) : 0;
-        const size_t need = std::max(c->con_lds, plane_lds);
+        const size_t mac_lds = P.spectral ? spec_mac_lds(c->spec_npm) : 0;
+        const size_t need = std::max(c->con_lds, std::max(plane_lds, mac_lds));
         if (ea != hipSuccess || (size_t)lds_max < need) {
             release(c);
             return set_err(nullptr, ea != hipSuccess ? U1ML_EDEVICE : U1ML_ENOTSUP,

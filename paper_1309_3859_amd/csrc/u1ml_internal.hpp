@@ -29,6 +29,7 @@ struct EnsDesc {
     long long vac_part_off;  // double, [n_vac_blocks][12][hi, lo]: running sums over the configuration's measurements
     // spectral form (double2 offsets)
     long long wf_off, gf_off, sph_off, spo_off, facc_off;
+    long long cpl_off, opl_off;  // plane-major copies of one measurement's slab phases (double2) and O rows (real)
 };
 
 // Observable tables in device memory.
@@ -97,11 +98,22 @@ hipError_t launch_wfac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int
                        const double2* out_t, double scale, double2* wf, hipStream_t st);
 hipError_t launch_gfac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                        const double2* avg_t, const double2* wf, int q, double2* gf, hipStream_t st);
+// measurement m_in's slab phases and O rows copied to the plane-major order of each charge axis;
+// d_bstart: per ensemble n_dirs * s_in * ceil(Nx/32) * ceil(max extent/32) * max extent work-groups
+hipError_t launch_plane_stage(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+                              const ObsDesc* d_obs, const double2* hist_c, const void* hist_o, int m_in,
+                              int precision, double2* cpl, void* opl, hipStream_t st);
 hipError_t launch_dft_planes(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, size_t lds_bytes,
-                             const ObsDesc* d_obs, const int* d_r, const double2* hist_c, const void* hist_o,
-                             const double2* gf, double2* sph, double2* spo, int m_in, int precision, int tile,
+                             const ObsDesc* d_obs, const int* d_r, const double2* cpl, const void* opl,
+                             const double2* gf, double2* sph, double2* spo, int precision, int tile,
                              hipStream_t st);
-hipError_t launch_spec_mac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+// spectral sums: work-groups of kMacThreads per (axis, slab, probe group, kMacK values of k);
+// dynamic LDS spec_mac_lds(largest extent)
+constexpr int kMacK = 8;
+constexpr int kMacThreads = 192;
+constexpr int kMacComps = 6;
+inline size_t spec_mac_lds(int npm) { return (size_t)12 * npm * kMacK * 16; }
+hipError_t launch_spec_mac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int npm,
                            const ObsDesc* d_obs, const int* d_r, const int* d_comp, const int* d_gdesc,
                            const double2* sph, const double2* spo, double2* facc, hipStream_t st);
 hipError_t launch_spec_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_obs, long long n_outputs, int npm,

@@ -130,10 +130,12 @@ def test_contraction_form_selection(u1):
     assert p5["average_bytes"] < 2**30 and p5["ws_bytes"] < 16 * 2**30
     # the spectral sections: weights W (3 thick slabs) and G (6 thin slabs),
     # plane spectra of the 19 T fields and 12 O rows, spectral sums of 19 r x 6
-    # components x 2 kinds x 1 probe group over 48 x 48 planes, one link copy
+    # components x 2 kinds x 1 probe group over 48 x 48 planes, one link copy,
+    # and one measurement's slab phases (double2) and 12 O rows (FP32) in
+    # plane-major order
     nsig, R = 48 ** 3, 19
     want = 16 * (R * 3 * nsig + R * 6 * nsig + 6 * R * nsig + 6 * 12 * nsig + 6 * R * 6 * 2 * 48 * 48) \
-        + p5["link_bytes"]
+        + p5["link_bytes"] + 16 * 6 * nsig + 4 * 6 * 12 * nsig
     assert abs(p5["spectral_bytes"] - want) <= 6 * 256
     s5.form = u1.FORM_HISTORY
     assert u1.plan(s5)["average_bytes"] > 10 ** 12

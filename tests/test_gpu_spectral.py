@@ -4,7 +4,8 @@ configuration), through the C ABI.
 
 * against the history form on the same device trajectory (same links, same
   counters), one and two levels, several axes, probes of both modes and
-  several probe groups: every estimate within FP64 rounding of the
+  several probe groups, plane extents taking every radix of the plane FFT and
+  extents taking the direct sums: every estimate within FP64 rounding of the
   contraction order;
 * after a two-level configuration the links and counters equal those of the
   history form (the replay restores the start and repeats the trajectory);
@@ -81,6 +82,21 @@ def test_spectral_one_level_matches_history(env, prec):
     for a, b in zip(lh, ls):
         assert np.array_equal(a, b)
     assert ch == cs
+    _compare(mk(), rh, rs, 1e-12)
+
+
+def test_spectral_transform_sizes_match_history(env):
+    """Plane extents that take every radix of the plane FFT (4, 2, 3, 5) and
+    extents with a prime factor above 5 (14), which take the direct sums."""
+    u1, O, _ = env
+    mk = lambda: u1.Spec(ensembles=[u1.Ens((6, 10, 14), 4, 1.0, seed=13), u1.Ens((12, 20, 8), 4, 0.95, seed=14, key_id=2)],
+                         levels=[(2, 2, 1)], r=[1, 3], dirs=[0, 1, 2], probes=_disk(1) + [(2, 1, -1, 0)],
+                         comps=[0, 2, 4], precision=u1.FP64, n_or=2)
+    say("transform sizes")
+    rh, lh, ch = _run(u1, mk(), u1.FORM_HISTORY)
+    rs, ls, cs = _run(u1, mk(), u1.FORM_SPECTRAL)
+    for a, b in zip(lh, ls):
+        assert np.array_equal(a, b)
     _compare(mk(), rh, rs, 1e-12)
 
 
