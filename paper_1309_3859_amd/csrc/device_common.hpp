@@ -114,7 +114,8 @@ struct M<float> {
     __device__ static inline float acos_(float x) { return acosf(x); }
     __device__ static inline float log_(float x) { return __logf(x); }
     __device__ static inline float exp_(float x) { return __expf(x); }
-    __device__ static inline float sqrt_(float x) { return __builtin_sqrtf(x); }
+    // hardware square root (1 ulp), without the correctly rounded library's refinement
+    __device__ static inline float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     __device__ static inline float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     __device__ static inline float floor_(float x) { return floorf(x); }
     // 23-bit uniforms: exact in FP32, never 0 or 1
@@ -328,36 +329,27 @@ struct Geo {
     int nx, ny, nz, nt, sy, sz, st;  // sy = Nx/2, sz = sy Ny, st = sz Nz (strides in half indices)
 };
 
-// one periodic step along compile-time direction D, sign S
+// one periodic step along compile-time direction D, sign S.  The wrap is
+// written with an all-ones mask w (= -1 when the step crosses the boundary),
+// so the step is a few integer operations with no branch.
 template <int D, int S>
 __device__ inline Site mv(Site c, const Geo& g)
 {
     if (D == 0) {
-        c.x = S > 0 ? (c.x == g.nx - 1 ? 0 : c.x + 1) : (c.x == 0 ? g.nx - 1 : c.x - 1);
-    } else if (D == 1) {
-        if (S > 0) {
-            c.hrow += c.y == g.ny - 1 ? -(g.ny - 1) * g.sy : g.sy;
-            c.y = c.y == g.ny - 1 ? 0 : c.y + 1;
-        } else {
-            c.hrow += c.y == 0 ? (g.ny - 1) * g.sy : -g.sy;
-            c.y = c.y == 0 ? g.ny - 1 : c.y - 1;
-        }
-    } else if (D == 2) {
-        if (S > 0) {
-            c.hrow += c.z == g.nz - 1 ? -(g.nz - 1) * g.sz : g.sz;
-            c.z = c.z == g.nz - 1 ? 0 : c.z + 1;
-        } else {
-            c.hrow += c.z == 0 ? (g.nz - 1) * g.sz : -g.sz;
-            c.z = c.z == 0 ? g.nz - 1 : c.z - 1;
-        }
+        const int w = -(int)(S > 0 ? c.x == g.nx - 1 : c.x == 0);
+        c.x = S > 0 ? (c.x + 1) & ~w : c.x - 1 + (w & g.nx);
+        return c;
+    }
+    const int n = D == 1 ? g.ny : D == 2 ? g.nz : g.nt;
+    const int st = D == 1 ? g.sy : D == 2 ? g.sz : g.st;
+    int& v = D == 1 ? c.y : D == 2 ? c.z : c.t;
+    const int w = -(int)(S > 0 ? v == n - 1 : v == 0);
+    if (S > 0) {
+        c.hrow += st - (w & (n * st));
+        v = (v + 1) & ~w;
     } else {
-        if (S > 0) {
-            c.hrow += c.t == g.nt - 1 ? -(g.nt - 1) * g.st : g.st;
-            c.t = c.t == g.nt - 1 ? 0 : c.t + 1;
-        } else {
-            c.hrow += c.t == 0 ? (g.nt - 1) * g.st : -g.st;
-            c.t = c.t == 0 ? g.nt - 1 : c.t - 1;
-        }
+        c.hrow += (w & (n * st)) - st;
+        v = v - 1 + (w & n);
     }
     return c;
 }
