@@ -54,7 +54,8 @@ struct RetryQ {
 template <typename real, int KIND, int MU>
 __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens, const int2* __restrict__ bmap,
                                                  real* __restrict__ links, const uint32_t* __restrict__ upd,
-                                                 int pass_offset, int parity, int tau, float inv_tm1)
+                                                 int pass_offset, int parity, int tau, float inv_tm1,
+                                                 float inv_tau)
 {
     constexpr bool kQueue = (KIND == 0) && (sizeof(real) == 4);
     const int2 be = bmap[blockIdx.x];
@@ -64,7 +65,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
     const Geo g{E.nx, E.ny, E.nz, E.nt, E.nxh, E.nxh * E.ny, E.nxh * E.ny * E.nz};
     const bool masked = (MU < 3) && (tau > 1);
     const int slice = g.st;
-    const int active_t = masked ? g.nt - g.nt / tau : g.nt;
+    const int active_t = masked ? g.nt - fdiv(g.nt, tau, inv_tau) : g.nt;
     const int item = be.y * (int)blockDim.x + (int)threadIdx.x;
     const bool active = item < slice * active_t;
     if (!kQueue && !active) return;
@@ -99,13 +100,18 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
         if (KIND != 0) old = ldo(lb, self);
         real* dst = reinterpret_cast<real*>(reinterpret_cast<char*>(lb) + self);
 
-        real ar = real(0), ai = real(0);
+        real ar, ai;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             real s, co;
             M<real>::sincos_(v[k][0] - v[k][1] - v[k][2], &s, &co);
-            ar += co;
-            ai += s;
+            if (k == 0) {
+                ar = co;
+                ai = s;
+            } else {
+                ar += co;
+                ai += s;
+            }
             M<real>::sincos_(v[k][3] - v[k][4] - v[k][5], &s, &co);
             ar += co;
             ai += s;
@@ -160,9 +166,11 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
             const real dl = (real)E.beta * ((ar * cn - ai * sn) - (ar * co - ai * so));
             if (dl >= real(0) || m::u2(b.w[1]) < m::exp_(dl)) *dst = thn;
         } else {
-            if (ar == real(0) && ai == real(0)) return;
+            // stored unconditionally (A = 0 writes the old angle back), so the
+            // load of the old angle is issued with the staple loads
             const real phiA = M<real>::atan2_(ai, ar);
-            *dst = wrap_angle<real>(-old - real(2) * phiA);
+            const real th = wrap_angle<real>(-old - real(2) * phiA);
+            *dst = (ar == real(0) && ai == real(0)) ? old : th;
         }
     }
     if constexpr (kQueue) {
@@ -207,27 +215,27 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
 template <typename real, int KIND, int MU>
 static void launch_update_mu(dim3 g, dim3 b, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
                              const EnsDesc* d_ens, const int2* d_bmap, real* links, const uint32_t* d_upd,
-                             int pass_offset, int parity, int tau, float inv_tm1)
+                             int pass_offset, int parity, int tau, float inv_tm1, float inv_tau)
 {
     if (ev0)
         hipExtLaunchKernelGGL((k_update<real, KIND, MU>), g, b, lds, st, ev0, ev1, 0, d_ens, d_bmap, links, d_upd,
-                              pass_offset, parity, tau, inv_tm1);
+                              pass_offset, parity, tau, inv_tm1, inv_tau);
     else
         hipLaunchKernelGGL((k_update<real, KIND, MU>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset,
-                           parity, tau, inv_tm1);
+                           parity, tau, inv_tm1, inv_tau);
 }
 
 template <typename real, int KIND>
 static void launch_update_t(dim3 g, dim3 b, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const EnsDesc* d_ens,
                             const int2* d_bmap, real* links, const uint32_t* d_upd, int pass_offset, int mu,
-                            int parity, int tau, float inv_tm1)
+                            int parity, int tau, float inv_tm1, float inv_tau)
 {
     const size_t lds = (KIND == 0 && sizeof(real) == 4) ? sizeof(RetryQ) * b.x : 0;
     switch (mu) {
-    case 0: launch_update_mu<real, KIND, 0>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
-    case 1: launch_update_mu<real, KIND, 1>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
-    case 2: launch_update_mu<real, KIND, 2>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
-    default: launch_update_mu<real, KIND, 3>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 0: launch_update_mu<real, KIND, 0>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1, inv_tau); break;
+    case 1: launch_update_mu<real, KIND, 1>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1, inv_tau); break;
+    case 2: launch_update_mu<real, KIND, 2>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1, inv_tau); break;
+    default: launch_update_mu<real, KIND, 3>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1, inv_tau); break;
     }
 }
 
@@ -239,23 +247,24 @@ hipError_t launch_update(const EnsDesc* d_ens, const int2* d_bmap, int total_blo
     if ((ev_start == nullptr) != (ev_stop == nullptr)) return hipErrorInvalidValue;
     const dim3 g(total_blocks), b(block);
     const float inv_tm1 = tau > 1 ? 1.0f / (float)(tau - 1) : 1.0f;
+    const float inv_tau = tau > 1 ? 1.0f / (float)tau : 1.0f;
     if (kind < 0 || kind > 2) return hipErrorInvalidValue;
     if (precision == 0) {
         double* lk = (double*)links;
         if (kind == 0)
-            launch_update_t<double, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<double, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
         else if (kind == 1)
-            launch_update_t<double, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<double, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
         else
-            launch_update_t<double, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<double, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
     } else {
         float* lk = (float*)links;
         if (kind == 0)
-            launch_update_t<float, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<float, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
         else if (kind == 1)
-            launch_update_t<float, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<float, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
         else
-            launch_update_t<float, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
+            launch_update_t<float, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
     }
     return hipGetLastError();
 }
