@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--block", type=int, default=256,
                     help="work-group size of the update kernels (0: autotune; candidates differ by about 2 percent, "
                          "so a fixed size keeps profiled and unprofiled runs on the same launch shape)")
+    ap.add_argument("--n-inner", type=int, default=0,
+                    help="for kernel traces of the large presets: sublattice updates of the inner level (0: the preset's)")
+    ap.add_argument("--n-outer", type=int, default=0,
+                    help="for kernel traces of the two-level presets: updates of the outer level (0: the preset's)")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: one 256 MiB device copy (calibration of the byte counters), "
                          "then 20 launches each of the heatbath and overrelaxation phases of the dominant kernel")
@@ -196,7 +200,18 @@ def main():
     from paper_1309_3859_amd import configs, u1ml
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    make = configs.PRESETS[args.workload]
+    preset = configs.PRESETS[args.workload]
+
+    def make():
+        spec, sched = preset()
+        lv = [list(x) for x in spec.levels]
+        if args.n_inner:
+            lv[-1][1] = args.n_inner
+        if args.n_outer and len(lv) == 2:
+            lv[0][1] = args.n_outer
+        spec.levels = [tuple(x) for x in lv]
+        return spec, sched
+
     spec, sched = make()
     if args.counters:
         run_counter_workload(spec, sched)
@@ -236,7 +251,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if spec.precision == u1ml.FP32 else "f64",
         "data": "synthetic (seeded Monte-Carlo ensembles)",
-        "config": {"workload": make.__name__, "ensembles": len(spec.ensembles),
+        "config": {"workload": preset.__name__, "ensembles": len(spec.ensembles),
                    "lattices": sorted({f"{e.ns[0]}^3x{e.nt}" for e in spec.ensembles}),
                    "levels": spec.levels, "n_or": spec.n_or, "updates_per_step": upd,
                    "block": block},
