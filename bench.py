@@ -142,6 +142,22 @@ def time_steps(ctx, steps: int, warmup: int):
     return ms
 
 
+def time_full_sweeps(ctx, n: int = 10):
+    """Full-lattice sweeps (every link, no frozen slabs: 1 heatbath and n_or
+    overrelaxation passes each) timed with events on the context's stream;
+    returns link updates/s."""
+    import torch
+
+    ctx.sweeps(2)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(ctx.stream)
+    ctx.sweeps(n)
+    b.record(ctx.stream)
+    torch.cuda.synchronize()
+    return ctx.plan["updates_per_sweep"] * n / (a.elapsed_time(b) / 1e3)
+
+
 def copy_reference(nbytes: float, reps: int = 50):
     """A plain device copy moving the same number of bytes as one launch of
     the dominant kernel (half read, half written), timed with events: the
@@ -264,6 +280,8 @@ def main():
         "phases_us": {f"{('HB', 'OR', 'MET')[k]}_mu{m}": v[0] for (k, m), v in per_phase.items()},
     }
     line["roofline"]["copy_reference"] = copy_reference(b)
+    # the same batch in full-lattice sweeps (thermalisation), next to the multilevel rate of `value`
+    line["full_sweeps"] = {"value": time_full_sweeps(ctx), "unit": "link updates/s"}
     if not args.no_fp64 and spec.precision == u1ml.FP32:
         # the same workload with FP64 link storage and update arithmetic
         spec64, _ = make()

@@ -95,4 +95,15 @@ def beta_scan(betas, ns: int = 24, nt: int = 4, precision: int = FP32):
     return spec, {"start": HOT, "therm": 500}
 
 
-PRESETS = {"c1": c1_plain_fp64, "c2": c2_fp32_profiles, "c3": c3_precision, "c4": c4_batched, "c5": c5_largest}
+def out_of_cache(ns: int = 128, nt: int = 16):
+    """Not one of the paper's workloads: one 128^3 x 16 FP32 ensemble (537 MB
+    of links, twice the 256 MB Infinity Cache), one level tau = 2, the
+    correlator at r = 1 only; its update phases show the rate when the links
+    stream from DRAM."""
+    spec = Spec(ensembles=[Ens((ns, ns, ns), nt, 1.0, seed=8, key_id=0)], levels=[(2, 2, 1)], r=[1], dirs=[0],
+                precision=FP32, n_or=3, max_configs=4)
+    return spec, {"start": HOT, "therm": 0}
+
+
+PRESETS = {"c1": c1_plain_fp64, "c2": c2_fp32_profiles, "c3": c3_precision, "c4": c4_batched, "c5": c5_largest,
+           "dram": out_of_cache}
