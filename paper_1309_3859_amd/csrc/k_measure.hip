@@ -326,12 +326,15 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
     const bool line_ok = line < nlines;
     const int mc = E.con_mc;
     const int nmax = max(E.nx, max(E.ny, E.nz));
-    const int row_len = mc * nmax;  // LDS elements per staged row of one line
+    const int row_len = mc * nmax;  // LDS elements of one staged row of one line
     const int nc_rows = O.multihit ? 2 : 1;  // plain phases, and multihit phases
+    // LDS, site index k fastest, so that the consecutive pairs (x, r) of a
+    // wave read consecutive 16-byte words (no bank conflicts):
+    //   cl[q][k], clm[q][k]        phases of site k of the line (double2)
+    //   ol[q][o][k]                (O_sq, O_lin) of orientation o at site k of the displaced line (double2)
     double2* cl = reinterpret_cast<double2*>(lds_raw) + (size_t)grp * row_len;
     double2* clm = reinterpret_cast<double2*>(lds_raw) + (size_t)(lpb + grp) * row_len;
-    ot* ol = reinterpret_cast<ot*>(lds_raw + (size_t)nc_rows * lpb * row_len * sizeof(double2)) +
-             (size_t)grp * 12 * row_len;
+    double2* ol = reinterpret_cast<double2*>(lds_raw) + (size_t)nc_rows * lpb * row_len + (size_t)grp * 6 * row_len;
 
     // transverse coordinates of the line; sites along it are `stride` apart
     const int a1 = line_ok ? line % n3[d1] : 0, a2 = line_ok ? line / n3[d1] : 0;
@@ -351,8 +354,9 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
     const int nr = O.n_r, pairs = N * nr;
     const int npass = (pairs + G - 1) / G;
 
-    // element j of a staged block of rows of N: (row, k) = (j / N, j % N),
-    // carried from lane to lane + G without a division per element
+    // element j of a staged block (row, q, k), k fastest (contiguous in the
+    // history for the x axis), carried from lane to lane + G without a
+    // division per element
     const int g_q = G / N, g_k = G - (G / N) * N;
     const int l_q = lane / N, l_k = lane - (lane / N) * N;
     auto stage_rows = [&](const double2* src, double2* dst, int m0, int mm) {
@@ -367,7 +371,6 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
             }
         }
     };
-    auto stage_c = [&](int m0, int mm) { stage_rows(hc, cl, m0, mm); };
 
     for (int pass = 0; !INS && pass < npass; ++pass) {
         const int pr = pass * G + lane;
@@ -380,35 +383,21 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
         // multihit: both ends from the multihit phases, except neighbours on
         // the periodic axis (their temporal links share plaquettes): there
         // the far end keeps the plain phase
-        const double2* ca = O.multihit ? clm : cl;
-        const double2* cb = (O.multihit && r_ir != 1 && r_ir != N - 1) ? clm : cl;
+        const double2* pa = (O.multihit ? clm : cl) + x;
+        const double2* pb = ((O.multihit && r_ir != 1 && r_ir != N - 1) ? clm : cl) + xr;
         double tre = 0.0, tim = 0.0;
         for (int m0 = 0; m0 < n_meas; m0 += mc) {
             const int mm = min(mc, n_meas - m0);
             __syncthreads();
             if (line_ok) {
-                stage_c(m0, mm);
+                stage_rows(hc, cl, m0, mm);
                 if (O.multihit) stage_rows(hcm, clm, m0, mm);
             }
             __syncthreads();
             if (act) {
-                int q = 0;
-                for (; q + 4 <= mm; q += 4) {  // four measurements' reads in flight, summed in order
-                    double2 a[4], b[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        a[u] = ca[(q + u) * N + x];
-                        b[u] = cb[(q + u) * N + xr];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        tre += a[u].x * b[u].x + a[u].y * b[u].y;
-                        tim += a[u].x * b[u].y - a[u].y * b[u].x;
-                    }
-                }
-                for (; q < mm; ++q) {
-                    const double2 a = ca[q * N + x];
-                    const double2 b = cb[q * N + xr];
+#pragma unroll 4
+                for (int q = 0; q < mm; ++q) {
+                    const double2 a = pa[q * N], b = pb[q * N];
                     tre += a.x * b.x + a.y * b.y;
                     tim += a.x * b.y - a.y * b.x;
                 }
@@ -424,9 +413,9 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
     const int nc = O.n_comp;
     const size_t mstride_o = (size_t)S * 12 * nsig;
     const ot* ho = hist_o + E.ho_off + (size_t)s * 12 * nsig;
-    int row[6];
+    int orient[6];
 #pragma unroll
-    for (int ic = 0; ic < 6; ++ic) row[ic] = 2 * comp_orient(ic < nc ? comps[ic] : 0, dir);
+    for (int ic = 0; ic < 6; ++ic) orient[ic] = comp_orient(ic < nc ? comps[ic] : 0, dir);
     for (int p = 0; p < O.n_probe; ++p) {
         const int l = probes[4 * p], p1 = probes[4 * p + 1], p2 = probes[4 * p + 2], mode = probes[4 * p + 3];
         const int obase = site0(p1, p2);
@@ -438,12 +427,14 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
             const int r = rlist[ir];
             int xr = x + r;
             if (xr >= N) xr -= N;
-            int pos[6];
+            const double2* pa = cl + x;
+            const double2* pb = cl + xr;
+            const double2* po[6];
 #pragma unroll
             for (int ic = 0; ic < 6; ++ic) {
                 const int c = ic < nc ? comps[ic] : 0;
                 const int sh = l + (mode ? (comp_spans_axis(c) ? (r - 1) / 2 : r / 2) : 0);
-                pos[ic] = ((x + sh) % N + N) % N;
+                po[ic] = ol + orient[ic] * N + ((x + sh) % N + N) % N;
             }
             double acc[6][4];
 #pragma unroll
@@ -454,12 +445,14 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
                 const int mm = min(mc, n_meas - m0);
                 __syncthreads();
                 if (line_ok) {
-                    stage_c(m0, mm);
-                    // rows [12][mm][N] of the displaced line (row rq = rw * mm + q)
-                    int rw = l_q / mm, q = l_q - (l_q / mm) * mm, k = l_k;
-                    for (int j = lane; j < 12 * mm * N; j += G) {
-                        ol[(rw * mc + q) * N + k] =
-                            ho[(size_t)(m0 + q) * mstride_o + (size_t)rw * nsig + obase + (size_t)k * stride];
+                    stage_rows(hc, cl, m0, mm);
+                    // (O_sq, O_lin) pairs of the displaced line, element (o, q, k) with k fastest
+                    int o = l_q / mm, q = l_q - (l_q / mm) * mm, k = l_k;
+                    const int n6 = 6 * N;
+                    for (int j = lane; j < 6 * mm * N; j += G) {
+                        const ot* src = ho + (size_t)(m0 + q) * mstride_o + (size_t)(2 * o) * nsig + obase +
+                                        (size_t)k * stride;
+                        ol[q * n6 + o * N + k] = make_double2((double)src[0], (double)src[nsig]);
                         q += g_q;
                         k += g_k;
                         if (k >= N) {
@@ -468,28 +461,26 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
                         }
                         while (q >= mm) {
                             q -= mm;
-                            ++rw;
+                            ++o;
                         }
                     }
                 }
                 __syncthreads();
                 if (act) {
                     // every component slot is evaluated (slots past n_comp read a valid
-                    // row and are never stored), so the 12 reads issue together
-                    int q = 0;
-                    for (; q < mm; ++q) {
-                        const double2 a = cl[q * N + x];
-                        const double2 b = cl[q * N + xr];
+                    // row and are never stored), so the reads issue together
+                    for (int q = 0; q < mm; ++q) {
+                        const double2 a = pa[q * N];
+                        const double2 b = pb[q * N];
                         const double Tr = a.x * b.x + a.y * b.y;
                         const double Ti = a.x * b.y - a.y * b.x;
 #pragma unroll
                         for (int ic = 0; ic < 6; ++ic) {
-                            const double osq = (double)ol[(row[ic] * mc + q) * N + pos[ic]];
-                            const double olin = (double)ol[((row[ic] + 1) * mc + q) * N + pos[ic]];
-                            acc[ic][0] += Tr * osq;
-                            acc[ic][1] += Ti * osq;
-                            acc[ic][2] += Tr * olin;
-                            acc[ic][3] += Ti * olin;
+                            const double2 ov = po[ic][q * 6 * N];  // (O_sq, O_lin)
+                            acc[ic][0] += Tr * ov.x;
+                            acc[ic][1] += Ti * ov.x;
+                            acc[ic][2] += Tr * ov.y;
+                            acc[ic][3] += Ti * ov.y;
                         }
                     }
                 }

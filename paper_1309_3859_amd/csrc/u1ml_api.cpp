@@ -1111,7 +1111,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     // pairs (x, r), one thread each; a work-group of con_block threads holds
     // con_lpb such lines, and stages con_mc measurements at a time in LDS.
     const size_t R = P.r.size();
-    const size_t o_word = P.probes.empty() ? 0 : (P.precision == U1ML_FP64 ? 8 : 4);
+    const size_t o_bytes = P.probes.empty() ? 0 : 6 * 16;  // (O_sq, O_lin) of six orientations, FP64 in LDS
     std::vector<int> group(n);
     c->con_block = 256;
     for (int e = 0; e < n; ++e) {
@@ -1127,7 +1127,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         EnsDesc& E = c->h_ens[e];
         const int n3[3] = {E.nx, E.ny, E.nz};
         const size_t nmax = (size_t)std::max(E.nx, std::max(E.ny, E.nz));
-        const size_t per = (P.multihit ? 32 : 16) + 12 * o_word;  // LDS bytes per (measurement, line site)
+        const size_t per = (P.multihit ? 32 : 16) + o_bytes;  // LDS bytes per (measurement, line site)
         E.con_lpb = c->con_block / group[e];
         const size_t fit = (size_t)kConLds / ((size_t)E.con_lpb * nmax * per);
         E.con_mc = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)P.n_i));
