@@ -26,16 +26,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_update_or_c4_counters.md")
-KERNEL_SOURCES = ["k_update.hip", "device_common.hpp", "u1ml_internal.hpp"]
+KERNEL_SOURCES = ["k_update.hip", "device_common.hpp"]
 
 
 def kernel_source_hash() -> str:
+    """Hash of what the update kernel is built from: its two source files and
+    the ensemble descriptor it reads (the rest of the shared header holds other
+    kernels' declarations and constants)."""
     import hashlib
 
     h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1309_3859_amd", "csrc")
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1309_3859_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "u1ml_internal.hpp"), "rb") as fh:
+        text = fh.read()
+    start = text.index(b"struct EnsDesc {")
+    h.update(text[start:text.index(b"};", start) + 2])
     return h.hexdigest()
 
 
