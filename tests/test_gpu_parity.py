@@ -204,11 +204,15 @@ def _multilevel_pair(env, ns, nt, levels, n_or, r, dirs, probes, comps, beta=1.0
 PROBES = [(0, 0, 0, 1), (1, 1, -1, 1), (-1, 2, 1, 0)]
 
 
-@pytest.mark.parametrize("levels", [[(2, 3, 0)], [(4, 2, 0), (2, 3, 0)], [(4, 3, 0)]])
+@pytest.mark.parametrize("levels", [[(2, 3, 0)], [(4, 2, 0), (2, 3, 0)], [(4, 3, 0)], [(8, 2, 0)],
+                                    [(8, 2, 0), (4, 2, 0)]])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_measurement_and_estimators_match_oracle(env, levels, precision):
     """k = 0: no updates, so both sides measure the same links; the whole
-    measurement -> slab average -> combine -> product -> sum chain is compared."""
+    measurement -> slab average -> combine -> product -> sum chain is compared.
+    The last two cases are the degenerate slabs: one slab of the whole time
+    extent (the product over the other slabs is empty), and one thick slab
+    holding two thin ones."""
     say("measurement parity", levels, precision)
     got, want, _, _ = _multilevel_pair(env, (6, 6, 8), 8, levels, 3, [1, 2, 3], [0, 1, 2], PROBES, list(range(6)),
                                        precision=precision)
