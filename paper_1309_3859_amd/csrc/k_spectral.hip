@@ -528,11 +528,21 @@ __global__ void __launch_bounds__(kMacThreads) k_spec_mac(const EnsDesc* __restr
     const int k0 = kc * KC;
     if (k0 >= n12) return;  // uniform for the block
     const size_t ps = (size_t)id * Si + s;
-    for (int i = threadIdx.x; i < 12 * N * KC; i += blockDim.x) {
-        const int kk = i % KC, t = i / KC;
-        const int xp = t % N, row = t / N;
-        os[i] = k0 + kk < n12 ? spo[E.spo_off + (ps * 12 + row) * nsig + (size_t)xp * n12 + k0 + kk]
-                              : make_double2(0.0, 0.0);
+    // staged four elements per work-item and round, all loads issued before the LDS stores
+    const int n_os = 12 * N * KC;
+    for (int i0 = threadIdx.x; i0 < n_os; i0 += 4 * blockDim.x) {
+        double2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = min(i0 + u * (int)blockDim.x, n_os - 1);
+            const int kk = i % KC, t = i / KC;
+            const int xp = t % N, row = t / N;
+            v[u] = k0 + kk < n12 ? spo[E.spo_off + (ps * 12 + row) * nsig + (size_t)xp * n12 + k0 + kk]
+                                 : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * (int)blockDim.x < n_os) os[i0 + u * blockDim.x] = v[u];
     }
     __syncthreads();
     const int kk = threadIdx.x % KC, slot = threadIdx.x / KC;
@@ -551,7 +561,7 @@ __global__ void __launch_bounds__(kMacThreads) k_spec_mac(const EnsDesc* __restr
             orow[ic] = 2 * orient_of(c, dir);
             re[ic][0] = im[ic][0] = re[ic][1] = im[ic][1] = 0.0;
         }
-#pragma unroll 4
+#pragma unroll 8
         for (int xp = 0; xp < N; ++xp) {
             const double2 b = h[(size_t)xp * n12];
 #pragma unroll
