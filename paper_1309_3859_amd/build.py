@@ -28,6 +28,10 @@ FLAGS = [
     # multiply-adds fused only within one source expression, so every
     # instantiation of a kernel template rounds the same way
     "-ffp-contract=on",
+    # the first 16 kernel-argument dwords arrive in SGPRs at wave launch
+    # (gfx950 kernarg preloading; kernels keep a loading prologue for
+    # firmware without it), one scalar-memory round trip less per wave
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
