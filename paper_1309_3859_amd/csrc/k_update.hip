@@ -52,39 +52,40 @@ struct RetryQ {
 };
 
 template <typename real, int KIND, int MU>
-__global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens, const int2* __restrict__ bmap,
+__global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens, const UpdBlock* __restrict__ blocks,
                                                  real* __restrict__ links, const uint32_t* __restrict__ upd,
                                                  int pass_offset, int parity, int tau, float inv_tm1,
                                                  float inv_tau)
 {
     constexpr bool kQueue = (KIND == 0) && (sizeof(real) == 4);
-    const int2 be = bmap[blockIdx.x];
-    if (be.x < 0) return;  // padding block of the XCD-aware order (uniform for the block)
-    const int e = be.x;
-    const EnsDesc& E = ens[e];
-    const Geo g{E.nx, E.ny, E.nz, E.nt, E.nxh, E.nxh * E.ny, E.nxh * E.ny * E.nz};
+    // a padding block of the XCD-aware order carries a block index past its
+    // ensemble's links, so all its work-items are inactive (no branch on the
+    // record, whose fields then all load at once)
+    const UpdBlock B = blocks[blockIdx.x];
+    const EnsDesc& E = ens[B.e];  // coupling, key and step: read after the link loads are issued
+    const Geo g{B.nx, B.ny, B.nz, B.nt, B.nxh, B.nxh * B.ny, B.nxh * B.ny * B.nz};
     const bool masked = (MU < 3) && (tau > 1);
     const int slice = g.st;
     const int active_t = masked ? g.nt - fdiv(g.nt, tau, inv_tau) : g.nt;
-    const int item = be.y * (int)blockDim.x + (int)threadIdx.x;
+    const int item = B.blk * (int)blockDim.x + (int)threadIdx.x;
     const bool active = item < slice * active_t;
     if (!kQueue && !active) return;
-    real* lb = links + E.link_off;
-    const unsigned vh = (unsigned)E.vh;
+    real* lb = links + B.link_off;
+    const unsigned vh = (unsigned)B.vh;
     bool pending = false;
     float q_kappa = 0.0f, q_ar = 0.0f, q_ai = 0.0f;
     unsigned q_lid = 0, q_off = 0;
     if (active) {
-        const int j = fdiv(item, slice, E.inv_slice);
+        const int j = fdiv(item, slice, B.inv_slice);
         const int rem = item - (int)__umul24(j, slice);
         int t = j;
         if (masked) {
             const int jt = fdiv(j, tau - 1, inv_tm1);
             t = jt * tau + 1 + (j - jt * (tau - 1));
         }
-        const int yz = fdiv(rem, g.sy, E.inv_nxh);
+        const int yz = fdiv(rem, g.sy, B.inv_nxh);
         const int xh = rem - (int)__umul24(yz, g.sy);
-        const int z = fdiv(yz, g.ny, E.inv_ny);
+        const int z = fdiv(yz, g.ny, B.inv_ny);
         const int y = yz - (int)__umul24(z, g.ny);
         const int x = 2 * xh + ((y + z + t + parity) & 1);
         const Site c{x, y, z, t, (int)(__umul24(g.sy, yz) + __umul24(g.st, t))};
@@ -120,7 +121,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
             const real R = M<real>::sqrt_(ar * ar + ai * ai);
             const real kappa = (real)E.beta * R;
             const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
-            const uint32_t ctr = upd[E.res_index] + (uint32_t)pass_offset;
+            const uint32_t ctr = upd[B.res_index] + (uint32_t)pass_offset;
             if constexpr (kQueue) {
                 // theta = psi - arg A as one angle: exp(i theta) is proportional to
                 // exp(i psi) conj(A), so a single atan2 replaces arccos, atan2 and wrap
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
             // Metropolis: theta' = theta + delta (2 U1 - 1), accepted when
             // U2 < exp(beta (Re(e^{i theta'} A) - Re(e^{i theta} A)))
             const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
-            const uint32_t ctr = upd[E.res_index] + (uint32_t)pass_offset;
+            const uint32_t ctr = upd[B.res_index] + (uint32_t)pass_offset;
             const Block4 b = philox4x32_10(lid, ctr, 0u, DOM_METRO, E.seed, E.key_id);
             using m = M<real>;
             const real thn = wrap_angle<real>(old + (real)E.metro_delta * (real(2) * m::u1(b.w[0]) - real(1)));
@@ -191,7 +192,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
             queue[pos] = RetryQ{q_kappa, q_ar, q_ai, q_lid, q_off};
         }
         __syncthreads();
-        const uint32_t ctr = upd[E.res_index] + (uint32_t)pass_offset;
+        const uint32_t ctr = upd[B.res_index] + (uint32_t)pass_offset;
         for (int i = threadIdx.x; i < total; i += blockDim.x) {
             const RetryQ r = queue[i];
             const float rm1 = bf_rm1_f32(r.kappa);
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
 // whose events take the dispatch's own begin and end timestamps.
 template <typename real, int KIND, int MU>
 static void launch_update_mu(dim3 g, dim3 b, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
-                             const EnsDesc* d_ens, const int2* d_bmap, real* links, const uint32_t* d_upd,
+                             const EnsDesc* d_ens, const UpdBlock* d_bmap, real* links, const uint32_t* d_upd,
                              int pass_offset, int parity, int tau, float inv_tm1, float inv_tau)
 {
     if (ev0)
@@ -227,7 +228,7 @@ static void launch_update_mu(dim3 g, dim3 b, size_t lds, hipStream_t st, hipEven
 
 template <typename real, int KIND>
 static void launch_update_t(dim3 g, dim3 b, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const EnsDesc* d_ens,
-                            const int2* d_bmap, real* links, const uint32_t* d_upd, int pass_offset, int mu,
+                            const UpdBlock* d_bmap, real* links, const uint32_t* d_upd, int pass_offset, int mu,
                             int parity, int tau, float inv_tm1, float inv_tau)
 {
     const size_t lds = (KIND == 0 && sizeof(real) == 4) ? sizeof(RetryQ) * b.x : 0;
@@ -239,7 +240,7 @@ static void launch_update_t(dim3 g, dim3 b, hipStream_t st, hipEvent_t ev0, hipE
     }
 }
 
-hipError_t launch_update(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int block, int precision,
+hipError_t launch_update(const EnsDesc* d_ens, const UpdBlock* d_bmap, int total_blocks, int block, int precision,
                          void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu, int parity, int tau,
                          hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop)
 {

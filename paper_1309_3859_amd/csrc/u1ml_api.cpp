@@ -388,13 +388,13 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     Lo->s_count = take(sizeof(unsigned long long) * 2);
     Lo->s_stage = take(sizeof(double) * 4 * maxV);
     Lo->bmap_stride = blocks64;
-    Lo->s_bmap = take(sizeof(int2) * kUpdateClasses * blocks64);
+    Lo->s_bmap = take(sizeof(UpdBlock) * kUpdateClasses * blocks64);
     Lo->s_mmap = take(sizeof(int2) * mblocks);
     Lo->s_prodpart = take(sizeof(double) * PP);
     for (int l = 0; l < 2; ++l) {
         Lo->s_lens[l] = take(sizeof(EnsDesc) * n);
         Lo->s_lbstart[l] = take(sizeof(int) * (n + 1) * kNumTabs);
-        Lo->s_lbmap[l] = take(sizeof(int2) * kUpdateClasses * blocks64);
+        Lo->s_lbmap[l] = take(sizeof(UpdBlock) * kUpdateClasses * blocks64);
         Lo->s_lmmap[l] = take(sizeof(int2) * mblocks);
         Lo->s_lring[l] = take(sizeof(int) * 4);
     }
@@ -471,11 +471,11 @@ struct Lane {
     std::vector<int> idx;        // problem indices of the lane's ensembles
     std::vector<EnsDesc> h_ens;  // their descriptors, lane order
     std::vector<int> h_bstart;   // kNumTabs x (n + 1)
-    std::vector<int2> h_bmap;    // kUpdateClasses x bmap_stride
+    std::vector<UpdBlock> h_bmap;  // kUpdateClasses x bmap_stride
     std::vector<int2> h_mmap;    // measurement block -> (lane ensemble, block)
     EnsDesc* d_ens = nullptr;
     int* d_bstart = nullptr;
-    int2* d_bmap = nullptr;
+    UpdBlock* d_bmap = nullptr;
     int2* d_mmap = nullptr;
     int* d_ring = nullptr;
     double* prodpart = nullptr;
@@ -487,7 +487,7 @@ struct Lane {
 
     int tab_total(int tab) const { return h_bstart[(size_t)tab * (n + 1) + n]; }
     const int* tab_dev(int tab) const { return d_bstart + (size_t)tab * (n + 1); }
-    const int2* bmap_dev(int cls) const { return d_bmap + (size_t)cls * bmap_stride; }
+    const UpdBlock* bmap_dev(int cls) const { return d_bmap + (size_t)cls * bmap_stride; }
 };
 
 struct u1ml_ctx {
@@ -579,17 +579,42 @@ void build_update_tabs(const u1ml_ctx* c, Lane& L)
     // gives every XCD one contiguous stretch of the lattice, so neighbouring
     // rows shared by adjacent blocks are fetched into one L2 instead of
     // several.  Launches have 8 per blocks; entries past the end are idle.
-    L.h_bmap.assign((size_t)kUpdateClasses * L.bmap_stride, make_int2(-1, 0));
+    UpdBlock pad;
+    std::memset(&pad, 0, sizeof pad);
+    pad.e = -1;
+    L.h_bmap.assign((size_t)kUpdateClasses * L.bmap_stride, pad);
     for (int cls = 0; cls < kUpdateClasses; ++cls) {
         const int* b = &L.h_bstart[(size_t)(kTabUpd + cls) * (n + 1)];
         const int total = b[n];
         const int per = (total + kXcds - 1) / kXcds;
-        std::vector<int2> logical(total);
-        for (int e = 0; e < n; ++e)
-            for (int k = b[e]; k < b[e + 1]; ++k) logical[k] = make_int2(e, k - b[e]);
+        std::vector<UpdBlock> logical(total);
+        for (int e = 0; e < n; ++e) {
+            const EnsDesc& E = L.h_ens[e];
+            UpdBlock r = pad;
+            r.e = e;
+            r.nx = E.nx;
+            r.ny = E.ny;
+            r.nz = E.nz;
+            r.nt = E.nt;
+            r.nxh = E.nxh;
+            r.vh = E.vh;
+            r.inv_slice = E.inv_slice;
+            r.inv_nxh = E.inv_nxh;
+            r.inv_ny = E.inv_ny;
+            r.res_index = E.res_index;
+            r.link_off = E.link_off;
+            for (int k = b[e]; k < b[e + 1]; ++k) {
+                r.blk = k - b[e];
+                logical[k] = r;
+            }
+        }
+        // padding blocks: the last ensemble's record with a block index past
+        // its links (every work-item inactive)
+        UpdBlock idle = total > 0 ? logical[total - 1] : pad;
+        idle.blk = total > 0 ? b[n] - b[n - 1] : 0;
         for (int phys = 0; phys < per * kXcds; ++phys) {
             const int lg = (phys % kXcds) * per + phys / kXcds;
-            L.h_bmap[(size_t)cls * L.bmap_stride + phys] = lg < total ? logical[lg] : make_int2(-1, 0);
+            L.h_bmap[(size_t)cls * L.bmap_stride + phys] = lg < total ? logical[lg] : idle;
         }
         L.upd_grid[cls] = per * kXcds;
     }
@@ -648,7 +673,7 @@ hipError_t upload_lane(const Lane& L)
     const int ring0[4] = {0, 0, 0, 0};
     hipError_t e = hipMemcpy(L.d_ens, L.h_ens.data(), sizeof(EnsDesc) * L.n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(L.d_bstart, L.h_bstart.data(), sizeof(int) * L.h_bstart.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(L.d_bmap, L.h_bmap.data(), sizeof(int2) * L.h_bmap.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(L.d_bmap, L.h_bmap.data(), sizeof(UpdBlock) * L.h_bmap.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !L.h_mmap.empty())
         e = hipMemcpy(L.d_mmap, L.h_mmap.data(), sizeof(int2) * L.h_mmap.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(L.d_ring, ring0, sizeof ring0, hipMemcpyHostToDevice);
@@ -1171,7 +1196,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
             if (l == 0) {
                 L.d_ens = (EnsDesc*)(s + Lo.s_ens);
                 L.d_bstart = (int*)(s + Lo.s_bstart);
-                L.d_bmap = (int2*)(s + Lo.s_bmap);
+                L.d_bmap = (UpdBlock*)(s + Lo.s_bmap);
                 L.d_mmap = (int2*)(s + Lo.s_mmap);
                 L.d_ring = (int*)(s + Lo.s_ring);
                 L.prodpart = (double*)(s + Lo.s_prodpart);
@@ -1179,7 +1204,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
             } else {
                 L.d_ens = (EnsDesc*)(s + Lo.s_lens[l - 1]);
                 L.d_bstart = (int*)(s + Lo.s_lbstart[l - 1]);
-                L.d_bmap = (int2*)(s + Lo.s_lbmap[l - 1]);
+                L.d_bmap = (UpdBlock*)(s + Lo.s_lbmap[l - 1]);
                 L.d_mmap = (int2*)(s + Lo.s_lmmap[l - 1]);
                 L.d_ring = (int*)(s + Lo.s_lring[l - 1]);
                 // the two lanes use disjoint parts of the slab-product partials
@@ -1422,7 +1447,7 @@ u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block)
         if (!L->n) continue;
         build_update_tabs(ctx, *L);
         HIPCHK(ctx, hipMemcpy(L->d_bstart, L->h_bstart.data(), sizeof(int) * 4 * (L->n + 1), hipMemcpyHostToDevice));
-        HIPCHK(ctx, hipMemcpy(L->d_bmap, L->h_bmap.data(), sizeof(int2) * L->h_bmap.size(), hipMemcpyHostToDevice));
+        HIPCHK(ctx, hipMemcpy(L->d_bmap, L->h_bmap.data(), sizeof(UpdBlock) * L->h_bmap.size(), hipMemcpyHostToDevice));
     }
     drop_graphs(ctx);
     return U1ML_OK;

@@ -32,6 +32,21 @@ struct EnsDesc {
     long long cpl_off, opl_off;  // plane-major copies of one measurement's slab phases (double2) and O rows (real)
 };
 
+// One work-group of an update launch: its ensemble and block index within it
+// (a padding block of the XCD-aware order has an index past the ensemble's
+// links), with the geometry the update kernel needs before its loads, so that
+// one 64-byte scalar load replaces a block-map load followed by descriptor
+// loads.
+struct alignas(64) UpdBlock {
+    int e, blk;
+    int nx, ny, nz, nt, nxh, vh;
+    float inv_slice, inv_nxh, inv_ny;
+    int res_index;
+    long long link_off;
+    int pad0, pad1;
+};
+static_assert(sizeof(UpdBlock) == 64, "UpdBlock is one 64-byte scalar load");
+
 // Observable tables in device memory.
 struct ObsDesc {
     int n_dirs;
@@ -52,9 +67,9 @@ constexpr int kConLds = 49152;      // contraction: LDS budget per work-group (b
 // --- launchers (k_update.hip) ---
 hipError_t launch_init_links(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
                              void* links, int start, hipStream_t st);
-// d_bmap[b] = (ensemble, block index within the ensemble) for every block of the launch;
+// d_blocks[b]: ensemble, block index within the ensemble and geometry of every block of the launch;
 // ev_start/ev_stop (both or neither) record the dispatch's begin and end timestamps
-hipError_t launch_update(const EnsDesc* d_ens, const int2* d_bmap, int total_blocks, int block, int precision,
+hipError_t launch_update(const EnsDesc* d_ens, const UpdBlock* d_blocks, int total_blocks, int block, int precision,
                          void* links, const uint32_t* d_upd, int pass_offset, int kind, int mu, int parity, int tau,
                          hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_health(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
