@@ -101,6 +101,14 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
         if (KIND != 0) old = ldo(lb, self);
         real* dst = reinterpret_cast<real*>(reinterpret_cast<char*>(lb) + self);
 
+        // the first Philox block depends only on the link's id and the counter:
+        // formed here, it runs while the link angles are still in flight
+        const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
+        const uint32_t ctr = upd[B.res_index] + (uint32_t)pass_offset;
+        Block4 b0;
+        if (kQueue || KIND == 2)
+            b0 = philox4x32_10(lid, ctr, 0u, KIND == 2 ? DOM_METRO : DOM_HB, E.seed, E.key_id);
+
         real ar, ai;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -120,19 +128,18 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
         if (KIND == 0) {
             const real R = M<real>::sqrt_(ar * ar + ai * ai);
             const real kappa = (real)E.beta * R;
-            const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
-            const uint32_t ctr = upd[B.res_index] + (uint32_t)pass_offset;
             if constexpr (kQueue) {
                 // theta = psi - arg A as one angle: exp(i theta) is proportional to
                 // exp(i psi) conj(A), so a single atan2 replaces arccos, atan2 and wrap
                 float cp = 1.0f, sp = 0.0f;
                 bool done;
                 if (kappa == 0.0f) {
-                    int na;
-                    vonmises_cs_f32(0.0f, E.seed, E.key_id, lid, ctr, DOM_HB, &cp, &sp, &na);
+                    // psi uniform from attempt 0: pi (2 U1 - 1), in revolutions U1 - 1/2
+                    const float rev = M<float>::u1(b0.w[0]) - 0.5f;
+                    cp = __builtin_amdgcn_cosf(rev);
+                    sp = __builtin_amdgcn_sinf(rev);
                     done = true;
                 } else {
-                    const Block4 b0 = philox4x32_10(lid, ctr, 0u, DOM_HB, E.seed, E.key_id);
                     done = bf_pair_f32(kappa, bf_rm1_f32(kappa), b0, &cp, &sp);
                 }
                 if (done) {
@@ -156,9 +163,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
         } else if (KIND == 2) {
             // Metropolis: theta' = theta + delta (2 U1 - 1), accepted when
             // U2 < exp(beta (Re(e^{i theta'} A) - Re(e^{i theta} A)))
-            const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
-            const uint32_t ctr = upd[B.res_index] + (uint32_t)pass_offset;
-            const Block4 b = philox4x32_10(lid, ctr, 0u, DOM_METRO, E.seed, E.key_id);
+            const Block4& b = b0;
             using m = M<real>;
             const real thn = wrap_angle<real>(old + (real)E.metro_delta * (real(2) * m::u1(b.w[0]) - real(1)));
             real sn, cn, so, co;
