@@ -29,21 +29,34 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_update_or_c4_counters.md")
 KERNEL_SOURCES = ["k_update.hip", "device_common.hpp"]
 
 
+def _code_only(text: str) -> bytes:
+    """Source text without // comments, blank lines and indentation, so that an
+    edit of the comments alone keeps the hash."""
+    out = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].strip()
+        if code:
+            out.append(" ".join(code.split()))
+    return "\n".join(out).encode()
+
+
 def kernel_source_hash() -> str:
     """Hash of what the update kernel is built from: its two source files and
-    the ensemble descriptor it reads (the rest of the shared header holds other
-    kernels' declarations and constants)."""
+    the records it reads (the ensemble descriptor and the per-block record; the
+    rest of the shared header holds other kernels' declarations and
+    constants), comments left out."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1309_3859_amd", "csrc")
     for f in KERNEL_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    with open(os.path.join(csrc, "u1ml_internal.hpp"), "rb") as fh:
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(_code_only(fh.read()))
+    with open(os.path.join(csrc, "u1ml_internal.hpp")) as fh:
         text = fh.read()
-    start = text.index(b"struct EnsDesc {")
-    h.update(text[start:text.index(b"};", start) + 2])
+    for struct in ("struct EnsDesc {", "struct alignas(64) UpdBlock {"):
+        start = text.index(struct)
+        h.update(_code_only(text[start:text.index("};", start) + 2]))
     return h.hexdigest()
 
 

@@ -6,10 +6,14 @@
 // as phases, even then odd sites, in place).
 //
 // One work-item per link of the phase (direction mu, parity p, not frozen),
-// every ensemble of the batch in the same launch: block b belongs to the
-// ensemble e with bstart[e] <= b < bstart[e+1].  The staple of a link reads
-// 18 angles: 12 of the other parity (coalesced, shifted by one site), 6 of the
-// same parity; none of them is written by the phase, so the update is in place.
+// every ensemble of the batch in the same launch: work-group b reads its
+// ensemble, its block index within that ensemble and the geometry from one
+// record (UpdBlock), the records dealt to the 8 XCDs in contiguous stretches.
+// The staple of a link reads 18 angles: 12 of the other parity (coalesced,
+// shifted by one site), 6 of the same parity; none of them is written by the
+// phase, so the update is in place.  The all-link kernels below (start,
+// health check, canonical gather and scatter, plaquettes) find their ensemble
+// from block start offsets or a fixed number of blocks per ensemble.
 #include "device_common.hpp"
 #include <hip/hip_ext.h>
 

@@ -471,7 +471,7 @@ struct Lane {
     std::vector<int> idx;        // problem indices of the lane's ensembles
     std::vector<EnsDesc> h_ens;  // their descriptors, lane order
     std::vector<int> h_bstart;   // kNumTabs x (n + 1)
-    std::vector<UpdBlock> h_bmap;  // kUpdateClasses x bmap_stride
+    std::vector<UpdBlock> h_bmap;  // per-block update records, kUpdateClasses x bmap_stride
     std::vector<int2> h_mmap;    // measurement block -> (lane ensemble, block)
     EnsDesc* d_ens = nullptr;
     int* d_bstart = nullptr;
