@@ -192,11 +192,12 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
     for (int k = 0; k < 12; ++k) vac[k] = 0.0;
     if (item < nsig * S) {
         const Geo g{E.nx, E.ny, E.nz, E.nt, E.nxh, E.nxh * E.ny, E.nxh * E.ny * E.nz};
-        const int s = item / nsig;
+        // division-free decode: 1/N_sigma = (1/slice) / 2 and 1/Nx = (1/(Nx/2)) / 2 exactly
+        const int s = fdiv(item, nsig, 0.5f * E.inv_slice);
         const int xs = item - s * nsig;
-        const int yz = xs / E.nx;
+        const int yz = fdiv(xs, E.nx, 0.5f * E.inv_nxh);
         const int x = xs - yz * E.nx;
-        const int z = yz / E.ny;
+        const int z = fdiv(yz, E.ny, E.inv_ny);
         const int y = yz - z * E.ny;
         double Th = 0.0;
         double2 cm = make_double2(1.0, 0.0);  // multihit slab phase
