@@ -190,7 +190,10 @@ u1ml_status u1ml_plan(const u1ml_problem* problem, u1ml_plan_info* out);
 u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes, void* hip_stream,
                         u1ml_ctx** out);
 
-/* Frees host state and graphs; never frees d_ws.  NULL is accepted. */
+/* Waits for the context's outstanding work on its stream, then frees host
+ * state, graphs and the internal stream; never frees d_ws, which the caller
+ * may release once this returns.  NULL is accepted.  The context is freed
+ * even when the wait reports a device error (U1ML_EDEVICE). */
 u1ml_status u1ml_destroy(u1ml_ctx* ctx);
 
 /* Async.  Cold start (theta = 0) or hot start (theta = pi (2u - 1), u from

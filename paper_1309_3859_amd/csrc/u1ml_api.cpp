@@ -1267,8 +1267,11 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
 u1ml_status u1ml_destroy(u1ml_ctx* ctx)
 {
     if (!ctx) return U1ML_OK;
+    // every lane joins the context's stream, so this waits for all work that
+    // still reads the workspace or runs the graphs about to be destroyed
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
     release(ctx);
-    return U1ML_OK;
+    return e == hipSuccess ? U1ML_OK : set_err(nullptr, U1ML_EDEVICE, std::string("u1ml_destroy: ") + hipGetErrorString(e));
 }
 
 u1ml_status u1ml_init_links(u1ml_ctx* ctx, int start)

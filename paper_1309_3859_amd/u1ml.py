@@ -2,8 +2,8 @@
 
 Argument marshalling only: every step of the multilevel path runs in the HIP
 kernels of libu1ml.so.  PyTorch provides the device workspace and the stream.
-If the library is not built, importing this module raises: there is no CPU
-fallback.
+If the library is not built, the first call into it raises ImportError: there
+is no CPU fallback.
 
 Paper: Amado, Cardoso, Bicudo, arXiv 1309.3859 (Sec. II, II.C, Algorithm 1).
 """
