@@ -41,10 +41,11 @@ def _code_only(text: str) -> bytes:
 
 
 def kernel_source_hash() -> str:
-    """Hash of what the update kernel is built from: its two source files and
-    the records it reads (the ensemble descriptor and the per-block record; the
-    rest of the shared header holds other kernels' declarations and
-    constants), comments left out."""
+    """Hash of what the update kernel is built from and how it is launched:
+    its two source files, the records it reads (the ensemble descriptor and the
+    per-block record; the rest of the shared header holds other kernels'
+    declarations and constants) and the host function that builds the block
+    records and their order, comments left out."""
     import hashlib
 
     h = hashlib.sha256()
@@ -57,6 +58,10 @@ def kernel_source_hash() -> str:
     for struct in ("struct EnsDesc {", "struct alignas(64) UpdBlock {"):
         start = text.index(struct)
         h.update(_code_only(text[start:text.index("};", start) + 2]))
+    with open(os.path.join(csrc, "u1ml_api.cpp")) as fh:
+        text = fh.read()
+    start = text.index("void build_update_tabs(")
+    h.update(_code_only(text[start:text.index("\n}\n", start) + 3]))
     return h.hexdigest()
 
 

@@ -603,9 +603,17 @@ void build_update_tabs(const u1ml_ctx* c, Lane& L)
             r.inv_ny = E.inv_ny;
             r.res_index = E.res_index;
             r.link_off = E.link_off;
-            for (int k = b[e]; k < b[e + 1]; ++k) {
-                r.blk = k - b[e];
-                logical[k] = r;
+            // Time slice fastest: when a slice of sites is a whole number of
+            // blocks, the blocks of one stretch of the slice at consecutive
+            // times follow each other, so the links a slice shares with the
+            // next one are reused while they are still in the XCD's L2.
+            const int nb = b[e + 1] - b[e];
+            const long long slice = (long long)E.nxh * E.ny * E.nz;
+            const int bps = slice % c->block == 0 ? (int)(slice / c->block) : 0;
+            const int ns = bps > 0 ? nb / bps : 0;
+            for (int k = 0; k < nb; ++k) {
+                r.blk = (ns > 1 && ns * bps == nb) ? (k % ns) * bps + k / ns : k;
+                logical[b[e] + k] = r;
             }
         }
         // padding blocks: the last ensemble's record with a block index past
