@@ -728,11 +728,19 @@ __global__ void __launch_bounds__(64) k_product_final(const EnsDesc* __restrict_
     if (q < 2 && p != 0) return;
     if (q >= 2 && (!with_ins || O.n_probe == 0 || q - 2 >= 4 * nc)) return;
     const int b0 = bstart[e] + (ir * n_pgroups + p) * E.prod_nch;
+    // chunks added in order; the loads of eight chunks are issued before their additions
     dd a{0.0, 0.0};
-    for (int c = 0; c < E.prod_nch; ++c) {
-        const double* src = part + ((size_t)(b0 + c) * kProdQ + q) * 2;
-        a = dd_add(a, dd{src[0], src[1]});
+    const double* src = part + ((size_t)b0 * kProdQ + q) * 2;
+    constexpr size_t cs = (size_t)kProdQ * 2;
+    int c = 0;
+    for (; c + 8 <= E.prod_nch; c += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = make_double2(src[(c + u) * cs], src[(c + u) * cs + 1]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a = dd_add(a, dd{v[u].x, v[u].y});
     }
+    for (; c < E.prod_nch; ++c) a = dd_add(a, dd{src[c * cs], src[c * cs + 1]});
     double* out = results + ((size_t)(*ring) * O.n_ens_total + E.res_index) * O.n_doubles_per_config;
     const double nC = 1.0 / ((double)E.nsig * O.n_dirs);
     if (q < 2) {
@@ -767,9 +775,24 @@ __global__ void __launch_bounds__(256) k_vac_final(const EnsDesc* __restrict__ e
 {
     const int e = blockIdx.x / 12, k = blockIdx.x % 12;
     const EnsDesc& E = ens[e];
+    // partials i = tid, tid + 256, ... added in order; the loads of eight are
+    // issued before their additions
     dd a{0.0, 0.0};
-    for (int i = threadIdx.x; i < E.n_vac_blocks; i += blockDim.x) {
-        const double* p = vac_part + E.vac_part_off + (size_t)i * 24 + 2 * k;
+    const double* vp = vac_part + E.vac_part_off + 2 * k;
+    const int nb = E.n_vac_blocks;
+    int i = threadIdx.x;
+    for (; i + 7 * (int)blockDim.x < nb; i += 8 * blockDim.x) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double* p = vp + (size_t)(i + u * blockDim.x) * 24;
+            v[u] = make_double2(p[0], p[1]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a = dd_add(a, dd{v[u].x, v[u].y});
+    }
+    for (; i < nb; i += blockDim.x) {
+        const double* p = vp + (size_t)i * 24;
         a = dd_add(a, dd{p[0], p[1]});
     }
     __shared__ double shh[256], shl[256];
