@@ -80,7 +80,10 @@ enum { U1ML_FORM_AUTO = 0, U1ML_FORM_HISTORY = 1, U1ML_FORM_SPECTRAL = 2 };
 
 /* One ensemble: Ns^3 x Nt lattice (Sec. II), coupling beta = 1/g^2 and its
  * Philox key.  Every extent must be even and >= 2 (checkerboard across the
- * periodic wrap). */
+ * periodic wrap); the index arithmetic of the kernels further needs
+ * Nx Ny Nz / 2 < 2^24, Ny Nz < 2^22, Nt < 2^22 and the 4 V link words of
+ * one ensemble below 4 GiB (V < 2^28 sites in FP32, 2^27 in FP64; e.g.
+ * 256^3 x 14 in FP32), U1ML_EINVAL otherwise. */
 typedef struct {
     int ns[3];
     int nt;

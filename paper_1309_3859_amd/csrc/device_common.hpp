@@ -308,8 +308,9 @@ __device__ inline Coord step(Coord c, int dir, int s, int nx, int ny, int nz, in
 }
 
 // ---------------------------------------------------------------------------
-// Division-free index decode: q = a / b for 0 <= a, b > 0, a / b < 2^22,
-// from the FP32 reciprocal and one exact correction step.
+// Division-free index decode: q = a / b for 0 <= a < 2^31, 0 < b < 2^24
+// (the correction multiplies in 24 bits) and a / b < 2^22, from the FP32
+// reciprocal and one exact correction step.
 // ---------------------------------------------------------------------------
 __device__ inline int fdiv(int a, int b, float inv_b)
 {

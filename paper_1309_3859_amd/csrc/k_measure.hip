@@ -192,8 +192,10 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
     for (int k = 0; k < 12; ++k) vac[k] = 0.0;
     if (item < nsig * S) {
         const Geo g{E.nx, E.ny, E.nz, E.nt, E.nxh, E.nxh * E.ny, E.nxh * E.ny * E.nz};
-        // division-free decode: 1/N_sigma = (1/slice) / 2 and 1/Nx = (1/(Nx/2)) / 2 exactly
-        const int s = fdiv(item, nsig, 0.5f * E.inv_slice);
+        // division-free decode; N_sigma is even, so item / N_sigma = (item / 2) / (N_sigma / 2)
+        // with the divisor N_sigma / 2 (the slice) inside fdiv's 24-bit range, and
+        // 1/Nx = (1/(Nx/2)) / 2 exactly
+        const int s = fdiv(item >> 1, nsig >> 1, E.inv_slice);
         const int xs = item - s * nsig;
         const int yz = fdiv(xs, E.nx, 0.5f * E.inv_nxh);
         const int x = xs - yz * E.nx;

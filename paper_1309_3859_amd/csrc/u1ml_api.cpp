@@ -165,7 +165,11 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
         if (E.nt % P->tau_i != 0) return fail(err, "Nt must be a multiple of the inner tau");
         const double V = (double)E.ns[0] * E.ns[1] * E.ns[2] * E.nt;
         if (4.0 * V >= 4294967296.0) return fail(err, "4 V must fit in 32 bits (link ids)");
+        // the kernels address an ensemble's links with 32-bit byte offsets
+        if (4.0 * V * (P->precision == U1ML_FP64 ? 8 : 4) >= 4294967296.0)
+            return fail(err, "the links of one ensemble (4 V words) must stay below 4 GiB");
         if ((double)E.ns[1] * E.ns[2] >= 4194304.0) return fail(err, "Ny * Nz must be below 2^22");
+        if (E.nt >= 4194304) return fail(err, "Nt must be below 2^22");
         if ((double)E.ns[0] / 2 * E.ns[1] * E.ns[2] >= 16777216.0) return fail(err, "Ns^3 / 2 must be below 2^24");
         for (int i = 0; i < P->n_dirs; ++i) {
             const int d = P->dirs[i];

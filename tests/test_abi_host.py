@@ -61,6 +61,11 @@ BAD = [
     ("bad form", dict(form=3)),
     # a 66 x 66 plane orthogonal to the x axis holds more than 4096 sites
     ("spectral plane too large", dict(ens=((2, 66, 66), 4, 1.0), r=[1], form=2)),
+    # limits of the kernels' index arithmetic
+    ("Ns^3 / 2 >= 2^24", dict(ens=((324, 324, 324), 2, 1.0), r=[1])),
+    ("Nt >= 2^22", dict(ens=((2, 2, 2), 1 << 22, 1.0), r=[1])),
+    ("FP32 links of one ensemble >= 4 GiB", dict(ens=((256, 256, 256), 16, 1.0), r=[1], precision=1)),
+    ("FP64 links of one ensemble >= 4 GiB", dict(ens=((256, 256, 256), 8, 1.0), r=[1], precision=0)),
 ]
 
 
@@ -74,6 +79,13 @@ def test_planner_rejects_invalid_problems(u1, name, kw):
         u1.plan(_spec(u1, **kw))
     assert ei.value.status == 1  # EINVAL
     assert str(ei.value).strip() != "EINVAL:"
+
+
+@pytest.mark.parametrize("ns,nt,precision", [((256, 256, 256), 14, 1), ((256, 256, 256), 6, 0),
+                                             ((322, 322, 322), 8, 1), ((2, 2, 2), (1 << 22) - 2, 1)])
+def test_planner_accepts_lattices_at_the_limits(u1, ns, nt, precision):
+    info = u1.plan(_spec(u1, ensembles=[u1.Ens(ns, nt, 1.0)], r=[1], probes=[], comps=[], precision=precision))
+    assert info["link_bytes"] >= 4 * ns[0] * ns[1] * ns[2] * nt * (4 if precision else 8)
 
 
 def test_planner_accepts_presets_and_counts_updates(u1):

@@ -110,3 +110,29 @@ def test_full_size_measurement_chain(env, name):
             assert dco < rel * max(1.0, np.abs(want["CO"]).max())
         tol_v = 1e-12 if spec.precision == u1.FP64 else 1e-6
         assert np.max(np.abs(got["vac_sq"] - want["vac_sq"])) < tol_v
+
+
+def test_measurement_at_large_spatial_volume(env):
+    """256^3 x 4 (N_sigma = 2^24 sites, beyond the 24-bit range of a direct
+    site decode): one configuration without updates (n = 1, k = 0) equals
+    the plain definitions on the same links, C(r) = mean_x conj P(x) P(x + r e_x)
+    and the vacuum <O_sq> = 2 beta (1 - <cos theta_P>) of the plaquette kernel."""
+    u1, O, configs = env
+    ns, nt, beta = 256, 4, 1.0
+    spec = u1.Spec(ensembles=[u1.Ens((ns, ns, ns), nt, beta, seed=12)], levels=[(2, 1, 0)], r=[1, 2, 5], dirs=[0],
+                   precision=u1.FP32, max_configs=1)
+    say("large spatial volume", ns, nt)
+    ctx = u1.Context(spec)
+    ctx.init_links(u1.HOT)
+    ctx.multilevel()
+    got = spec.unpack(ctx.results()[0, 0])
+    plaq = ctx.plaquette()[0]
+    th = ctx.links(0).reshape(nt, ns, ns, ns, 4)  # [t][z][y][x][mu]
+    ctx.close()
+    P = np.exp(1j * th[..., 3].sum(axis=0))  # [z][y][x]
+    del th
+    for i, r in enumerate(spec.r):
+        want = np.mean(np.conj(P) * np.roll(P, -r, axis=2))
+        assert abs(got["C"][i] - want) < 1e-12, (r, got["C"][i], want)
+    # FP32 plaquette angles and sines in the measurement, FP64 in the plaquette kernel
+    assert np.max(np.abs(got["vac_sq"] - 2 * beta * (1 - plaq))) < 2e-6
