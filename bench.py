@@ -234,8 +234,8 @@ def run_counter_workload(spec, sched):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU decomposition is a design "
-              "note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path; "
+              "how a batch or one lattice would shard across GPUs is described in the design notes", file=sys.stderr)
         sys.exit(2)
     import torch
 

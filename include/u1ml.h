@@ -49,7 +49,7 @@ typedef enum {
     U1ML_ENOMEM = 2,  /* size overflow in the planner, or host allocation   */
     U1ML_EDEVICE = 3, /* a HIP call failed (message in u1ml_last_error)     */
     U1ML_ESTATE = 4,  /* call made in the wrong state (e.g. before init)    */
-    U1ML_ENOTSUP = 5  /* option not supported by this build                 */
+    U1ML_ENOTSUP = 5  /* not supported by the device or the runtime          */
 } u1ml_status;
 
 enum { U1ML_FP64 = 0, U1ML_FP32 = 1 };         /* link storage / update arithmetic */
