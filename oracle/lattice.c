@@ -292,7 +292,7 @@ double orc_bessel_ratio(double kappa)
     return t;
 }
 
-/* Multihit (Sec. II.C: "analytical multihit", Parisi-Petronzio-Rapuano):
+/* Analytic multihit (Sec. II.C; Parisi, Petronzio and Rapuano):
  * with every other link fixed, theta has density ~ exp(beta |A| cos(theta +
  * arg A)), so E[e^{i theta}] = e^{-i arg A} I_1(beta |A|) / I_0(beta |A|). */
 void orc_link_mean(const orc_lattice* lat, long site, int mu, double* re, double* im)

@@ -3,8 +3,8 @@
  * Polyakov-loop correlator and of the plaquette (field) insertions.
  *
  * TEST INFRASTRUCTURE ONLY (see u1_oracle.h).  Plain FP64 complex arithmetic,
- * running accumulators per spatial site (the paper's "extra lattices",
- * Sec. II.D), plain left-to-right sums.
+ * running accumulators per spatial site (the additional accumulator
+ * lattices of Sec. II.D), plain left-to-right sums.
  *
  * Paper sections followed (arXiv 1309.3859):
  *  - two-link operator T(x,t,r) = U_0(x,t)^dagger U_0(x + r mu, t), and
