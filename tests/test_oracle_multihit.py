@@ -1,5 +1,5 @@
-"""Oracle analytic multihit of the temporal links in the correlator averages
-(Sec. II.C "analytical multihit"), pinned to:
+"""Oracle analytic multihit (Sec. II.C) of the temporal links in the
+correlator averages, pinned to:
  - I_1/I_0 from an independent Bessel implementation (scipy);
  - the conditional mean e^{-i arg A} I_1/I_0(beta|A|) against direct numerical
    integration of e^{i theta} exp(beta Re(e^{i theta} A));
