@@ -430,11 +430,11 @@ hipError_t launch_scatter_links(const EnsDesc* d_ens, int ens, int precision, vo
 
 // ---------------------------------------------------------------------------
 // Plaquette means per orientation (E_x, E_y, E_z, B_x, B_y, B_z), FP64 sums.
-// Block (e, b) strides over the ensemble's sites; partials are summed in a
-// fixed order by k_plaq_final.
+// Work-group (e, b), one of kPlaqBlocks per ensemble, walks the ensemble's
+// sites in a fixed stride (V < 2^28 sites, so 32-bit indices) and reduces its
+// sums through LDS; k_plaq_final adds an ensemble's partials in a fixed-order
+// tree.
 // ---------------------------------------------------------------------------
-constexpr int kPlaqBlocks = 64;
-
 template <typename real>
 __global__ void __launch_bounds__(256) k_plaq_partial(const EnsDesc* __restrict__ ens, const real* __restrict__ links,
                                                       double* __restrict__ partials)
@@ -443,17 +443,17 @@ __global__ void __launch_bounds__(256) k_plaq_partial(const EnsDesc* __restrict_
     const int b = blockIdx.x % kPlaqBlocks;
     const EnsDesc& E = ens[e];
     LinkView<real> L{links + E.link_off, E.vh, E.nxh, E.ny, E.nz};
-    const long long V = 2ll * E.vh;
+    const int V = 2 * E.vh;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     static const int pa[6] = {0, 1, 2, 1, 2, 0};
     static const int pb[6] = {3, 3, 3, 2, 0, 1};
-    for (long long s = (long long)b * 256 + threadIdx.x; s < V; s += 256ll * kPlaqBlocks) {
-        const int x = (int)(s % E.nx);
-        long long r = s / E.nx;
-        const int y = (int)(r % E.ny);
+    for (int s = b * 256 + (int)threadIdx.x; s < V; s += 256 * kPlaqBlocks) {
+        const int x = s % E.nx;
+        int r = s / E.nx;
+        const int y = r % E.ny;
         r /= E.ny;
-        const int z = (int)(r % E.nz);
-        const int t = (int)(r / E.nz);
+        const int z = r % E.nz;
+        const int t = r / E.nz;
         const Coord c = {x, y, z, t};
         const int p = (x + y + z + t) & 1;
 #pragma unroll
@@ -477,14 +477,24 @@ __global__ void __launch_bounds__(256) k_plaq_partial(const EnsDesc* __restrict_
     if (threadIdx.x < 6) partials[(size_t)blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void k_plaq_final(const EnsDesc* __restrict__ ens, const double* __restrict__ partials, double* __restrict__ out)
+// one 256-thread work-group per ensemble: thread i adds partials i, i + 256,
+// ... in order, then an LDS tree
+__global__ void __launch_bounds__(256) k_plaq_final(const EnsDesc* __restrict__ ens,
+                                                    const double* __restrict__ partials, double* __restrict__ out)
 {
     const int e = blockIdx.x;
-    const int o = threadIdx.x;
-    if (o >= 6) return;
-    double s = 0.0;
-    for (int b = 0; b < kPlaqBlocks; ++b) s += partials[((size_t)e * kPlaqBlocks + b) * 6 + o];
-    out[e * 6 + o] = s / (2.0 * (double)ens[e].vh);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < kPlaqBlocks; b += blockDim.x)
+        for (int o = 0; o < 6; ++o) acc[o] += partials[((size_t)e * kPlaqBlocks + b) * 6 + o];
+    __shared__ double sh[6][256];
+    for (int o = 0; o < 6; ++o) sh[o][threadIdx.x] = acc[o];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int o = 0; o < 6; ++o) sh[o][threadIdx.x] += sh[o][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[e * 6 + threadIdx.x] = sh[threadIdx.x][0] / (2.0 * (double)ens[e].vh);
 }
 
 hipError_t launch_plaquette(const EnsDesc* d_ens, int n_ens, int, int precision, const void* links,
@@ -496,7 +506,7 @@ hipError_t launch_plaquette(const EnsDesc* d_ens, int n_ens, int, int precision,
     else
         hipLaunchKernelGGL(k_plaq_partial<float>, dim3(n_ens * kPlaqBlocks), dim3(256), 0, st, d_ens,
                            (const float*)links, d_partials);
-    hipLaunchKernelGGL(k_plaq_final, dim3(n_ens), dim3(64), 0, st, d_ens, d_partials, d_out);
+    hipLaunchKernelGGL(k_plaq_final, dim3(n_ens), dim3(256), 0, st, d_ens, d_partials, d_out);
     return hipGetLastError();
 }
 

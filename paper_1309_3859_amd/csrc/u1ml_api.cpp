@@ -387,7 +387,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     Lo->s_upd = take(sizeof(uint32_t) * n);
     Lo->s_ring = take(sizeof(int) * 4);
     Lo->s_vpart = take(sizeof(double) * VAC);
-    Lo->s_ppart = take(sizeof(double) * 6 * 64 * n);
+    Lo->s_ppart = take(sizeof(double) * 6 * kPlaqBlocks * n);
     Lo->s_pout = take(sizeof(double) * 6 * n);
     Lo->s_count = take(sizeof(unsigned long long) * 2);
     Lo->s_stage = take(sizeof(double) * 4 * maxV);

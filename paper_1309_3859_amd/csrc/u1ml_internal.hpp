@@ -63,6 +63,7 @@ constexpr int kUpdateClasses = 4;  // temporal, spatial full, spatial inner tau,
 constexpr int kProdChunk = 2048;    // slab products: (axis, site) items per work-group
 constexpr int kProdQ = 26;          // slab products: correlator re, im and 12 insertion quantities re, im
 constexpr int kConLds = 49152;      // contraction: LDS budget per work-group (bytes)
+constexpr int kPlaqBlocks = 1024;   // plaquette means: work-groups (and partials) per ensemble
 
 // --- launchers (k_update.hip) ---
 hipError_t launch_init_links(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,

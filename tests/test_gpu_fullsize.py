@@ -136,3 +136,37 @@ def test_measurement_at_large_spatial_volume(env):
         assert abs(got["C"][i] - want) < 1e-12, (r, got["C"][i], want)
     # FP32 plaquette angles and sines in the measurement, FP64 in the plaquette kernel
     assert np.max(np.abs(got["vac_sq"] - 2 * beta * (1 - plaq))) < 2e-6
+
+
+def test_update_phases_at_the_largest_lattice(env):
+    """322^3 x 8 in FP32, the largest cube the planner accepts: 4.27 GB of
+    links, so the kernels' 32-bit byte offsets reach 2^32 - 2.2e7 (the odd
+    temporal links, updated here, are the last array).  An overrelaxation
+    phase keeps the total action, the same phase applied twice restores every
+    plaquette mean, and a heatbath phase raises the temporal plaquettes and
+    leaves every angle in range."""
+    u1, O, configs = env
+    ns, nt = 322, 8
+    spec = u1.Spec(ensembles=[u1.Ens((ns, ns, ns), nt, 1.0, seed=13)], levels=[(2, 1, 0)], r=[1], dirs=[0],
+                   precision=u1.FP32, max_configs=1)
+    info = u1.plan(spec)
+    assert 2 ** 31 < 16 * ns ** 3 * nt <= info["link_bytes"] < 2 ** 32
+    say("largest lattice", ns, nt, info["ws_bytes"])
+    ctx = u1.Context(spec)
+    ctx.init_links(u1.HOT)
+    p0 = ctx.plaquette()[0]
+    ctx.phase(u1.OVERRELAX, 3, 1)
+    p1 = ctx.plaquette()[0]
+    ctx.phase(u1.OVERRELAX, 3, 1)
+    p2 = ctx.plaquette()[0]
+    ctx.phase(u1.HEATBATH, 3, 1)
+    p3 = ctx.plaquette()[0]
+    bad = ctx.health()
+    ctx.close()
+    say("plaquettes", p0, p1, p2, p3)
+    assert abs(p1.sum() - p0.sum()) < 1e-6
+    assert np.max(np.abs(p1 - p0)) > 1e-6  # it moved action between the three temporal orientations (~1/sqrt(V))
+    assert np.max(np.abs(p2 - p0)) < 1e-6
+    assert p3[:3].sum() > p0[:3].sum() + 0.05
+    assert np.array_equal(p3[3:], p0[3:])  # spatial plaquettes hold no temporal link
+    assert bad == 0
