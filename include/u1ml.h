@@ -52,6 +52,18 @@ typedef enum {
     U1ML_ENOTSUP = 5  /* not supported by the device or the runtime          */
 } u1ml_status;
 
+/* Errors common to every call: nothing throws or aborts across this
+ * interface; every call returns a status and records a message for
+ * u1ml_last_error.  EINVAL for a NULL context or output pointer, an
+ * ensemble index outside [0, n_ens), a kind, direction, parity or count out
+ * of range, a tau that is neither <= 1 nor one of the problem's level
+ * thicknesses, or a host buffer of the wrong length.  ESTATE for updates,
+ * timings, plaquettes or configurations before the links are set
+ * (u1ml_init_links or u1ml_set_links), and for u1ml_multilevel with a full
+ * results ring.  EDEVICE when a HIP call fails;
+ * an asynchronous call's kernel errors surface at the next synchronising
+ * call.  Calls on one context must come from one host thread at a time. */
+
 enum { U1ML_FP64 = 0, U1ML_FP32 = 1 };         /* link storage / update arithmetic */
 enum { U1ML_COLD = 0, U1ML_HOT = 1 };          /* start of u1ml_init_links         */
 enum { U1ML_HEATBATH = 0, U1ML_OVERRELAX = 1, U1ML_METROPOLIS = 2 }; /* kind of u1ml_phase */
