@@ -8,7 +8,8 @@
 // One work-item per link of the phase (direction mu, parity p, not frozen),
 // every ensemble of the batch in the same launch: work-group b reads its
 // ensemble, its block index within that ensemble and the geometry from one
-// record (UpdBlock), the records dealt to the 8 XCDs in contiguous stretches.
+// record (UpdBlock), the records dealt to the 8 XCDs in contiguous stretches
+// and, within an ensemble, ordered time slice fastest (set by the host).
 // The staple of a link reads 18 angles: 12 of the other parity (coalesced,
 // shifted by one site), 6 of the same parity; none of them is written by the
 // phase, so the update is in place.  The all-link kernels below (start,
