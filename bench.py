@@ -16,6 +16,7 @@ it writes once) divided by its average launch time from HIP events.
 from __future__ import annotations
 
 import argparse
+import inspect
 import json
 import os
 import sys
@@ -102,6 +103,8 @@ def parse():
                     help="for kernel traces of the large presets: sublattice updates of the inner level (0: the preset's)")
     ap.add_argument("--n-outer", type=int, default=0,
                     help="for kernel traces of the two-level presets: updates of the outer level (0: the preset's)")
+    ap.add_argument("--n-ens", type=int, default=0,
+                    help="for the replicas preset: number of replicas in the batch (0: the preset's 16)")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: one 256 MiB device copy (calibration of the byte counters), "
                          "then 20 launches each of the heatbath and overrelaxation phases of the dominant kernel")
@@ -244,8 +247,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     preset = configs.PRESETS[args.workload]
 
+    if args.n_ens and "n_ens" not in inspect.signature(preset).parameters:
+        sys.exit(f"--n-ens applies to the replicas preset, not to {args.workload}")
+
     def make():
-        spec, sched = preset()
+        spec, sched = preset(n_ens=args.n_ens) if args.n_ens else preset()
         lv = [list(x) for x in spec.levels]
         if args.n_inner:
             lv[-1][1] = args.n_inner

@@ -61,6 +61,17 @@ def c4_batched(precision: int = FP32, n_iter: int = 50, max_configs: int = 4):
     return spec, {"start": HOT, "therm": 500}
 
 
+def replicas(n_ens: int = 16, precision: int = FP32, n_iter: int = 50, max_configs: int = 4):
+    """n_ens independent replicas of the paper's 24^3 x 8 lattice at beta = 0.99
+    (Philox key (seed 9, key_id j)) in one batch; one level (thickness 2, 50
+    updates), correlators r = 1..12 along x.  The batch-size study: how the
+    rate of one small lattice grows when replicas share every launch."""
+    ens = [Ens((24, 24, 24), 8, 0.99, seed=9, key_id=j) for j in range(n_ens)]
+    spec = Spec(ensembles=ens, levels=[(2, n_iter, 1)], r=list(range(1, 13)), dirs=[0], precision=precision, n_or=3,
+                max_configs=max_configs)
+    return spec, {"start": HOT, "therm": 500}
+
+
 def c5_largest(n_outer: int = 40, n_inner: int = 100, full_map: bool = True, max_configs: int = 1):
     """48^3 x 12, beta = 1.005, two levels (2 inside 4; 100 and 40 updates),
     r = 2..20 along x, the full transverse map |x_perp| <= 12 of all six
@@ -106,4 +117,4 @@ def out_of_cache(ns: int = 128, nt: int = 16):
 
 
 PRESETS = {"c1": c1_plain_fp64, "c2": c2_fp32_profiles, "c3": c3_precision, "c4": c4_batched, "c5": c5_largest,
-           "dram": out_of_cache}
+           "dram": out_of_cache, "replicas": replicas}
