@@ -101,9 +101,14 @@ def test_planner_accepts_presets_and_counts_updates(u1):
     assert p["updates_per_config"] == 10 * 4 * per_pass == 25600
     assert p["updates_per_sweep"] == 4 * 4 * L ** 4
     assert p["n_doubles_per_config"] == spec.n_doubles_per_config()
-    for name in ("c2", "c3", "c4"):
+    for name in ("c2", "c3", "c4", "replicas"):
         s, _ = configs.PRESETS[name]()
         assert u1.plan(s)["ws_bytes"] < 16 * 2**30
+    # replicas: N copies of one lattice plan N times its updates
+    one = u1.plan(configs.replicas(n_ens=1)[0])["updates_per_config"]
+    # per sweep of 4 passes at tau = 2: every temporal link (V) and the spatial links of half the slices (3V/2)
+    V = 24 ** 3 * 8
+    assert u1.plan(configs.replicas(n_ens=32)[0])["updates_per_config"] == 32 * one == 32 * 50 * 4 * (V + 3 * V // 2)
 
 
 def test_paper_memory_example(u1):
