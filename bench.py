@@ -87,6 +87,22 @@ def counter_traffic():
         return None
 
 
+def metropolis_acceptance(ctx, spec, tau):
+    """Acceptance rate of one phase of the paper's Metropolis update (step
+    metro_delta) over the whole batch: spatial direction x, even sites, inner
+    slabs; the fraction of the phase's links whose angle changed."""
+    from paper_1309_3859_amd import analysis, u1ml
+
+    before = [ctx.links(e) for e in range(len(spec.ensembles))]
+    ctx.phase(u1ml.METROPOLIS, 0, 0, tau)
+    moved = total = 0
+    for e, ens in enumerate(spec.ensembles):
+        m = analysis.phase_mask(ens.ns, ens.nt, 0, 0, tau)
+        moved += int(((before[e] != ctx.links(e)) & m).sum())
+        total += int(m.sum())
+    return {"delta": spec.metro_delta, "acceptance": moved / total, "links": total}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +330,7 @@ def main():
     line["roofline"]["copy_reference"] = copy_reference(b)
     # the same batch in full-lattice sweeps (thermalisation), next to the multilevel rate of `value`
     line["full_sweeps"] = {"value": time_full_sweeps(ctx), "unit": "link updates/s"}
+    line["metropolis"] = metropolis_acceptance(ctx, spec, tau)
     if not args.no_fp64 and spec.precision == u1ml.FP32:
         # the same workload with FP64 link storage and update arithmetic
         spec64, _ = make()

@@ -235,3 +235,26 @@ def peak_position(betas, chi, n_points: int = 5):
     bb, cc = b[lo:lo + n_points], c[lo:lo + n_points]
     a2, a1, _ = np.polyfit(bb, cc, 2)
     return float(-a1 / (2 * a2))
+
+
+def phase_mask(ns: Sequence[int], nt: int, mu: int, parity: int, tau: int = 0) -> np.ndarray:
+    """Links one checkerboard phase updates, as a boolean mask over the
+    canonical link view (element mu + 4 (x + Nx (y + Ny (z + Nz t)))):
+    direction mu at the sites of the given parity, without the frozen spatial
+    links of the layers t = 0 mod tau when tau > 1 (Sec. II.C.1)."""
+    nx, ny, nz = ns
+    t, z, y, x = np.meshgrid(np.arange(nt), np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    sites = (x + y + z + t) % 2 == parity
+    if mu < 3 and tau > 1:
+        sites &= t % tau != 0
+    mask = np.zeros((nt, nz, ny, nx, 4), dtype=bool)
+    mask[..., mu] = sites
+    return mask.reshape(-1)
+
+
+def acceptance_rate(before: np.ndarray, after: np.ndarray, ns: Sequence[int], nt: int, mu: int, parity: int,
+                    tau: int = 0) -> float:
+    """Acceptance rate of one Metropolis phase (Sec. II): the fraction of the
+    phase's links whose angle changed between the two canonical views."""
+    m = phase_mask(ns, nt, mu, parity, tau)
+    return float(np.mean(before[m] != after[m]))

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from helpers.inputs import random_links, random_links_fp32
+from paper_1309_3859_amd import analysis as A
 from helpers.stats import batch_mean_err, circ_dist
 
 pytestmark = pytest.mark.gpu
@@ -71,6 +72,9 @@ def test_metropolis_phases(env, prec):
                 moved = int(np.count_nonzero(circ_dist(ref.links(), th) > 0))
                 if p == u1.FP64:
                     assert d.max() < 1e-12, (tau, mu, par, d.max())
+                    # identical decisions, so identical acceptance rates
+                    args = ((6, 4, 4), 4, mu, par, tau)
+                    assert A.acceptance_rate(th, ctx.links(0), *args) == A.acceptance_rate(th, ref.links(), *args)
                 else:
                     assert int(np.count_nonzero(d > 2e-5)) <= 2, (tau, mu, par)
                 assert moved > 0

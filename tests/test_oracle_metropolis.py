@@ -108,3 +108,38 @@ def test_metropolis_4d_strong_coupling(orc):
     m, e = batch_mean_err(vals.mean(axis=1))
     u = special.iv(1, beta) / special.iv(0, beta)
     assert abs(m - u) < max(4 * e, 10 * u**5), (m, e, u)
+
+
+def test_phase_mask_and_acceptance_rate(orc):
+    """The host's phase mask holds exactly the links an oracle phase may move
+    (all of them at beta = 0), and the acceptance rate lies strictly between 0
+    and 1 at beta = 1 and falls as the proposal step grows."""
+    from paper_1309_3859_amd import analysis as A
+
+    ns, nt = (4, 6, 4), 4
+    V = 4 * 6 * 4 * 4
+    for tau in (0, 2):
+        for mu in range(4):
+            for par in (0, 1):
+                m = A.phase_mask(ns, nt, mu, par, tau)
+                assert m.sum() == (V // 2 if (mu == 3 or tau == 0) else V // 4)
+                lat = orc.Lattice(4, list(ns) + [nt], 0.0, seed=44, key_id=mu)
+                lat.init(1)
+                lat.set_update(2, 0.9)
+                th0 = lat.links()
+                lat.phase(2, mu, par, tau)
+                th1 = lat.links()
+                assert np.array_equal(th0 != th1, m)
+                assert A.acceptance_rate(th0, th1, ns, nt, mu, par, tau) == 1.0
+    rates = []
+    for delta in (0.3, 1.0, 3.0):
+        lat = orc.Lattice(4, list(ns) + [nt], 1.0, seed=45)
+        lat.init(1)
+        lat.set_update(2, delta)
+        lat.sweeps(3)
+        th0 = lat.links()
+        lat.phase(2, 1, 0, 0)
+        th1 = lat.links()
+        assert not np.any((th0 != th1) & ~A.phase_mask(ns, nt, 1, 0, 0))
+        rates.append(A.acceptance_rate(th0, th1, ns, nt, 1, 0, 0))
+    assert 0.0 < rates[2] < rates[1] < rates[0] < 1.0, rates
