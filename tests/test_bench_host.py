@@ -30,3 +30,21 @@ def test_multi_gpu_request_is_refused(monkeypatch, capsys):
     else:
         raise AssertionError("bench.py accepted --gpus 2")
     assert "one GPU only" in capsys.readouterr().err
+
+
+def test_cpu_baseline_runs_one_oracle_process_per_ensemble():
+    """The oracle leg runs each ensemble in a child interpreter (no GPU), and
+    its update count is the planner's for the sampled levels."""
+    from paper_1309_3859_amd import configs, u1ml
+
+    spec, _ = configs.beta_scan([0.9, 1.0, 1.1], ns=4, nt=4)
+    r = bench.cpu_baseline(spec, 5.0, workers=2)
+    assert r["kind"] == "oracle" and r["cores"] == 2, r
+    assert "one ensemble per process" in r["sample"], r
+    assert r["value"] > 0 and r["single_thread"]["value"] > 0
+    # the children's update count equals the planner's for the same (cut-down) levels
+    job = {"ns": [4, 4, 4], "nt": 4, "beta": 1.0, "seed": 7, "key_id": 0, "levels": bench._sample_levels(spec),
+           "r": [1], "dirs": [0], "probes": [], "comps": [], "n_or": spec.n_or}
+    spec.levels = [tuple(lv) for lv in bench._sample_levels(spec)]
+    spec.ensembles = spec.ensembles[:1]
+    assert bench.oracle_configuration(job)["updates"] == u1ml.plan(spec)["updates_per_config"]
