@@ -103,6 +103,49 @@ def metropolis_acceptance(ctx, spec, tau):
     return {"delta": spec.metro_delta, "acceptance": moved / total, "links": total}
 
 
+def measurement_accuracy(ctx64, spec):
+    """Accuracy of the FP32 form against the FP64 form on identical inputs:
+    the FP64 context's current links, rounded to FP32 for both sides, (1)
+    measured once without updates by each precision (largest relative
+    difference of the correlators C(r) and of the vacuum plaquette over the
+    batch), then (2) updated by one overrelaxation and one heatbath phase
+    with the same counters (circular differences of the links: median,
+    99.9th percentile, maximum; a heatbath link whose accept decision flips
+    under FP32 rounding lands elsewhere)."""
+    import dataclasses
+
+    import numpy as np
+
+    from paper_1309_3859_amd import u1ml
+
+    links = [np.asarray(ctx64.links(e), dtype=np.float32).astype(np.float64) for e in range(len(spec.ensembles))]
+    tau = spec.levels[-1][0]
+    out, after = {}, {}
+    for prec in (u1ml.FP32, u1ml.FP64):
+        sp = dataclasses.replace(spec, levels=[(tau, 1, 0)], precision=prec, max_configs=1, _keep=[])
+        c = u1ml.Context(sp)
+        for e, th in enumerate(links):
+            c.set_links(th, e)
+            c.set_counter(0, e)
+        c.multilevel()
+        out[prec] = [sp.unpack(rec) for rec in c.results()[0]]
+        c.phase(u1ml.OVERRELAX, 0, 0, tau)
+        c.phase(u1ml.HEATBATH, 0, 1, tau)
+        after[prec] = [c.links(e) for e in range(len(links))]
+        c.close()
+    pairs = list(zip(out[u1ml.FP32], out[u1ml.FP64]))
+    rel_c = max(float(np.max(np.abs(a["C"] - b["C"]) / np.abs(b["C"]))) for a, b in pairs)
+    rel_v = max(float(np.max(np.abs(a["vac_sq"] - b["vac_sq"]) / np.abs(b["vac_sq"]))) for a, b in pairs)
+    moved = np.concatenate([(a != th) | (b != th) for a, b, th in zip(after[u1ml.FP32], after[u1ml.FP64], links)])
+    d = np.concatenate([np.abs(np.angle(np.exp(1j * (a - b)))) for a, b in zip(after[u1ml.FP32], after[u1ml.FP64])])
+    d = d[moved]
+    return {"measurement": "C(r) and vacuum <O_sq>, one measurement without updates on the same FP32-rounded links",
+            "max_rel_diff_C": rel_c, "max_rel_diff_vacuum": rel_v,
+            "update": "links after one overrelaxation and one heatbath phase from the same links and counters",
+            "link_diff_median": float(np.median(d)), "link_diff_p999": float(np.quantile(d, 0.999)),
+            "link_diff_max": float(d.max()), "links_updated": int(d.size)}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,7 +446,8 @@ def main():
         ctx64.sweeps(5)
         ms64 = time_steps(ctx64, args.steps, args.warmup)
         line["plain_fp64"] = {"value": upd * args.steps / (ms64 / 1e3), "unit": "link updates/s",
-                              "ms_per_step": ms64 / args.steps, "dtype": "f64"}
+                              "ms_per_step": ms64 / args.steps, "dtype": "f64",
+                              "accuracy_of_f32": measurement_accuracy(ctx64, spec)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(line), flush=True)
