@@ -59,8 +59,7 @@ struct RetryQ {
 template <typename real, int KIND, int MU>
 __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens, const UpdBlock* __restrict__ blocks,
                                                  real* __restrict__ links, const uint32_t* __restrict__ upd,
-                                                 int pass_offset, int parity, int tau, float inv_tm1,
-                                                 float inv_tau)
+                                                 int pass_offset, int parity, int tau, float inv_tm1)
 {
     constexpr bool kQueue = (KIND == 0) && (sizeof(real) == 4);
     // a padding block of the XCD-aware order carries a block index past its
@@ -71,9 +70,8 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
     const Geo g{B.nx, B.ny, B.nz, B.nt, B.nxh, B.nxh * B.ny, B.nxh * B.ny * B.nz};
     const bool masked = (MU < 3) && (tau > 1);
     const int slice = g.st;
-    const int active_t = masked ? g.nt - fdiv(g.nt, tau, inv_tau) : g.nt;
     const int item = B.blk * (int)blockDim.x + (int)threadIdx.x;
-    const bool active = item < slice * active_t;
+    const bool active = item < B.n_items;
     if (!kQueue && !active) return;
     real* lb = links + B.link_off;
     const unsigned vh = (unsigned)B.vh;
@@ -85,8 +83,12 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
         const int rem = item - (int)__umul24(j, slice);
         int t = j;
         if (masked) {
-            const int jt = fdiv(j, tau - 1, inv_tm1);
-            t = jt * tau + 1 + (j - jt * (tau - 1));
+            if (tau == 2) {  // uniform: the thinnest slabs skip the division
+                t = 2 * j + 1;
+            } else {
+                const int jt = fdiv(j, tau - 1, inv_tm1);
+                t = jt * tau + 1 + (j - jt * (tau - 1));
+            }
         }
         const int yz = fdiv(rem, g.sy, B.inv_nxh);
         const int xh = rem - (int)__umul24(yz, g.sy);
@@ -226,27 +228,27 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
 template <typename real, int KIND, int MU>
 static void launch_update_mu(dim3 g, dim3 b, size_t lds, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
                              const EnsDesc* d_ens, const UpdBlock* d_bmap, real* links, const uint32_t* d_upd,
-                             int pass_offset, int parity, int tau, float inv_tm1, float inv_tau)
+                             int pass_offset, int parity, int tau, float inv_tm1)
 {
     if (ev0)
         hipExtLaunchKernelGGL((k_update<real, KIND, MU>), g, b, lds, st, ev0, ev1, 0, d_ens, d_bmap, links, d_upd,
-                              pass_offset, parity, tau, inv_tm1, inv_tau);
+                              pass_offset, parity, tau, inv_tm1);
     else
         hipLaunchKernelGGL((k_update<real, KIND, MU>), g, b, lds, st, d_ens, d_bmap, links, d_upd, pass_offset,
-                           parity, tau, inv_tm1, inv_tau);
+                           parity, tau, inv_tm1);
 }
 
 template <typename real, int KIND>
 static void launch_update_t(dim3 g, dim3 b, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const EnsDesc* d_ens,
                             const UpdBlock* d_bmap, real* links, const uint32_t* d_upd, int pass_offset, int mu,
-                            int parity, int tau, float inv_tm1, float inv_tau)
+                            int parity, int tau, float inv_tm1)
 {
     const size_t lds = (KIND == 0 && sizeof(real) == 4) ? sizeof(RetryQ) * b.x : 0;
     switch (mu) {
-    case 0: launch_update_mu<real, KIND, 0>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1, inv_tau); break;
-    case 1: launch_update_mu<real, KIND, 1>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1, inv_tau); break;
-    case 2: launch_update_mu<real, KIND, 2>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1, inv_tau); break;
-    default: launch_update_mu<real, KIND, 3>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1, inv_tau); break;
+    case 0: launch_update_mu<real, KIND, 0>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 1: launch_update_mu<real, KIND, 1>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    case 2: launch_update_mu<real, KIND, 2>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
+    default: launch_update_mu<real, KIND, 3>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
     }
 }
 
@@ -258,24 +260,23 @@ hipError_t launch_update(const EnsDesc* d_ens, const UpdBlock* d_bmap, int total
     if ((ev_start == nullptr) != (ev_stop == nullptr)) return hipErrorInvalidValue;
     const dim3 g(total_blocks), b(block);
     const float inv_tm1 = tau > 1 ? 1.0f / (float)(tau - 1) : 1.0f;
-    const float inv_tau = tau > 1 ? 1.0f / (float)tau : 1.0f;
     if (kind < 0 || kind > 2) return hipErrorInvalidValue;
     if (precision == 0) {
         double* lk = (double*)links;
         if (kind == 0)
-            launch_update_t<double, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
+            launch_update_t<double, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else if (kind == 1)
-            launch_update_t<double, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
+            launch_update_t<double, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else
-            launch_update_t<double, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
+            launch_update_t<double, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
     } else {
         float* lk = (float*)links;
         if (kind == 0)
-            launch_update_t<float, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
+            launch_update_t<float, 0>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else if (kind == 1)
-            launch_update_t<float, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
+            launch_update_t<float, 1>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
         else
-            launch_update_t<float, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1, inv_tau);
+            launch_update_t<float, 2>(g, b, st, ev_start, ev_stop, d_ens, d_bmap, lk, d_upd, pass_offset, mu, parity, tau, inv_tm1);
     }
     return hipGetLastError();
 }

@@ -587,6 +587,7 @@ void build_update_tabs(const u1ml_ctx* c, Lane& L)
     std::memset(&pad, 0, sizeof pad);
     pad.e = -1;
     L.h_bmap.assign((size_t)kUpdateClasses * L.bmap_stride, pad);
+    const std::vector<long long>* items[kUpdateClasses] = {&it0, &it1, &it2, &it3};
     for (int cls = 0; cls < kUpdateClasses; ++cls) {
         const int* b = &L.h_bstart[(size_t)(kTabUpd + cls) * (n + 1)];
         const int total = b[n];
@@ -607,6 +608,7 @@ void build_update_tabs(const u1ml_ctx* c, Lane& L)
             r.inv_ny = E.inv_ny;
             r.res_index = E.res_index;
             r.link_off = E.link_off;
+            r.n_items = (int)(*items[cls])[e];
             // Time slice fastest: when a slice of sites is a whole number of
             // blocks, the blocks of one stretch of the slice at consecutive
             // times follow each other, so the links a slice shares with the

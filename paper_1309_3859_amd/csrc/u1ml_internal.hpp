@@ -34,7 +34,8 @@ struct EnsDesc {
 
 // One work-group of an update launch: its ensemble and block index within it
 // (a padding block of the XCD-aware order has an index past the ensemble's
-// links), with the geometry the update kernel needs before its loads, so that
+// links), the number of links of the ensemble that the launch's phase class
+// updates, and the geometry the update kernel needs before its loads, so that
 // one 64-byte scalar load replaces a block-map load followed by descriptor
 // loads.
 struct alignas(64) UpdBlock {
@@ -43,7 +44,8 @@ struct alignas(64) UpdBlock {
     float inv_slice, inv_nxh, inv_ny;
     int res_index;
     long long link_off;
-    int pad0, pad1;
+    int n_items;  // non-frozen links of one (direction, parity) of this class
+    int pad1;
 };
 static_assert(sizeof(UpdBlock) == 64, "UpdBlock is one 64-byte scalar load");
 
