@@ -149,22 +149,27 @@ __device__ inline void plaq_O<float>(float th, double beta, double sqrt_beta, do
     *olin = sqrt_beta * (double)s;
 }
 
-// Sum of 12 per-thread doubles over a 256-thread block in a fixed order
-// (through LDS, then each wave reduces three of the quantities), added to the
-// block's running double-double partials acc[12][2] of the configuration; the
-// first measurement (first != 0) overwrites them instead, so they need no
-// clearing between configurations.
+// Sum of 12 per-thread doubles over a 256-thread block in a fixed order (lanes
+// l and l + 32 of a wave added by one exchange, the 128 pair sums staged in
+// LDS, then each wave reduces three of the quantities), added to the block's
+// running double-double partials acc[12][2] of the configuration; the first
+// measurement (first != 0) overwrites them instead, so they need no clearing
+// between configurations.  12 KB of LDS, so that LDS does not limit a CU to
+// fewer work-groups than its wave slots hold.
 __device__ inline void block_sum12(const double* v, double* acc, int first)
 {
-    __shared__ double red[12][256];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) red[k][threadIdx.x] = v[k];
-    __syncthreads();
+    __shared__ double red[12][128];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const double a = v[k] + __shfl_xor(v[k], 32);
+        if (lane < 32) red[k][wave * 32 + lane] = a;
+    }
+    __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
         const int k = 3 * wave + kk;
-        double a = red[k][lane] + red[k][lane + 64] + red[k][lane + 128] + red[k][lane + 192];
+        double a = red[k][lane] + red[k][lane + 64];
         for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
         if (lane == 0) {
             const dd r = first ? dd{a, 0.0} : dd_add(dd{acc[2 * k], acc[2 * k + 1]}, a);
