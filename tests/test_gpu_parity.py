@@ -140,6 +140,39 @@ def test_every_phase_matches_oracle(env, ns, nt, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_heatbath_at_zero_coupling(env, precision):
+    """beta = 0, the degenerate case of the update: every link has kappa = 0
+    and its new angle is uniform from the first Philox word.  Each heatbath
+    phase equals the oracle's (FP64 within 1e-12, FP32 storage within 2e-5),
+    and a full sweep leaves angles uniform on [-pi, pi) (Kolmogorov-Smirnov)."""
+    from scipy import stats
+
+    u1, O, torch = env
+    ns, nt = (6, 4, 4), 4
+    V = int(np.prod(ns)) * nt
+    spec, ctx = _ctx(u1, ns, nt, beta=0.0, precision=precision, seed=17, key_id=3)
+    ref = O.Lattice(4, list(ns) + [nt], 0.0, seed=17, key_id=3)
+    th0 = random_links_fp32(V, 8) if precision else random_links(V, 8)
+    tol = 1e-12 if precision == 0 else 2e-5
+    for mu, p, tau in itertools.product(range(4), (0, 1), (0, 2)):
+        ctx.set_links(th0)
+        ctx.set_counter(4)
+        ref.set_links(th0)
+        ref.counter = 4
+        ctx.phase(0, mu, p, tau)
+        ref.phase(0, mu, p, tau)
+        d = circ_dist(ctx.links(0), ref.links())
+        assert d.max() < tol, (mu, p, tau, d.max())
+    big = u1.Spec(ensembles=[u1.Ens((8, 8, 8), 8, 0.0, seed=18)], levels=[(2, 1, 1)], r=[1], precision=precision,
+                  n_or=0)
+    c2 = u1.Context(big)
+    c2.init_links(u1.COLD)
+    c2.sweeps(1)
+    th = c2.links(0)
+    assert stats.kstest((th + np.pi) / (2 * np.pi), "uniform").pvalue > 1e-3
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_plaquette_matches_oracle(env, precision):
     u1, O, torch = env
     ns, nt = (6, 4, 2), 8
