@@ -89,7 +89,7 @@ static int l_mid(int r, int comp)
 
 long orc_ml_result_size(const orc_ml_spec* sp)
 {
-    return 2L * sp->n_r + 4L * sp->n_r * sp->n_probe * sp->n_comp + 12L;
+    return 2L * sp->n_r + 4L * sp->n_r * sp->n_probe * sp->n_comp + 12L + sp->n_r;
 }
 
 typedef struct {
@@ -206,49 +206,123 @@ static void measure(const ctx_t* c, int tau, cplx* Tacc, cplx* TOacc, double* vs
     }
 }
 
+/* Products over slabs as a mantissa and a binary exponent.  The signal
+ * <P^dagger P> falls exponentially with r N_t (about 1e-15 at the paper's
+ * largest separations, Sec. II.C.2 and Fig. 4), and a lattice of many slabs
+ * multiplies many averages of modulus below one, so a plain FP64 product can
+ * leave the range of normal numbers.  After every factor the product is
+ * rescaled by a power of two so that the larger of |re|, |im| lies in [1, 2);
+ * a zero product stays zero. */
+typedef struct {
+    cplx m;
+    long e;
+} scplx;
+
+static scplx s_norm(cplx m, long e)
+{
+    scplx z;
+    double a = fmax(fabs(m.re), fabs(m.im));
+    z.m = m;
+    z.e = e;
+    if (a == 0.0 || !isfinite(a)) return z;
+    int k = ilogb(a);
+    z.m = c_make(ldexp(m.re, -k), ldexp(m.im, -k));
+    z.e = e + k;
+    return z;
+}
+
+static scplx s_mul(scplx a, cplx b) { return s_norm(c_mul(a.m, b), a.e); }
+
+static int s_zero(scplx a) { return a.m.re == 0.0 && a.m.im == 0.0; }
+
+/* value of a * 2^-E as a plain double */
+static cplx s_rel(scplx a, long E)
+{
+    long k = a.e - E;
+    if (k < -2200) k = -2200; /* far below the smallest subnormal: zero */
+    return c_make(ldexp(a.m.re, (int)k), ldexp(a.m.im, (int)k));
+}
+
+void orc_scaled_product(long n, const double* re, const double* im, double* mre, double* mim, long* ex)
+{
+    scplx p = s_norm(c_make(1.0, 0.0), 0);
+    for (long i = 0; i < n; ++i) p = s_mul(p, c_make(re[i], im[i]));
+    *mre = p.m.re;
+    *mim = p.m.im;
+    *ex = p.e;
+}
+
 /* Final estimators from slab averages AT[...][S][x] and ATO[...][S][x]:
  *   C(r)  = 1/(N_sigma |M|)     sum_mu sum_x prod_S [T](S)
- *   CO(r) = 1/(N_sigma |M| N_t) sum_mu sum_x sum_S [TO](S) prod_{S'!=S} [T](S') */
-static void finalize(const ctx_t* c, int S, const cplx* AT, const cplx* ATO, double* out)
+ *   CO(r) = 1/(N_sigma |M| N_t) sum_mu sum_x sum_S [TO](S) prod_{S'!=S} [T](S')
+ * written as mantissas relative to 2^E(r), E(r) the largest binary exponent
+ * of the per-site products prod_S [T](S) (0 if all vanish), with E(r) stored
+ * after the vacuum sums.  Two passes over the sites: the exponents first,
+ * then the plain left-to-right sums of the rescaled terms. */
+static void finalize(const orc_ml_spec* sp, long Nsig, int Nt, int S, const cplx* AT, const cplx* ATO, double* out)
 {
-    const orc_ml_spec* sp = c->sp;
     long base_co = 2L * sp->n_r;
-    double nC = 1.0 / ((double)c->Nsig * sp->n_dirs);
-    double nCO = 1.0 / ((double)c->Nsig * sp->n_dirs * c->Nt);
+    long base_e = 2L * sp->n_r + 4L * sp->n_r * sp->n_probe * sp->n_comp + 12L;
+    double nC = 1.0 / ((double)Nsig * sp->n_dirs);
+    double nCO = 1.0 / ((double)Nsig * sp->n_dirs * Nt);
+    long n_items = (long)sp->n_dirs * Nsig;
+    scplx* P = (scplx*)malloc(sizeof(scplx) * (size_t)(n_items > 0 ? n_items : 1));
+    if (!P) return;
+#define AT_(idir, ir, s, xs) AT[(((long)(idir) * sp->n_r + (ir)) * S + (s)) * Nsig + (xs)]
     for (int ir = 0; ir < sp->n_r; ++ir) {
-        cplx sumC = c_make(0.0, 0.0);
+        long E = 0;
+        int any = 0;
         for (int idir = 0; idir < sp->n_dirs; ++idir) {
-            for (long xs = 0; xs < c->Nsig; ++xs) {
-                cplx p = c_make(1.0, 0.0);
-                for (int s = 0; s < S; ++s) p = c_mul(p, AT[idx_T(c, idir, ir, S, s, xs)]);
-                sumC = c_add(sumC, p);
+            for (long xs = 0; xs < Nsig; ++xs) {
+                scplx p = s_norm(c_make(1.0, 0.0), 0);
+                for (int s = 0; s < S; ++s) p = s_mul(p, AT_(idir, ir, s, xs));
+                P[idir * Nsig + xs] = p;
+                if (!s_zero(p) && (!any || p.e > E)) {
+                    E = p.e;
+                    any = 1;
+                }
             }
         }
+        cplx sumC = c_make(0.0, 0.0);
+        for (long it = 0; it < n_items; ++it) sumC = c_add(sumC, s_rel(P[it], E));
         out[2 * ir + 0] = sumC.re * nC;
         out[2 * ir + 1] = sumC.im * nC;
+        out[base_e + ir] = (double)E;
         for (int ip = 0; ip < sp->n_probe; ++ip) {
             for (int ic = 0; ic < sp->n_comp; ++ic) {
                 for (int kind = 0; kind < 2; ++kind) {
+                    long k = (((long)ir * sp->n_probe + ip) * sp->n_comp + ic) * 2 + kind;
                     cplx sumCO = c_make(0.0, 0.0);
                     for (int idir = 0; idir < sp->n_dirs; ++idir) {
-                        for (long xs = 0; xs < c->Nsig; ++xs) {
+                        for (long xs = 0; xs < Nsig; ++xs) {
                             for (int s = 0; s < S; ++s) {
-                                cplx term = ATO[idx_TO(c, idir, ir, ip, ic, kind, S, s, xs)];
+                                long kk = ((long)idir * sp->n_r + ir) * sp->n_probe + ip;
+                                kk = (kk * sp->n_comp + ic) * 2 + kind;
+                                scplx term = s_norm(ATO[(kk * S + s) * Nsig + xs], 0);
                                 for (int s2 = 0; s2 < S; ++s2) {
                                     if (s2 == s) continue;
-                                    term = c_mul(term, AT[idx_T(c, idir, ir, S, s2, xs)]);
+                                    term = s_mul(term, AT_(idir, ir, s2, xs));
                                 }
-                                sumCO = c_add(sumCO, term);
+                                sumCO = c_add(sumCO, s_rel(term, E));
                             }
                         }
                     }
-                    long k = (((long)ir * sp->n_probe + ip) * sp->n_comp + ic) * 2 + kind;
                     out[base_co + 2 * k + 0] = sumCO.re * nCO;
                     out[base_co + 2 * k + 1] = sumCO.im * nCO;
                 }
             }
         }
     }
+#undef AT_
+    free(P);
+}
+
+int orc_ml_finalize(const orc_ml_spec* sp, long n_sigma, int nt, int n_slabs, const double* at, const double* ato,
+                    double* out)
+{
+    if (n_sigma < 1 || nt < 1 || n_slabs < 1) return 1;
+    finalize(sp, n_sigma, nt, n_slabs, (const cplx*)at, (const cplx*)ato, out);
+    return 0;
 }
 
 static int check_spec(const orc_lattice* lat, const orc_ml_spec* sp)
@@ -354,9 +428,9 @@ int orc_multilevel(orc_lattice* lat, const orc_ml_spec* sp, double* out)
         double inv_o = 1.0 / (double)n_o;
         for (long k = 0; k < nT_o; ++k) Tout[k] = c_scale(Tout[k], inv_o);
         for (long k = 0; k < nTO_o; ++k) TOout[k] = c_scale(TOout[k], inv_o);
-        finalize(&c, S_o, Tout, TOout, out);
+        finalize(sp, c.Nsig, c.Nt, S_o, Tout, TOout, out);
     } else {
-        finalize(&c, S_i, Tin, TOin, out);
+        finalize(sp, c.Nsig, c.Nt, S_i, Tin, TOin, out);
     }
     long base_v = 2L * sp->n_r + 4L * sp->n_r * sp->n_probe * sp->n_comp;
     for (int o = 0; o < 6; ++o) {

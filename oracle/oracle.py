@@ -87,6 +87,9 @@ def lib():
         L.orc_plaquette_means.argtypes = [vp, pd]
         L.orc_ml_result_size.argtypes = [C.POINTER(_Spec)]
         L.orc_ml_result_size.restype = lng
+        L.orc_scaled_product.argtypes = [lng, pd, pd, pd, pd, C.POINTER(lng)]
+        L.orc_ml_finalize.argtypes = [C.POINTER(_Spec), lng, i32, i32, pd, pd, pd]
+        L.orc_ml_finalize.restype = i32
         L.orc_multilevel.argtypes = [vp, C.POINTER(_Spec), pd]
         L.orc_multilevel.restype = i32
         _lib = L
@@ -158,20 +161,56 @@ class MLSpec:
         return s
 
     def result_size(self) -> int:
-        return 2 * len(self.r) + 4 * len(self.r) * len(self.probes) * len(self.comps) + 12
+        return 2 * len(self.r) + 4 * len(self.r) * len(self.probes) * len(self.comps) + 12 + len(self.r)
 
     def unpack(self, out: np.ndarray) -> dict:
-        """Split one configuration's doubles into C[r], CO[r,probe,comp,kind], vacuum."""
+        """Split one configuration's doubles into C[r], CO[r,probe,comp,kind],
+        vacuum and the binary exponents E[r]: "C" and "CO" are the values
+        (mantissa * 2^E[r], zero where that underflows), "C_mant", "CO_mant"
+        the stored mantissas."""
         nr, npb, nc = len(self.r), len(self.probes), len(self.comps)
         C_ = out[: 2 * nr].reshape(nr, 2)
         CO = out[2 * nr: 2 * nr + 4 * nr * npb * nc].reshape(nr, npb, nc, 2, 2)
         base = 2 * nr + 4 * nr * npb * nc
+        ex = out[base + 12: base + 12 + nr].astype(np.int64)
+        cm = C_[:, 0] + 1j * C_[:, 1]
+        com = CO[..., 0] + 1j * CO[..., 1]
+        scale = lambda m, e: np.ldexp(m.real, e) + 1j * np.ldexp(m.imag, e)
         return {
-            "C": C_[:, 0] + 1j * C_[:, 1],
-            "CO": CO[..., 0] + 1j * CO[..., 1],
+            "C": scale(cm, ex),
+            "CO": scale(com, ex[:, None, None, None]),
+            "C_mant": cm,
+            "CO_mant": com,
+            "exp": ex,
             "vac_sq": out[base: base + 6].copy(),
             "vac_lin": out[base + 6: base + 12].copy(),
         }
+
+
+def scaled_product(factors):
+    """Product of complex factors as (mantissa, binary exponent), rescaled after
+    every factor; mantissa max(|re|, |im|) in [1, 2)."""
+    z = np.ascontiguousarray(np.asarray(factors, dtype=np.complex128))
+    re, im = np.ascontiguousarray(z.real), np.ascontiguousarray(z.imag)
+    mr, mi, ex = C.c_double(), C.c_double(), C.c_long()
+    lib().orc_scaled_product(z.size, _dptr(re), _dptr(im), C.byref(mr), C.byref(mi), C.byref(ex))
+    return complex(mr.value, mi.value), int(ex.value)
+
+
+def ml_finalize(spec: "MLSpec", n_sigma: int, nt: int, at: np.ndarray, ato: np.ndarray) -> np.ndarray:
+    """The oracle's final estimators from given slab averages
+    at[dir, r, slab, x] and ato[dir, r, probe, comp, kind, slab, x] (complex)."""
+    s = spec._struct()
+    n = lib().orc_ml_result_size(C.byref(s))
+    out = np.zeros(n, dtype=np.float64)
+    at = np.ascontiguousarray(at, dtype=np.complex128)
+    ato = np.ascontiguousarray(ato if np.size(ato) else np.zeros(1), dtype=np.complex128)
+    n_slabs = at.shape[2]
+    rc = lib().orc_ml_finalize(C.byref(s), n_sigma, nt, n_slabs, at.ctypes.data_as(C.POINTER(C.c_double)),
+                               ato.ctypes.data_as(C.POINTER(C.c_double)), _dptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle finalize: code {rc}")
+    return out
 
 
 class Lattice:

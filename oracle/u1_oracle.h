@@ -118,12 +118,26 @@ void orc_link_mean(const orc_lattice* lat, long site, int mu, double* re, double
 
 /* Number of doubles one configuration's estimates occupy:
  * C[r] (re, im), CO[r][probe][comp][kind] (re, im), vacuum <O_sq>[6],
- * vacuum <O_lin>[6].  kind 0 = O_sq, kind 1 = O_lin. */
+ * vacuum <O_lin>[6], binary exponent E[r].  kind 0 = O_sq, kind 1 = O_lin.
+ * C and CO are mantissas: the estimate of separation r is the stored value
+ * times 2^E[r] (products over slabs can leave the range of FP64). */
 long orc_ml_result_size(const orc_ml_spec* spec);
 
 /* One multilevel configuration (the body of the paper's Algorithm 1 with one
  * or two levels); writes orc_ml_result_size() doubles. Returns 0 on success. */
 int orc_multilevel(orc_lattice* lat, const orc_ml_spec* spec, double* out);
+
+/* Product of n complex factors (re[i], im[i]) as mantissa * 2^ex, rescaled
+ * after every factor so that max(|re|, |im|) of the mantissa lies in [1, 2). */
+void orc_scaled_product(long n, const double* re, const double* im, double* mre, double* mim, long* ex);
+
+/* The final estimators of orc_multilevel from given slab averages:
+ * at[((dir * n_r + r) * n_slabs + s) * n_sigma + x] and
+ * ato[((((dir * n_r + r) * n_probe + p) * n_comp + c) * 2 + kind) * n_slabs + s) * n_sigma + x]
+ * (complex, interleaved re, im); fills C, CO and E[r] of out (the vacuum
+ * slots are left as they are).  Returns 0 on success. */
+int orc_ml_finalize(const orc_ml_spec* spec, long n_sigma, int nt, int n_slabs, const double* at, const double* ato,
+                    double* out);
 
 #ifdef __cplusplus
 }
