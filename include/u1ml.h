@@ -180,7 +180,13 @@ typedef struct {
                                    for comparison (Sec. II.D)                 */
     long n_doubles_per_config; /* doubles per ensemble per configuration:
                                   C[r] (re, im), CO[r][probe][comp][kind]
-                                  (re, im), vacuum <O_sq>[6], <O_lin>[6]      */
+                                  (re, im), vacuum <O_sq>[6], <O_lin>[6],
+                                  binary exponent E[r]; C and CO of
+                                  separation r are mantissas, the estimate is
+                                  the stored value times 2^E[r] (the products
+                                  over slabs, Sec. II.C.2-3, can leave the
+                                  range of FP64; E[r] is the largest exponent
+                                  of the per-site correlator products)      */
     long updates_per_config;  /* non-frozen link updates of one multilevel
                                  configuration, all ensembles               */
     long updates_per_sweep;   /* link updates of one full-lattice sweep      */

@@ -33,17 +33,65 @@ def jackknife(samples: np.ndarray, estimator: Callable[[np.ndarray], np.ndarray]
     return full, err
 
 
-def correlator(records: Sequence[dict]):
-    """<P^dagger P>(r) with jackknife errors."""
+def block_means(samples: np.ndarray, n_blocks: Optional[int]):
+    """Means of n_blocks consecutive equal blocks of the samples (axis 0; a
+    tail shorter than a block is dropped), or the samples themselves if
+    n_blocks is None.  Estimators that are functions of means, jackknifed over
+    block means, absorb the autocorrelation of consecutive configurations."""
+    x = np.asarray(samples)
+    if n_blocks is None:
+        return x
+    b = x.shape[0] // n_blocks
+    if b < 1:
+        raise ValueError("fewer samples than blocks")
+    return x[: b * n_blocks].reshape((n_blocks, b) + x.shape[1:]).mean(axis=1)
+
+
+def common_scale(records: Sequence[dict]):
+    """C [n, R] and CO [n, R, P, Nc, 2] of every record as mantissas relative
+    to one binary exponent per separation (the largest of the records'), and
+    that exponent [R]: value = mantissa * 2^E.  Records without exponents are
+    taken as they are (E = 0)."""
+    if not records or "exp" not in records[0]:
+        C = np.array([rec["C"] for rec in records])
+        CO = np.array([rec["CO"] for rec in records]) if records and "CO" in records[0] else None
+        return C, CO, np.zeros(C.shape[1] if C.ndim > 1 else 0, dtype=np.int64)
+    ex = np.array([rec["exp"] for rec in records])  # [n, R]
+    E = ex.max(axis=0)
+    sh = ex - E[None, :]
+
+    def rescale(m, k):
+        return np.ldexp(m.real, k) + 1j * np.ldexp(m.imag, k)
+
+    C = np.array([rescale(rec["C_mant"], sh[i]) for i, rec in enumerate(records)])
+    CO = np.array([rescale(rec["CO_mant"], sh[i][:, None, None, None]) for i, rec in enumerate(records)])
+    return C, CO, E
+
+
+def correlator(records: Sequence[dict], n_blocks: Optional[int] = None):
+    """<P^dagger P>(r) with jackknife errors (over blocks of consecutive
+    records if n_blocks is given)."""
     C = np.array([rec["C"].real for rec in records])
-    return jackknife(C, lambda x: x.mean(axis=0))
+    return jackknife(block_means(C, n_blocks), lambda x: x.mean(axis=0))
 
 
-def field_profile(records: Sequence[dict], comps: Sequence[int], dirs: Sequence[int] = (0,)):
+def log_correlator(records: Sequence[dict], n_blocks: Optional[int] = None):
+    """ln <P^dagger P>(r) with jackknife errors, formed from the mantissas and
+    exponents of the records, so it stays finite where <P^dagger P> itself is
+    below the range of FP64."""
+    C, _, E = common_scale(records)
+    return jackknife(block_means(C.real, n_blocks), lambda x: np.log(x.mean(axis=0)) + E * np.log(2.0))
+
+
+def field_profile(records: Sequence[dict], comps: Sequence[int], dirs: Sequence[int] = (0,),
+                  n_blocks: Optional[int] = None):
     """Connected insertions <O>_{P^dagger P}[r, probe, comp, kind] (kind 0:
-    2 beta (1 - Re P), kind 1: sqrt(beta) Im P) with jackknife errors."""
-    C = np.array([rec["C"].real for rec in records])  # [n, R]
-    CO = np.array([rec["CO"] for rec in records])  # [n, R, P, Nc, 2]
+    2 beta (1 - Re P), kind 1: sqrt(beta) Im P) with jackknife errors (over
+    blocks of consecutive records if n_blocks is given).  The ratios are
+    formed from mantissas on a common exponent per separation, so they hold
+    where the correlator is below the range of FP64."""
+    C, CO, _ = common_scale(records)
+    C = C.real  # [n, R]
     vac = np.array([rec["vac_sq"] for rec in records])  # [n, 6]
     n = C.shape[0]
     packed = np.concatenate([C.reshape(n, -1), CO.real.reshape(n, -1), CO.imag.reshape(n, -1), vac], axis=1)
@@ -64,7 +112,7 @@ def field_profile(records: Sequence[dict], comps: Sequence[int], dirs: Sequence[
         out[..., 1, 1] = re[..., 1] / c[:, None, None]  # and real part of the O_lin ratio
         return out
 
-    return jackknife(packed, est)
+    return jackknife(block_means(packed, n_blocks), est)
 
 
 def flux_tube_width2(profile: np.ndarray, p1: Sequence[int], p2: Sequence[int]):
@@ -81,9 +129,10 @@ def flux_tube_width2(profile: np.ndarray, p1: Sequence[int], p2: Sequence[int]):
 # ---------------------------------------------------------------------------
 def potential(records: Sequence[dict], nt: int):
     """V(r) = -ln <P^dagger P>(r) / N_t with jackknife errors (the Polyakov
-    correlator at temperature 1/N_t decays as exp(-N_t V))."""
-    C = np.array([rec["C"].real for rec in records])
-    return jackknife(C, lambda x: -np.log(x.mean(axis=0)) / nt)
+    correlator at temperature 1/N_t decays as exp(-N_t V)); from the
+    mantissas and exponents, so it holds where the correlator underflows."""
+    C, _, E = common_scale(records)
+    return jackknife(C.real, lambda x: -(np.log(x.mean(axis=0)) + E * np.log(2.0)) / nt)
 
 
 def fit_potential(r, V, err=None, gamma: Optional[float] = None):
@@ -221,6 +270,65 @@ def plaquette_susceptibility(series, n_plaquettes: int, n_blocks: int = 20):
         return n_plaquettes * (np.mean(v * v) - np.mean(v) ** 2)
 
     return jackknife(blocks, est)
+
+
+def gamma_method(series, grad: Optional[Callable[[np.ndarray], np.ndarray]] = None, S: float = 1.5):
+    """Error of a function f of the means of a Monte-Carlo time series, with
+    its integrated autocorrelation time (Wolff, Comput. Phys. Commun. 156
+    (2004) 143, "Monte Carlo errors with less errors").
+
+    series: [n] or [n, k] (k primary observables per configuration, in
+    Monte-Carlo order); grad(means) -> df/da_alpha (default: the mean of a
+    single observable).  The fluctuations are projected on the gradient,
+        delta_i = sum_alpha f_alpha (a_{alpha,i} - abar_alpha),
+    their autocorrelation function Gamma(t) is summed up to the window W
+    chosen automatically: W is the first t where
+        exp(-t / tau) - tau / sqrt(t n) < 0,  tau = S / ln((2 tau_int(t) + 1) / (2 tau_int(t) - 1)),
+    and  tau_int = 1/2 + sum_{t=1}^{W} Gamma(t) / Gamma(0),  sigma^2 = 2 tau_int Gamma(0) / n.
+    Returns (sigma, tau_int, d tau_int, W)."""
+    a = np.asarray(series, float)
+    if a.ndim == 1:
+        a = a[:, None]
+    n = a.shape[0]
+    mean = a.mean(axis=0)
+    g = np.ones(a.shape[1]) if grad is None else np.asarray(grad(mean), float)
+    d = (a - mean) @ g
+    # Gamma(t) for every t at once from the power spectrum of the zero-padded series
+    m = 1 << int(np.ceil(np.log2(2 * n)))
+    f = np.fft.rfft(d, m)
+    gam = np.fft.irfft(f * np.conj(f), m)[:n] / (n - np.arange(n))
+    if gam[0] <= 0:
+        return 0.0, 0.5, 0.0, 0
+    tint = 0.5
+    W = 0
+    for t in range(1, n // 2):
+        tint += gam[t] / gam[0]
+        if tint <= 0.5:
+            W = t
+            break
+        tau = S / np.log((2 * tint + 1) / (2 * tint - 1))
+        if np.exp(-t / tau) - tau / np.sqrt(t * n) < 0:
+            W = t
+            break
+    else:
+        W = n // 2 - 1
+    tint = max(tint, 0.5)
+    sigma = np.sqrt(2 * tint * gam[0] / n)
+    dtint = tint * np.sqrt(4 * (W + 0.5 - tint) / n)
+    return float(sigma), float(tint), float(dtint), int(W)
+
+
+def susceptibility_gamma(series, n_plaquettes: int):
+    """chi = N_P (<P^2> - <P>^2) of a series of lattice-averaged plaquettes,
+    with its error and integrated autocorrelation time from gamma_method
+    (gradient N_P (-2 <P>, 1) on the primary observables (P, P^2)).
+    Returns (chi, sigma, tau_int, d tau_int, W)."""
+    x = np.asarray(series, float)
+    a = np.stack([x, x * x], axis=1)
+    m = a.mean(axis=0)
+    chi = n_plaquettes * (m[1] - m[0] ** 2)
+    sigma, tint, dtint, W = gamma_method(a, lambda mm: n_plaquettes * np.array([-2.0 * mm[0], 1.0]))
+    return float(chi), sigma, tint, dtint, W
 
 
 def peak_position(betas, chi, n_points: int = 5):

@@ -21,6 +21,7 @@
 // as (mantissa, binary exponent) pairs so they cannot underflow, and all sums
 // over sites are double-double in a fixed order, so results are reproducible.
 #include "device_common.hpp"
+#include "scaled.hpp"
 #include "u1ml_internal.hpp"
 
 namespace u1ml {
@@ -56,38 +57,6 @@ __device__ inline dd dd_add(dd a, dd b)
     const double hi = s + err;
     return dd{hi, err - (hi - s)};
 }
-
-// scaled complex: value = (re + i im) * 2^ex, max(|re|,|im|) >= 2^-600 or 0
-struct sc {
-    double re, im;
-    int ex;
-};
-
-__device__ inline sc sc_norm(double re, double im, int ex)
-{
-    const double m = fmax(fabs(re), fabs(im));
-    if (m == 0.0 || !isfinite(m)) return sc{re, im, 0};
-    const int k = ilogb(m);
-    return sc{ldexp(re, -k), ldexp(im, -k), ex + k};
-}
-
-// The mantissa is renormalised only once its magnitude falls below 2^-600:
-// scaling by a power of two commutes with rounding while values stay normal,
-// so the result equals renormalising after every product, bit for bit.
-__device__ inline sc sc_lazy(double re, double im, int ex)
-{
-    if (fmax(fabs(re), fabs(im)) < 0x1p-600) return sc_norm(re, im, ex);
-    return sc{re, im, ex};
-}
-
-__device__ inline sc sc_mul(sc a, double2 b) { return sc_lazy(a.re * b.x - a.im * b.y, a.re * b.y + a.im * b.x, a.ex); }
-
-__device__ inline sc sc_mul(sc a, sc b)
-{
-    return sc_lazy(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re, a.ex + b.ex);
-}
-
-__device__ inline double2 sc_val(sc a) { return make_double2(ldexp(a.re, a.ex), ldexp(a.im, a.ex)); }
 
 // absolute orientation of frame component c for charge axis dir:
 // E_i -> i (plaquette P_{i t}); B_x, B_y, B_z -> 3, 4, 5 (P_yz, P_zx, P_xy)
@@ -598,35 +567,132 @@ hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, 
 }
 
 // ---------------------------------------------------------------------------
-// Slab products and sums over sites.  Work-group (e, r, probe group, chunk):
-// every thread walks the chunk's (axis, x) items in a fixed stride, forms
-// P(x) = prod_S A(S) and W_S(x) = prod_{S' != S} A(S') as scaled complex
-// numbers, and adds P (correlator, probe 0 only) and sum_S B(S) W_S
-// (insertions) to double-double accumulators; a fixed-order tree reduces the
-// work-group into part[wg][26][hi, lo], and k_product_final adds the chunks
-// of each (e, r, probe) in chunk order.
+// Slab products and sums over sites (Sec. II.C.2-3).  The products over many
+// slabs of averages of modulus below one can leave the range of FP64, so they
+// run as scaled complex numbers, and both sums are taken relative to 2^E(r),
+// E(r) the largest binary exponent of the per-site correlator products of
+// separation r over the charge axes and sites (0 if they all vanish).  The
+// record holds the mantissas and E(r); values in range are unchanged bit for
+// bit by the scaling.
+//
+// Three launches, each over the work-group table of (e, r, probe group, site
+// chunk):
+//   k_prod_exp:      the largest exponent of each chunk (probe group 0 only),
+//                    kept in the first slot of the chunk's partials;
+//   k_prod_exp_final: E(r) of each (e, r) from its chunks, written to the
+//                    configuration's record (where the products and the
+//                    spectral weights read it);
+//   k_product:       every thread walks the chunk's (axis, x) items in a fixed
+//                    stride, forms P(x) = prod_S A(S) and W_S(x) =
+//                    prod_{S' != S} A(S'), and adds P 2^-E (correlator, probe 0
+//                    only) and sum_S B(S) W_S 2^-E (insertions) to
+//                    double-double accumulators; a fixed-order tree reduces the
+//                    work-group into part[wg][26][hi, lo];
+//   k_product_final: the chunks of each (e, r, probe) in chunk order.
 // src_t  = A * scale_t, src_to = B * scale_t (scale_t = 1 or 1/n_outer).
 // ---------------------------------------------------------------------------
+struct ProdItem {
+    int e, ir, p, ch;
+};
+
+__device__ inline bool prod_item(const int* __restrict__ bstart, int n_ens, const EnsDesc* __restrict__ ens,
+                                 int n_r, int n_pgroups, ProdItem* o)
+{
+    o->e = find_ens_m(bstart, n_ens, blockIdx.x);
+    const EnsDesc& E = ens[o->e];
+    const int local = blockIdx.x - bstart[o->e];
+    o->ch = local % E.prod_nch;
+    o->p = (local / E.prod_nch) % n_pgroups;
+    o->ir = local / (E.prod_nch * n_pgroups);
+    return o->ir < n_r;  // the work-group table holds n_r * n_pgroups * prod_nch per ensemble (uniform)
+}
+
+// the current configuration's record of ensemble E
+template <typename T>
+__device__ inline T* record_of(const EnsDesc& E, const ObsDesc& O, T* results, const int* ring)
+{
+    return results + ((size_t)(*ring) * O.n_ens_total + E.res_index) * O.n_doubles_per_config;
+}
+
+__device__ inline sc slab_product(const double2* __restrict__ row, int S, int nsig, int skip, double scale_t)
+{
+    sc P{1.0, 0.0, 0};
+    for (int s = 0; s < S; ++s) {
+        if (s == skip) continue;
+        double2 a = row[(size_t)s * nsig];
+        a.x *= scale_t;
+        a.y *= scale_t;
+        P = sc_mul(P, a);
+    }
+    return P;
+}
+
+__global__ void __launch_bounds__(256) k_prod_exp(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
+                                                  int n_ens, const ObsDesc* __restrict__ obs, int n_pgroups,
+                                                  const double2* __restrict__ src_t, int use_outer, double scale_t,
+                                                  double* __restrict__ part)
+{
+    const ObsDesc& O = *obs;
+    ProdItem I;
+    if (!prod_item(bstart, n_ens, ens, O.n_r, n_pgroups, &I) || I.p != 0) return;
+    const EnsDesc& E = ens[I.e];
+    const int nsig = E.nsig;
+    const int S = use_outer ? E.s_out : E.s_in;
+    const long long t_off = use_outer ? E.ot_off : E.at_off;
+    const int n_items = O.n_dirs * nsig;
+    const int it_end = min(n_items, (I.ch + 1) * kProdChunk);
+    int emax = kNoExp;
+    for (int it = I.ch * kProdChunk + (int)threadIdx.x; it < it_end; it += blockDim.x) {
+        const int id = it / nsig, xs = it - id * nsig;
+        const double2* row = src_t + t_off + ((size_t)id * O.n_r + I.ir) * S * nsig + xs;
+        emax = max(emax, sc_exp(slab_product(row, S, nsig, -1, scale_t)));
+    }
+    __shared__ int sh[256];
+    sh[threadIdx.x] = emax;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * kProdQ * 2] = (double)sh[0];
+}
+
+// one work-item per (e, r)
+__global__ void __launch_bounds__(64) k_prod_exp_final(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
+                                                       int n_ens, const ObsDesc* __restrict__ obs, int n_pgroups,
+                                                       const double* __restrict__ part, double* __restrict__ results,
+                                                       const int* __restrict__ ring)
+{
+    const ObsDesc& O = *obs;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_ens * O.n_r) return;
+    const int e = i / O.n_r, ir = i % O.n_r;
+    const EnsDesc& E = ens[e];
+    const int b0 = bstart[e] + ir * n_pgroups * E.prod_nch;  // probe group 0
+    int emax = kNoExp;
+    for (int c = 0; c < E.prod_nch; ++c) emax = max(emax, (int)part[(size_t)(b0 + c) * kProdQ * 2]);
+    record_of(E, O, results, ring)[O.n_doubles_per_config - O.n_r + ir] = emax == kNoExp ? 0.0 : (double)emax;
+}
+
 __global__ void __launch_bounds__(256) k_product(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
                                                  int n_ens, const ObsDesc* __restrict__ obs, int n_pgroups,
                                                  const double2* __restrict__ src_t, const double2* __restrict__ src_to,
-                                                 int use_outer, double scale_t, double* __restrict__ part)
+                                                 int use_outer, double scale_t, double* __restrict__ part,
+                                                 const double* __restrict__ results, const int* __restrict__ ring)
 {
-    const int e = find_ens_m(bstart, n_ens, blockIdx.x);
-    const EnsDesc& E = ens[e];
     const ObsDesc& O = *obs;
     const int n_r = O.n_r;
-    const int local = blockIdx.x - bstart[e];
-    const int ch = local % E.prod_nch;
-    const int p = (local / E.prod_nch) % n_pgroups;
-    const int ir = local / (E.prod_nch * n_pgroups);
-    if (ir >= n_r) return;  // the work-group table holds n_r * n_pgroups * prod_nch per ensemble (uniform)
+    ProdItem I;
+    if (!prod_item(bstart, n_ens, ens, n_r, n_pgroups, &I)) return;
+    const EnsDesc& E = ens[I.e];
+    const int ch = I.ch, p = I.p, ir = I.ir;
     const int nsig = E.nsig;
     const int S = use_outer ? E.s_out : E.s_in;
     const long long t_off = use_outer ? E.ot_off : E.at_off;
     const long long to_off = use_outer ? E.oto_off : E.ato_off;
     const int nc = O.n_comp;
     const bool has_probe = O.n_probe > 0 && src_to != nullptr;  // null: insertions come from the spectral form
+    const int Er = (int)record_of(E, O, results, ring)[O.n_doubles_per_config - n_r + ir];
     dd cre{0, 0}, cim{0, 0};
     dd ore[12], oim[12];
 #pragma unroll
@@ -638,37 +704,23 @@ __global__ void __launch_bounds__(256) k_product(const EnsDesc* __restrict__ ens
     const int it_end = min(n_items, (ch + 1) * kProdChunk);
     for (int it = ch * kProdChunk + (int)threadIdx.x; it < it_end; it += blockDim.x) {
         const int id = it / nsig, xs = it - id * nsig;
-        const size_t trow = ((size_t)id * n_r + ir) * S;
-        sc P{1.0, 0.0, 0};
-        for (int s = 0; s < S; ++s) {
-            double2 a = src_t[t_off + (trow + s) * nsig + xs];
-            a.x *= scale_t;
-            a.y *= scale_t;
-            P = sc_mul(P, a);
-        }
+        const double2* row = src_t + t_off + ((size_t)id * n_r + ir) * S * nsig + xs;
         if (p == 0) {
-            const double2 v = sc_val(P);
+            const double2 v = sc_rel(slab_product(row, S, nsig, -1, scale_t), Er);
             cre = dd_add(cre, v.x);
             cim = dd_add(cim, v.y);
         }
         if (!has_probe) continue;
         for (int s = 0; s < S; ++s) {
-            sc W{1.0, 0.0, 0};
-            for (int s2 = 0; s2 < S; ++s2) {
-                if (s2 == s) continue;
-                double2 a = src_t[t_off + (trow + s2) * nsig + xs];
-                a.x *= scale_t;
-                a.y *= scale_t;
-                W = sc_mul(W, a);
-            }
+            const sc W = slab_product(row, S, nsig, s, scale_t);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 if (k < 2 * nc) {
-                    const size_t row = ((((size_t)id * n_r + ir) * O.n_probe + p) * nc) * 2 + k;
-                    double2 b = src_to[to_off + (row * S + s) * nsig + xs];
+                    const size_t krow = ((((size_t)id * n_r + ir) * O.n_probe + p) * nc) * 2 + k;
+                    double2 b = src_to[to_off + (krow * S + s) * nsig + xs];
                     b.x *= scale_t;
                     b.y *= scale_t;
-                    const double2 v = sc_val(sc_mul(W, b));
+                    const double2 v = sc_rel(sc_mul(W, b), Er);
                     ore[k] = dd_add(ore[k], v.x);
                     oim[k] = dd_add(oim[k], v.y);
                 }
@@ -748,7 +800,7 @@ __global__ void __launch_bounds__(64) k_product_final(const EnsDesc* __restrict_
         for (int u = 0; u < 8; ++u) a = dd_add(a, dd{v[u].x, v[u].y});
     }
     for (; c < E.prod_nch; ++c) a = dd_add(a, dd{src[c * cs], src[c * cs + 1]});
-    double* out = results + ((size_t)(*ring) * O.n_ens_total + E.res_index) * O.n_doubles_per_config;
+    double* out = record_of(E, O, results, ring);
     const double nC = 1.0 / ((double)E.nsig * O.n_dirs);
     if (q < 2) {
         out[2 * ir + q] = (a.hi + a.lo) * nC;
@@ -759,13 +811,28 @@ __global__ void __launch_bounds__(64) k_product_final(const EnsDesc* __restrict_
     }
 }
 
+hipError_t launch_prod_exp(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+                           const ObsDesc* d_obs, int n_r, int n_pgroups, const double2* src_t, int use_outer,
+                           double scale, double* part, double* results, const int* d_ring, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_prod_exp, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, n_pgroups,
+                       src_t, use_outer, scale, part);
+    const int ne = n_ens * n_r;
+    hipLaunchKernelGGL(k_prod_exp_final, dim3((ne + 63) / 64), dim3(64), 0, st, d_ens, d_bstart, n_ens, d_obs,
+                       n_pgroups, part, results, d_ring);
+    return hipGetLastError();
+}
+
 hipError_t launch_product(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
                           const ObsDesc* d_obs, int n_r, int n_pgroups, const double2* src_t, const double2* src_to,
                           int use_outer, double scale, double* part, double* results, const int* d_ring,
                           hipStream_t st)
 {
+    hipError_t e = launch_prod_exp(d_ens, d_bstart, n_ens, total_blocks, d_obs, n_r, n_pgroups, src_t, use_outer,
+                                   scale, part, results, d_ring, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_product, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, n_pgroups,
-                       src_t, src_to, use_outer, scale, part);
+                       src_t, src_to, use_outer, scale, part, results, d_ring);
     const int nq = n_ens * n_r * n_pgroups * kProdQ;
     hipLaunchKernelGGL(k_product_final, dim3((nq + 63) / 64), dim3(64), 0, st, d_ens, d_bstart, n_ens, d_obs, n_pgroups,
                        part, results, d_ring, src_to != nullptr ? 1 : 0);

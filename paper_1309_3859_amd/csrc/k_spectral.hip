@@ -22,6 +22,7 @@
 // are read off once per configuration.  Memory is independent of the number
 // of probes.
 #include "device_common.hpp"
+#include "scaled.hpp"
 #include "u1ml_internal.hpp"
 
 namespace u1ml {
@@ -73,16 +74,27 @@ __device__ inline dds dds_add(dds a, double b)
 
 // ---------------------------------------------------------------------------
 // Weights.  One work-item per (ensemble, axis, r, x); it writes every slab.
-//   k_wfac: W[axis, r][S][x] = prod_{S' != S} scale * out_t[axis, r][S'][x]
+//   k_wfac: W[axis, r][S][x] = 2^-E(r) prod_{S' != S} scale * out_t[axis, r][S'][x]
 //   k_gfac: G[axis, r][s][x] = W_S(x) prod_{s' in S, s' != s} avg_t[axis, r][s'][x]
-//           (q thin slabs per thick slab, q = 0 for all slabs; W = 1 when wf is null),
-//           stored in the plane-major order of the axis (plane_index)
-// Products run over ascending slab index.
+//           (q thin slabs per thick slab, q = 0 for all slabs; W = 2^-E(r) when
+//           wf is null), stored in the plane-major order of the axis (plane_index)
+// E(r) is the exponent of the configuration's correlator products, read from
+// its record, so that the spectral sums come out relative to the same 2^E(r)
+// as the correlator.  The products over slabs run as scaled complex numbers,
+// over ascending slab index.
 // ---------------------------------------------------------------------------
+__device__ inline int record_exp(const EnsDesc& E, const ObsDesc& O, const double* __restrict__ results,
+                                 const int* __restrict__ ring, int ir)
+{
+    const double* rec = results + ((size_t)(*ring) * O.n_ens_total + E.res_index) * O.n_doubles_per_config;
+    return (int)rec[O.n_doubles_per_config - O.n_r + ir];
+}
+
 __global__ void __launch_bounds__(256) k_wfac(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
                                               int n_ens, const ObsDesc* __restrict__ obs,
                                               const double2* __restrict__ out_t, double scale,
-                                              double2* __restrict__ wf)
+                                              double2* __restrict__ wf, const double* __restrict__ results,
+                                              const int* __restrict__ ring)
 {
     const int e = find_ens_s(bstart, n_ens, blockIdx.x);
     const EnsDesc& E = ens[e];
@@ -91,23 +103,25 @@ __global__ void __launch_bounds__(256) k_wfac(const EnsDesc* __restrict__ ens, c
     if (item >= (long long)obs->n_dirs * obs->n_r * nsig) return;
     const int xs = (int)(item % nsig);
     const long long idr = item / nsig;
+    const int Er = record_exp(E, *obs, results, ring, (int)(idr % obs->n_r));
     for (int S = 0; S < So; ++S) {
-        double2 w = make_double2(1.0, 0.0);
+        sc w{1.0, 0.0, 0};
         for (int S2 = 0; S2 < So; ++S2) {
             if (S2 == S) continue;
             double2 a = out_t[E.ot_off + ((size_t)idr * So + S2) * nsig + xs];
             a.x *= scale;
             a.y *= scale;
-            w = cmul(w, a);
+            w = sc_mul(w, a);
         }
-        wf[E.wf_off + ((size_t)idr * So + S) * nsig + xs] = w;
+        wf[E.wf_off + ((size_t)idr * So + S) * nsig + xs] = sc_rel(w, Er);
     }
 }
 
 __global__ void __launch_bounds__(256) k_gfac(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
                                               int n_ens, const ObsDesc* __restrict__ obs,
                                               const double2* __restrict__ avg_t, const double2* __restrict__ wf,
-                                              int q, double2* __restrict__ gf)
+                                              int q, double2* __restrict__ gf, const double* __restrict__ results,
+                                              const int* __restrict__ ring)
 {
     const int e = find_ens_s(bstart, n_ens, blockIdx.x);
     const EnsDesc& E = ens[e];
@@ -118,14 +132,19 @@ __global__ void __launch_bounds__(256) k_gfac(const EnsDesc* __restrict__ ens, c
     const long long idr = item / nsig;
     const int qq = q > 0 ? q : Si;  // q = 0: one thick slab of every slab (one level)
     const int pidx = plane_index(xs, obs->dirs[idr / obs->n_r], E.nx, E.ny, E.nz);
+    const int Er = wf ? 0 : record_exp(E, *obs, results, ring, (int)(idr % obs->n_r));
     for (int s = 0; s < Si; ++s) {
         const int S = s / qq;
-        double2 g = wf ? wf[E.wf_off + ((size_t)idr * So + S) * nsig + xs] : make_double2(1.0, 0.0);
+        sc g{1.0, 0.0, 0};
+        if (wf) {
+            const double2 w = wf[E.wf_off + ((size_t)idr * So + S) * nsig + xs];
+            g = sc{w.x, w.y, 0};
+        }
         for (int s2 = S * qq; s2 < S * qq + qq; ++s2) {
             if (s2 == s) continue;
-            g = cmul(g, avg_t[E.at_off + ((size_t)idr * Si + s2) * nsig + xs]);
+            g = sc_mul(g, avg_t[E.at_off + ((size_t)idr * Si + s2) * nsig + xs]);
         }
-        gf[E.gf_off + ((size_t)idr * Si + s) * nsig + pidx] = g;
+        gf[E.gf_off + ((size_t)idr * Si + s) * nsig + pidx] = sc_rel(g, Er);
     }
 }
 
@@ -690,16 +709,20 @@ __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_wfac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
-                       const double2* out_t, double scale, double2* wf, hipStream_t st)
+                       const double2* out_t, double scale, double2* wf, const double* results, const int* d_ring,
+                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_wfac, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, out_t, scale, wf);
+    hipLaunchKernelGGL(k_wfac, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, out_t, scale, wf,
+                       results, d_ring);
     return hipGetLastError();
 }
 
 hipError_t launch_gfac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
-                       const double2* avg_t, const double2* wf, int q, double2* gf, hipStream_t st)
+                       const double2* avg_t, const double2* wf, int q, double2* gf, const double* results,
+                       const int* d_ring, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gfac, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, avg_t, wf, q, gf);
+    hipLaunchKernelGGL(k_gfac, dim3(total_blocks), dim3(256), 0, st, d_ens, d_bstart, n_ens, d_obs, avg_t, wf, q, gf,
+                       results, d_ring);
     return hipGetLastError();
 }
 

@@ -184,7 +184,7 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
             }
         }
     }
-    P->nd_cfg = 2ll * P->r.size() + 4ll * P->r.size() * P->probes.size() * P->comps.size() + 12;
+    P->nd_cfg = 2ll * P->r.size() + 4ll * P->r.size() * P->probes.size() * P->comps.size() + 12 + P->r.size();
     if (p->form < U1ML_FORM_AUTO || p->form > U1ML_FORM_SPECTRAL) return fail(err, "form must be 0, 1 or 2");
     P->form_req = p->form;
     if (p->form == U1ML_FORM_SPECTRAL)
@@ -217,10 +217,16 @@ constexpr long long kMaxGraphLaunches = 8192;
 long long body_launches(const Problem& P)
 {
     const long long sweep = (1ll + P.n_or) * 8;
-    long long level = (long long)P.n_o * ((long long)P.k_o * sweep + (long long)P.n_i * (P.k_i * sweep + 1) + 4);
-    if (P.spectral) level += (long long)P.n_o * (1 + 3ll * P.n_i);
+    // per measurement: the measurement, and in the spectral form staging,
+    // plane transforms and spectral sums (at most 6); per inner level: the two
+    // contractions, the combine, the exponent pass (2) and the weights
+    const long long meas = 1 + (P.spectral ? 6 : 0);
+    const long long level = (long long)P.n_o * ((long long)P.k_o * sweep + (long long)P.n_i * (P.k_i * sweep + meas) + 6);
     const long long passes = (P.spectral && P.two) ? 2 : 1;
-    return passes * level + 16;
+    // per configuration: products (4), vacuum, spectral final (2), outer
+    // weights, ring and counters; per ensemble: up to three fills and two
+    // link copies
+    return passes * level + 10 + 5ll * P.n_ens;
 }
 
 // probe groups of the slab-product launch: every probe in the history form,
@@ -791,9 +797,13 @@ hipError_t enq_levels(u1ml_ctx* c, const Lane& L, hipStream_t st, bool store_o, 
             e = launch_combine(L.d_ens, L.tab_dev(kTabComb), n, L.tab_total(kTabComb), c->d_obs, c->at,
                                ins_hist ? c->ato : nullptr, c->ot, ins_hist ? c->oto : nullptr, P.tau_o / P.tau_i, st);
         if (spec_acc) {
+            // one level: the weights are relative to 2^E(r) of this level's correlator products
+            if (e == hipSuccess && !P.two)
+                e = launch_prod_exp(L.d_ens, L.tab_dev(kTabProd), n, L.tab_total(kTabProd), c->d_obs,
+                                    (int)P.r.size(), prod_groups(P), c->at, 0, 1.0, L.prodpart, c->res, L.d_ring, st);
             if (e == hipSuccess)
                 e = launch_gfac(L.d_ens, L.tab_dev(kTabSite), n, L.tab_total(kTabSite), c->d_obs, c->at,
-                                P.two ? c->wf : nullptr, P.two ? P.tau_o / P.tau_i : 0, c->gf, st);
+                                P.two ? c->wf : nullptr, P.two ? P.tau_o / P.tau_i : 0, c->gf, c->res, L.d_ring, st);
             const size_t lds = (2 * (size_t)c->spec_n12max + 2 * (size_t)c->spec_npm) * sizeof(double2);
             for (int m = 0; e == hipSuccess && m < P.n_i; ++m) {
                 e = launch_plane_stage(L.d_ens, L.tab_dev(kTabStage), n, L.tab_total(kTabStage), c->d_obs, c->hc,
@@ -871,7 +881,7 @@ hipError_t enq_multilevel(u1ml_ctx* c, const Lane& L, hipStream_t st)
         if (e == hipSuccess) e = launch_vac_final(L.d_ens, n, c->d_obs, c->vpart, P.n_o * P.n_i, c->res, L.d_ring, st);
         if (e == hipSuccess)
             e = launch_wfac(L.d_ens, L.tab_dev(kTabSite), n, L.tab_total(kTabSite), c->d_obs, c->ot, 1.0 / P.n_o,
-                            c->wf, st);
+                            c->wf, c->res, L.d_ring, st);
         if (e == hipSuccess) e = copy_lane_links(c, L, c->saved, c->links, st);
         if (e == hipSuccess) e = zero_lane(L, c->facc, c->S.facc, 16, c->Lo.sz_facc, st);
         int hb2 = 0;

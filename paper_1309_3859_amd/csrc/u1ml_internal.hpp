@@ -102,7 +102,13 @@ hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens,
 hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                           const double2* avg_t, const double2* avg_to, double2* out_t, double2* out_to, int q,
                           hipStream_t st);
+// Slab products relative to 2^E(r), E(r) the largest binary exponent of the per-site correlator
+// products; launch_prod_exp finds E(r) and writes it to the current record (where launch_product,
+// launch_wfac and launch_gfac read it); launch_product runs it first.
 // d_bstart: per ensemble n_r * n_pgroups * E.prod_nch work-groups; part: 52 doubles per work-group
+hipError_t launch_prod_exp(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+                           const ObsDesc* d_obs, int n_r, int n_pgroups, const double2* src_t, int use_outer,
+                           double scale, double* part, double* results, const int* d_ring, hipStream_t st);
 hipError_t launch_product(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
                           const ObsDesc* d_obs, int n_r, int n_pgroups, const double2* src_t, const double2* src_to,
                           int use_outer, double scale, double* part, double* results, const int* d_ring,
@@ -112,10 +118,13 @@ hipError_t launch_vac_final(const EnsDesc* d_ens, int n_ens, const ObsDesc* d_ob
 hipError_t launch_ring_advance(int* d_ring, hipStream_t st);
 
 // --- spectral form (k_spectral.hip) ---
+// weights relative to 2^E(r) (read from the current record; gfac only when wf is null)
 hipError_t launch_wfac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
-                       const double2* out_t, double scale, double2* wf, hipStream_t st);
+                       const double2* out_t, double scale, double2* wf, const double* results, const int* d_ring,
+                       hipStream_t st);
 hipError_t launch_gfac(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
-                       const double2* avg_t, const double2* wf, int q, double2* gf, hipStream_t st);
+                       const double2* avg_t, const double2* wf, int q, double2* gf, const double* results,
+                       const int* d_ring, hipStream_t st);
 // measurement m_in's slab phases and O rows copied to the plane-major order of each charge axis;
 // d_bstart: per ensemble n_dirs * s_in * ceil(Nx/32) * ceil(max extent/32) * max extent work-groups
 hipError_t launch_plane_stage(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,

@@ -194,16 +194,25 @@ class Spec:
 
     def n_doubles_per_config(self) -> int:
         R, Np, Nc = len(self.r), len(self.probes), len(self.comps)
-        return 2 * R + 4 * R * Np * Nc + 12
+        return 2 * R + 4 * R * Np * Nc + 12 + R
 
     def unpack(self, rec: np.ndarray) -> dict:
-        """One ensemble's record: C[r], CO[r, probe, comp, kind], vacuum sums."""
+        """One ensemble's record: C[r], CO[r, probe, comp, kind] as values
+        (mantissa * 2^E[r], zero where that underflows), the stored mantissas
+        "C_mant", "CO_mant", the binary exponents "exp" and the vacuum sums."""
         R, Np, Nc = len(self.r), len(self.probes), len(self.comps)
         Cv = rec[: 2 * R].reshape(R, 2)
         CO = rec[2 * R: 2 * R + 4 * R * Np * Nc].reshape(R, Np, Nc, 2, 2)
         b = 2 * R + 4 * R * Np * Nc
-        return {"C": Cv[:, 0] + 1j * Cv[:, 1], "CO": CO[..., 0] + 1j * CO[..., 1],
-                "vac_sq": rec[b: b + 6].copy(), "vac_lin": rec[b + 6: b + 12].copy()}
+        ex = rec[b + 12: b + 12 + R].astype(np.int64)
+        cm = Cv[:, 0] + 1j * Cv[:, 1]
+        com = CO[..., 0] + 1j * CO[..., 1]
+
+        def scale(m, e):
+            return np.ldexp(m.real, e) + 1j * np.ldexp(m.imag, e)
+
+        return {"C": scale(cm, ex), "CO": scale(com, ex[:, None, None, None]), "C_mant": cm, "CO_mant": com,
+                "exp": ex, "vac_sq": rec[b: b + 6].copy(), "vac_lin": rec[b + 6: b + 12].copy()}
 
 
 def plan(spec: Spec) -> dict:

@@ -4,6 +4,9 @@ and synthetic data with known answers.
 * jackknife error of a mean equals the standard error s / sqrt(n) exactly;
 * the connected insertion ratios of synthetic records;
 * V(r) = -ln<P^dagger P>/N_t and the potential fit recover V_0, sigma, gamma;
+* records whose correlators lie far below the range of FP64 (mantissa and
+  binary exponent per separation) give the exact ln<P^dagger P> and the same
+  ratios as the plain values scaled into range (40-digit mpmath sums);
 * the lattice Green function at the origin is Watson's integral / 2 (closed
   form in Gamma functions); G(r) -> 1/(4 pi r); rbar -> r - 1/2;
 * r_0 is exact for a Coulomb-plus-linear potential when rbar makes the
@@ -52,6 +55,37 @@ def test_field_profile_ratios():
     assert np.allclose(out[..., 0, 0], CO.real[..., 0] / C[:, None, None] - np.array(v)[None, None, :])
     assert np.allclose(out[..., 1, 0], CO.imag[..., 1] / C[:, None, None])
     assert np.all(err > 0)
+
+
+def test_scaled_records_below_fp64_range():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    rng = np.random.default_rng(4)
+    n, R, P, Nc = 9, 2, 2, 2
+    recs, scaled = [], []
+    for _ in range(n):
+        ex = rng.integers(-2100, -2090, R)
+        cm = rng.uniform(0.5, 1.0, R) + 1j * rng.normal(0, 1e-3, R)
+        com = rng.normal(size=(R, P, Nc, 2)) + 1j * rng.normal(size=(R, P, Nc, 2))
+        zero = np.zeros(R, complex)
+        recs.append({"C": zero, "CO": np.zeros_like(com), "C_mant": cm, "CO_mant": com, "exp": ex,
+                     "vac_sq": rng.uniform(0.5, 1.5, 6)})
+        # the same record scaled by 2^2095 into range (ratios are unchanged)
+        scaled.append({"C": np.ldexp(cm.real, ex + 2095) + 1j * np.ldexp(cm.imag, ex + 2095),
+                       "CO": np.ldexp(com.real, ex[:, None, None, None] + 2095)
+                       + 1j * np.ldexp(com.imag, ex[:, None, None, None] + 2095),
+                       "vac_sq": recs[-1]["vac_sq"]})
+    lc, lerr = A.log_correlator(recs)
+    for ir in range(R):
+        mean = mp.fsum(mp.mpf(float(r["C_mant"][ir].real)) * mp.mpf(2) ** int(r["exp"][ir]) for r in recs) / n
+        assert abs(lc[ir] - float(mp.log(mean))) < 1e-12 * abs(float(mp.log(mean)))
+    assert np.all(np.isfinite(lerr)) and np.all(lerr > 0)
+    V, _ = A.potential(recs, 4)
+    assert np.allclose(V, -lc / 4, rtol=1e-14)
+    out, err = A.field_profile(recs, [0, 3])
+    want, werr = A.field_profile(scaled, [0, 3])
+    assert np.allclose(out, want, rtol=1e-12, atol=0)
+    assert np.allclose(err, werr, rtol=1e-9, atol=0)
 
 
 def test_potential_and_fit():
@@ -135,3 +169,30 @@ def test_peak_position():
     assert abs(A.peak_position(b, 3.0 - 40 * (b - 1.003) ** 2) - 1.003) < 1e-12
     g = np.exp(-((b - 1.012) / 0.03) ** 2)
     assert abs(A.peak_position(b, g, n_points=3) - 1.012) < 2e-3
+
+
+def test_gamma_method_on_processes_with_known_autocorrelation():
+    """AR(1) x_t = phi x_{t-1} + sqrt(1 - phi^2) e_t has rho(t) = phi^t, so
+    tau_int = (1 + phi) / (2 (1 - phi)) and the error of the mean is
+    sqrt(2 tau_int / n); for independent Gaussian draws of variance s^2 the
+    susceptibility N s^2 has the error N s^2 sqrt(2 / n) and tau_int = 1/2."""
+    rng = np.random.default_rng(11)
+    n = 400_000
+    for phi in (0.0, 0.5, 0.8, 0.95):
+        e = rng.normal(size=n)
+        x = np.empty(n)
+        x[0] = e[0]
+        c = np.sqrt(1 - phi * phi)
+        for t in range(1, n):
+            x[t] = phi * x[t - 1] + c * e[t]
+        sigma, tint, dtint, W = A.gamma_method(x)
+        want = (1 + phi) / (2 * (1 - phi))
+        assert abs(tint - want) < max(3 * dtint, 0.02), (phi, tint, want, dtint)
+        assert abs(sigma - np.sqrt(2 * want / n)) < 0.05 * np.sqrt(2 * want / n)
+        assert W > 0
+    s, N = 0.01, 1000
+    x = rng.normal(0.6, s, n)
+    chi, sig, tint, _, _ = A.susceptibility_gamma(x, N)
+    assert abs(chi - N * s * s) < 4 * sig
+    assert abs(sig - N * s * s * np.sqrt(2 / n)) < 0.05 * sig
+    assert abs(tint - 0.5) < 0.02

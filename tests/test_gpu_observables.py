@@ -3,12 +3,13 @@
    l = -3 .. r + 3 and transverse offsets p1, E_par and E_perp1), history and
    spectral forms, one measurement without updates, against the oracle on the
    same links (FP64 1e-12);
- - a batched coupling scan: the plaquette susceptibility of each ensemble of
-   one batch from the per-sweep plaquettes; at beta = 0.9 (away from the
-   small volume's pseudo-critical region, where tunnelling makes short-chain
-   estimates of chi unreliable) it agrees with the oracle's own chain within
-   4 combined standard errors.
+ - a batched coupling scan: the plaquette susceptibility of replicas at
+   beta = 0.9, 1.0 and 1.1 in one batch from the per-sweep plaquettes, with
+   autocorrelation-aware errors (Gamma method), against the oracle's chains
+   within 3 combined standard errors.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -62,28 +63,35 @@ def test_in_plane_map(env, form):
 
 
 def test_beta_scan_susceptibility(env):
+    """The plaquette susceptibility on 4^4 at beta = 0.9, 1.0 (near this
+    volume's pseudo-critical coupling) and 1.1: eight replicas per coupling in
+    one batch, 10000 sweeps each after 200, errors and integrated
+    autocorrelation times from the Gamma method; against the oracle's own
+    chains (four of 20000 sweeps per coupling, stored by
+    tests/golden/make_susceptibility.py) within 3 combined standard errors."""
     u1, O, configs = env
-    betas = [0.9, 1.0, 1.1]
-    spec, _ = configs.beta_scan(betas, ns=4, nt=4, precision=u1.FP64)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "susceptibility_4x4.json")) as f:
+        gold = json.load(f)
+    betas = [float(b) for b in gold["betas"]]
+    n_rep, n = 8, 10000
+    n_plaq = gold["n_plaquettes"]
+    ens = [u1.Ens((4, 4, 4), 4, b, seed=300 + k, key_id=k) for b in betas for k in range(n_rep)]
+    spec = u1.Spec(ensembles=ens, levels=[(2, 1, 1)], r=[1], precision=u1.FP64, n_or=gold["n_or"])
     ctx = u1.Context(spec)
     ctx.init_links(u1.HOT)
-    ctx.sweeps(100)
-    n, n_plaq = 1500, 6 * 4 ** 4
-    series = np.empty((n, len(betas)))
+    ctx.sweeps(gold["therm"])
+    series = np.empty((n, len(ens)))
     for i in range(n):
         ctx.sweeps(1)
         series[i] = ctx.plaquette().mean(axis=1)
-    chi = [A.plaquette_susceptibility(series[:, j], n_plaq) for j in range(len(betas))]
-    say("GPU chi", chi)
-    ref = O.Lattice(4, [4, 4, 4, 4], 0.9, seed=7, key_id=0)
-    ref.init(1)
-    ref.sweeps(100)
-    os_ = np.empty(n)
-    for i in range(n):
-        ref.sweeps(1)
-        os_[i] = ref.plaquette_means().mean()
-    c_ref, e_ref = A.plaquette_susceptibility(os_, n_plaq)
-    say("oracle chi(0.9)", c_ref, e_ref)
-    c_gpu, e_gpu = chi[0]
-    assert abs(c_gpu - c_ref) < 4 * np.hypot(e_gpu, e_ref)
-    assert all(c > 0 for c, _ in chi)
+    for j, b in enumerate(betas):
+        res = [A.susceptibility_gamma(series[:, j * n_rep + k], n_plaq) for k in range(n_rep)]
+        chi = float(np.mean([r[0] for r in res]))
+        sig = float(np.sqrt(np.sum([r[1] ** 2 for r in res])) / n_rep)
+        tau = max(r[2] for r in res)
+        ref = gold["betas"][str(b)]
+        say(f"beta {b}: GPU chi {chi:.4f} +- {sig:.4f} (tau_int <= {tau:.2f}), "
+            f"oracle {ref['chi']:.4f} +- {ref['sigma']:.4f}")
+        # chains of at least 100 tau_int, where the Gamma-method error is reliable
+        assert n >= 100 * tau and gold["sweeps"] >= 100 * max(c["tau_int"] for c in ref["chains"])
+        assert abs(chi - ref["chi"]) < 3 * np.hypot(sig, ref["sigma"])

@@ -8,15 +8,16 @@ oracle within 1e-12 per phase (test_gpu_parity.py).
   rounding-level difference, so this is the yardstick);
 * one measurement without updates on the same links (the FP32 run holds them
   rounded): every estimate's error against the FP64 run's;
-* the precision study proper: FP32 and FP64 chains from the same seed, every
-  observable's difference against the combined statistical error.
+* the precision study proper: FP32 and FP64 chains of the full preset from
+  the same seed, every observable's difference against the combined
+  statistical error (the FP64 path stands for the oracle at this size).
 """
 import sys
 
 import numpy as np
 import pytest
 
-from helpers.stats import batch_mean_err, circ_dist
+from helpers.stats import circ_dist
 
 pytestmark = pytest.mark.gpu
 
@@ -103,20 +104,27 @@ def test_one_measurement_fp32_against_fp64(env):
 
 
 def test_precision_study_chains(env):
-    """FP32 and FP64 chains of the preset (reduced to 4 x 10 updates per
-    configuration) from the same seed, independent after thermalisation:
-    every correlator, insertion and vacuum estimate agrees within 6 combined
-    standard errors (20 batch means over 40 configurations), and fewer than 5 %
-    of them differ by more than 3; the largest normalised difference is
-    printed."""
+    """FP32 and FP64 chains of the preset (20 outer x 50 inner updates per
+    configuration, 40 configurations, two full sweeps between them) from the
+    same seed, independent after thermalisation.  The host estimators on each
+    chain: <P^dagger P>(r), ln <P^dagger P>(r), the connected insertions of
+    the six components (both kinds and their checks) and the vacuum
+    plaquettes, with jackknife errors over 20 blocks; the normalised
+    differences |FP32 - FP64| / sigma pass the 3-sigma check with its
+    multiple-comparison allowance.  The table of differences is printed."""
+    from helpers.stats import check_sigma
+    from paper_1309_3859_amd import analysis as A
+
     u1, configs = env
+    n_conf, nb = 40, 20
     rec = {}
     for prec in (u1.FP32, u1.FP64):
-        spec, sched = configs.c3_precision(prec, n_outer=4, n_inner=10, max_configs=40)
+        spec, sched = configs.c3_precision(prec, max_configs=n_conf)
+        say("precision chain", prec, spec.levels)
         c = u1.Context(spec)
         c.init_links(sched["start"])
         c.sweeps(30)
-        for _ in range(40):
+        for _ in range(n_conf):
             # full-lattice sweeps between configurations also renew the frozen
             # boundary links, so that the configurations are not all
             # conditioned on the same boundaries
@@ -124,15 +132,19 @@ def test_precision_study_chains(env):
             c.multilevel()
         r = c.results()
         rec[prec] = [spec.unpack(r[k][0]) for k in range(r.shape[0])]
-    worst = 0.0
-    for key, f in [("C", lambda x: x["C"].real), ("CO_sq", lambda x: x["CO"][..., 0].real),
-                   ("CO_lin", lambda x: x["CO"][..., 1].imag), ("vac", lambda x: x["vac_sq"])]:
-        m32, e32 = batch_mean_err(np.array([f(x) for x in rec[u1.FP32]]), 20)
-        m64, e64 = batch_mean_err(np.array([f(x) for x in rec[u1.FP64]]), 20)
-        z = np.abs(m32 - m64) / np.sqrt(e32**2 + e64**2 + 1e-300)
-        say(key, "max |FP32 - FP64| / sigma", float(z.max()), "median", float(np.median(z)),
-            "fraction above 3", float(np.mean(z > 3)))
-        worst = max(worst, float(z.max()))
-        assert np.all(z < 6), key
-        assert np.mean(z > 3) < 0.05, key
-    say("largest normalised difference", worst)
+        c.close()
+    zs = []
+    for name, est in [("<P+P>(r)", lambda rs: A.correlator(rs, n_blocks=nb)),
+                      ("ln <P+P>(r)", lambda rs: A.log_correlator(rs, n_blocks=nb)),
+                      ("<O>_P+P[r, comp, kind]", lambda rs: A.field_profile(rs, spec.comps, spec.dirs, n_blocks=nb)),
+                      ("vacuum <O_sq>", lambda rs: A.jackknife(
+                          A.block_means(np.array([x["vac_sq"] for x in rs]), nb), lambda v: v.mean(axis=0)))]:
+        (m32, e32), (m64, e64) = est(rec[u1.FP32]), est(rec[u1.FP64])
+        z = np.abs(m32 - m64) / np.sqrt(e32 ** 2 + e64 ** 2 + 1e-300)
+        rel = np.abs(e64 / np.where(m64 == 0, 1.0, m64))
+        say(f"{name}: n = {z.size}, max |FP32 - FP64|/sigma {z.max():.2f}, median {np.median(z):.2f}, "
+            f"above 3: {int(np.sum(z > 3))}; median relative FP64 error {np.median(rel):.2e}")
+        zs.append(np.ravel(z))
+    ok, count, allowed, zmax, bound = check_sigma(np.concatenate(zs), nb - 1)
+    say("all", sum(z.size for z in zs), "above 3 sigma", count, "allowed", allowed, "largest", zmax, "bound", bound)
+    assert ok
