@@ -274,14 +274,17 @@ u1ml_status u1ml_autotune(u1ml_ctx* ctx, u1ml_tune_report* report);
 /* Sets the update kernels' work-group size (64, 128, 256, 512 or 1024). */
 u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block);
 
-/* Synchronises.  n_lanes = 2 (the default for two or more ensembles) runs
- * u1ml_sweeps and u1ml_multilevel as two lanes of about equal volume on two
- * streams at once (the context's stream and an internal one, joined back
- * into the context's stream by events), so the arithmetic-bound heatbath
- * phases of one lane overlap the memory-bound overrelaxation phases of the
- * other; n_lanes = 1 runs the whole batch on the context's stream.  Every
- * ensemble's links and estimates are bit-identical either way.  EINVAL for
- * n_lanes other than 1 or 2, or 2 with a single ensemble. */
+/* Synchronises.  n_lanes = 2, 3 or 4 runs u1ml_sweeps and u1ml_multilevel
+ * as that many lanes of about equal volume (ensembles dealt largest first) on
+ * as many streams at once (the context's stream and internal ones, joined
+ * back into the context's stream by events): a checkerboard phase lasts a
+ * few microseconds, mostly launch and load latency, so phases of several
+ * lanes side by side fill the device where one does not, and the
+ * arithmetic-bound heatbath phases of one lane overlap the memory-bound
+ * overrelaxation phases of another.  n_lanes = 1 runs the whole batch on the
+ * context's stream.  Default: 2 for two or more ensembles.  Every ensemble's
+ * links and estimates are bit-identical for every lane count.  EINVAL for
+ * n_lanes outside 1..4 or above the number of ensembles. */
 u1ml_status u1ml_set_lanes(u1ml_ctx* ctx, int n_lanes);
 
 /* 1: capture sweeps and multilevel bodies into HIP graphs (default);

@@ -42,8 +42,8 @@ struct Layout {
     // scratch sub-offsets (bytes from off_scr)
     size_t s_ens, s_obs, s_r, s_probe, s_comp, s_bstart, s_upd, s_ring, s_vpart, s_ppart, s_pout, s_count,
         s_stage, s_bmap, s_mmap, s_prodpart, s_pgroup, s_gdesc;
-    // the two lanes' descriptors and tables (each sized for the whole batch)
-    size_t s_lens[2], s_lbstart[2], s_lbmap[2], s_lmmap[2], s_lring[2];
+    // the lanes' descriptors and tables (each sized for the whole batch)
+    size_t s_lens[4], s_lbstart[4], s_lbmap[4], s_lmmap[4], s_lring[4];
     size_t bmap_stride;  // entries per update class (blocks of 64 threads)
     int n_bstart_tables;
 };
@@ -60,6 +60,8 @@ constexpr int kTabMac = 11;   // spectral sums: work-groups
 constexpr int kTabStage = 12; // spectral staging: work-groups
 constexpr int kNumTabs = 13;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
+constexpr int kMaxLanes = 4;  // streams that sweeps and configurations are spread over
+constexpr int kDefaultLanes = 2;
 
 struct Problem {
     int n_ens = 0;
@@ -401,7 +403,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     Lo->s_bmap = take(sizeof(UpdBlock) * kUpdateClasses * blocks64);
     Lo->s_mmap = take(sizeof(int2) * mblocks);
     Lo->s_prodpart = take(sizeof(double) * PP);
-    for (int l = 0; l < 2; ++l) {
+    for (int l = 0; l < kMaxLanes; ++l) {
         Lo->s_lens[l] = take(sizeof(EnsDesc) * n);
         Lo->s_lbstart[l] = take(sizeof(int) * (n + 1) * kNumTabs);
         Lo->s_lbmap[l] = take(sizeof(UpdBlock) * kUpdateClasses * blocks64);
@@ -472,10 +474,14 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
 // A lane: a subset of the problem's ensembles with its own descriptors,
 // launch tables, results-ring counter, stream and graphs.  The whole batch
 // is one lane (used by every call); a batch of two or more ensembles is also
-// split into two lanes of about equal volume that run sweeps and multilevel
-// configurations on two streams at once, so the heatbath phases (bound by
-// arithmetic) of one lane overlap the overrelaxation phases (bound by memory
-// latency) of the other.  Each ensemble's arithmetic is the same either way.
+// split into up to four lanes of about equal volume that run sweeps and
+// multilevel configurations on as many streams at once.  A checkerboard
+// phase of a few tens of MB lasts a few microseconds, most of it the latency
+// of its dependent loads and of the launch itself, so phases of different
+// lanes running side by side fill the machine where one alone does not, and
+// the heatbath phases (bound by arithmetic) of one lane overlap the
+// overrelaxation phases (bound by memory) of another.  Each ensemble's
+// arithmetic is the same in every lane arrangement.
 struct Lane {
     int n = 0;
     std::vector<int> idx;        // problem indices of the lane's ensembles
@@ -508,8 +514,8 @@ struct u1ml_ctx {
     char* ws = nullptr;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
-    hipStream_t lane_stream = nullptr;  // second lane's stream
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t lane_stream[kMaxLanes] = {};  // streams of lanes 1.. (lane 0 runs on the context's stream)
+    hipEvent_t ev_fork = nullptr, ev_join[kMaxLanes] = {};
     int device = 0;
     // device pointers
     void* links = nullptr;
@@ -533,8 +539,8 @@ struct u1ml_ctx {
     unsigned long long* d_count = nullptr;
     std::vector<EnsDesc> h_ens;  // descriptors in problem order
     Lane whole;                  // every ensemble
-    Lane split[2];               // two lanes (batches of two or more ensembles)
-    bool lanes = false;          // sweeps and configurations run on the two lanes
+    Lane split[kMaxLanes];       // the lanes (batches of two or more ensembles)
+    int n_lanes = 1;             // lanes that sweeps and configurations run on (1: the whole batch)
     int block = 256;
     bool initialised = false;
     int ring_count = 0;
@@ -543,6 +549,14 @@ struct u1ml_ctx {
 };
 
 namespace {
+
+// the whole-batch lane and every lane of the split (those not in use have no ensembles)
+std::vector<Lane*> all_lanes(u1ml_ctx* c)
+{
+    std::vector<Lane*> v{&c->whole};
+    for (int l = 0; l < kMaxLanes; ++l) v.push_back(&c->split[l]);
+    return v;
+}
 
 u1ml_status set_err(u1ml_ctx* c, u1ml_status s, const std::string& m)
 {
@@ -698,6 +712,55 @@ hipError_t upload_lane(const Lane& L)
         e = hipMemcpy(L.d_mmap, L.h_mmap.data(), sizeof(int2) * L.h_mmap.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(L.d_ring, ring0, sizeof ring0, hipMemcpyHostToDevice);
     return e;
+}
+
+// Splits the batch into nl lanes of about equal volume (largest ensembles
+// first, each to the lane with the least volume so far; a lane keeps the
+// problem order), builds and uploads their tables.  Lanes past nl are
+// emptied; their device areas stay reserved.
+hipError_t split_lanes(u1ml_ctx* c, int nl)
+{
+    const int n = c->P.n_ens;
+    const Layout& Lo = c->Lo;
+    char* s = c->ws + Lo.off_scr;
+    std::vector<int> order(n);
+    for (int e = 0; e < n; ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->h_ens[a].vh > c->h_ens[b].vh; });
+    std::vector<std::vector<int>> parts(nl);
+    std::vector<long long> load(nl, 0);
+    for (int e : order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        parts[l].push_back(e);
+        load[l] += c->h_ens[e].vh;
+    }
+    size_t pp_off = 0;
+    for (int l = 0; l < kMaxLanes; ++l) {
+        Lane& L = c->split[l];
+        if (L.g_sweep) (void)hipGraphExecDestroy(L.g_sweep);
+        if (L.g_ml) (void)hipGraphExecDestroy(L.g_ml);
+        L.g_sweep = L.g_ml = nullptr;
+        L.idx = l < nl ? parts[l] : std::vector<int>();
+        std::sort(L.idx.begin(), L.idx.end());
+        L.n = (int)L.idx.size();
+        L.h_ens.clear();
+        for (int e : L.idx) L.h_ens.push_back(c->h_ens[e]);
+        L.bmap_stride = Lo.bmap_stride;
+        L.d_ens = (EnsDesc*)(s + Lo.s_lens[l]);
+        L.d_bstart = (int*)(s + Lo.s_lbstart[l]);
+        L.d_bmap = (UpdBlock*)(s + Lo.s_lbmap[l]);
+        L.d_mmap = (int2*)(s + Lo.s_lmmap[l]);
+        L.d_ring = (int*)(s + Lo.s_lring[l]);
+        // the lanes use disjoint parts of the slab-product partials
+        L.prodpart = (double*)(s + Lo.s_prodpart) + pp_off;
+        L.stream = l == 0 ? c->stream : c->lane_stream[l];
+        if (L.n == 0) continue;
+        build_lane_tables(c, L);
+        pp_off += (size_t)L.tab_total(kTabProd) * kProdQ * 2;
+        hipError_t e = upload_lane(L);
+        if (e != hipSuccess) return e;
+    }
+    c->n_lanes = nl;
+    return hipSuccess;
 }
 
 // Bytes [begin, end) of ensemble k's share of a section whose per-ensemble
@@ -904,7 +967,7 @@ hipError_t enq_sweep_with_counter(u1ml_ctx* c, const Lane& L, hipStream_t st)
 
 void drop_graphs(u1ml_ctx* c)
 {
-    for (Lane* L : {&c->whole, &c->split[0], &c->split[1]}) {
+    for (Lane* L : all_lanes(c)) {
         if (L->g_sweep) (void)hipGraphExecDestroy(L->g_sweep);
         if (L->g_ml) (void)hipGraphExecDestroy(L->g_ml);
         L->g_sweep = L->g_ml = nullptr;
@@ -916,25 +979,32 @@ void release(u1ml_ctx* c)
 {
     drop_graphs(c);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
-    if (c->lane_stream) (void)hipStreamDestroy(c->lane_stream);
+    for (int l = 0; l < kMaxLanes; ++l) {
+        if (c->ev_join[l]) (void)hipEventDestroy(c->ev_join[l]);
+        if (c->lane_stream[l]) (void)hipStreamDestroy(c->lane_stream[l]);
+    }
     if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
 }
 
-// Runs body(lane, stream) for the two lanes at once: the second lane's
-// stream waits for the context's stream, and the context's stream waits for
-// the second lane at the end.
+// Runs body(lane) for the lanes in use, all at once: the streams of lanes
+// 1.. wait for the context's stream (lane 0's), and the context's stream
+// waits for each of them at the end.  One lane: the whole batch on the
+// context's stream.
 template <typename F>
 hipError_t on_lanes(u1ml_ctx* c, F&& body)
 {
+    if (c->n_lanes <= 1) return body(c->whole);
     hipError_t e = hipEventRecord(c->ev_fork, c->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(c->lane_stream, c->ev_fork, 0);
-    if (e == hipSuccess) e = body(c->split[0]);
-    hipError_t e2 = e == hipSuccess ? body(c->split[1]) : hipSuccess;
-    hipError_t e3 = hipEventRecord(c->ev_join, c->lane_stream);
-    if (e3 == hipSuccess) e3 = hipStreamWaitEvent(c->stream, c->ev_join, 0);
-    return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3);
+    for (int l = 1; l < c->n_lanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(c->lane_stream[l], c->ev_fork, 0);
+    for (int l = 0; l < c->n_lanes && e == hipSuccess; ++l) e = body(c->split[l]);
+    // the joins are enqueued whatever happened, so no lane stream is left behind
+    for (int l = 1; l < c->n_lanes; ++l) {
+        hipError_t j = hipEventRecord(c->ev_join[l], c->lane_stream[l]);
+        if (j == hipSuccess) j = hipStreamWaitEvent(c->stream, c->ev_join[l], 0);
+        if (e == hipSuccess) e = j;
+    }
+    return e;
 }
 
 template <typename F>
@@ -1191,53 +1261,22 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
             for (int k = 1; k < 3; ++k)
                 if (n3[(P.dirs[i] + k) % 3] % 4 != 0) c->spec_tile = 2;
     }
-    // the whole batch, and (two or more ensembles) two lanes of about equal
-    // volume, largest ensembles first; each lane keeps the problem order
+    // the whole batch as one lane; the split into lanes follows the streams below
     {
-        std::vector<int> all_idx(n);
-        for (int e = 0; e < n; ++e) all_idx[e] = e;
-        std::vector<int> order(all_idx);
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return c->h_ens[a].vh > c->h_ens[b].vh; });
-        std::vector<int> parts[2];
-        long long load[2] = {0, 0};
-        for (int e : order) {
-            const int l = load[1] < load[0] ? 1 : 0;
-            parts[l].push_back(e);
-            load[l] += c->h_ens[e].vh;
-        }
-        Lane* lanes[3] = {&c->whole, &c->split[0], &c->split[1]};
-        const std::vector<int>* idxs[3] = {&all_idx, &parts[0], &parts[1]};
-        size_t pp_off = 0;
-        for (int l = 0; l < 3; ++l) {
-            Lane& L = *lanes[l];
-            L.idx = *idxs[l];
-            std::sort(L.idx.begin(), L.idx.end());
-            L.n = (int)L.idx.size();
-            L.h_ens.clear();
-            for (int e : L.idx) L.h_ens.push_back(c->h_ens[e]);
-            L.bmap_stride = Lo.bmap_stride;
-            if (l == 0) {
-                L.d_ens = (EnsDesc*)(s + Lo.s_ens);
-                L.d_bstart = (int*)(s + Lo.s_bstart);
-                L.d_bmap = (UpdBlock*)(s + Lo.s_bmap);
-                L.d_mmap = (int2*)(s + Lo.s_mmap);
-                L.d_ring = (int*)(s + Lo.s_ring);
-                L.prodpart = (double*)(s + Lo.s_prodpart);
-                L.stream = c->stream;
-            } else {
-                L.d_ens = (EnsDesc*)(s + Lo.s_lens[l - 1]);
-                L.d_bstart = (int*)(s + Lo.s_lbstart[l - 1]);
-                L.d_bmap = (UpdBlock*)(s + Lo.s_lbmap[l - 1]);
-                L.d_mmap = (int2*)(s + Lo.s_lmmap[l - 1]);
-                L.d_ring = (int*)(s + Lo.s_lring[l - 1]);
-                // the two lanes use disjoint parts of the slab-product partials
-                L.prodpart = (double*)(s + Lo.s_prodpart) + pp_off;
-            }
-            build_lane_tables(c, L);
-            if (l > 0) pp_off += (size_t)L.tab_total(kTabProd) * kProdQ * 2;
-        }
-        c->lanes = n >= 2;
+        Lane& L = c->whole;
+        L.idx.resize(n);
+        for (int e = 0; e < n; ++e) L.idx[e] = e;
+        L.n = n;
+        L.h_ens = c->h_ens;
+        L.bmap_stride = Lo.bmap_stride;
+        L.d_ens = (EnsDesc*)(s + Lo.s_ens);
+        L.d_bstart = (int*)(s + Lo.s_bstart);
+        L.d_bmap = (UpdBlock*)(s + Lo.s_bmap);
+        L.d_mmap = (int2*)(s + Lo.s_mmap);
+        L.d_ring = (int*)(s + Lo.s_ring);
+        L.prodpart = (double*)(s + Lo.s_prodpart);
+        L.stream = c->stream;
+        build_lane_tables(c, L);
     }
     {
         // every dynamic LDS request must fit the device's limit per work-group
@@ -1267,18 +1306,18 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     up(c->d_pgroup, P.pgroup.data(), sizeof(int) * P.pgroup.size());
     up(c->d_gdesc, P.gdesc.data(), sizeof(int) * P.gdesc.size());
     up(c->d_upd, zeros.data(), sizeof(uint32_t) * n);
-    for (Lane* L : {&c->whole, &c->split[0], &c->split[1]}) {
-        if (st != U1ML_OK || L->n == 0) continue;
-        hipError_t e = upload_lane(*L);
+    if (st == U1ML_OK) {
+        hipError_t e = upload_lane(c->whole);
         if (e != hipSuccess) st = set_err(nullptr, U1ML_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
     if (st == U1ML_OK) {
-        hipError_t e = hipStreamCreateWithFlags(&c->lane_stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
-        if (e != hipSuccess) st = set_err(nullptr, U1ML_EDEVICE, std::string("lane stream: ") + hipGetErrorString(e));
-        c->split[0].stream = c->stream;
-        c->split[1].stream = c->lane_stream;
+        hipError_t e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+        for (int l = 1; l < kMaxLanes && e == hipSuccess; ++l) {
+            e = hipStreamCreateWithFlags(&c->lane_stream[l], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[l], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = split_lanes(c, std::min(n, kDefaultLanes));
+        if (e != hipSuccess) st = set_err(nullptr, U1ML_EDEVICE, std::string("lanes: ") + hipGetErrorString(e));
     }
     if (st != U1ML_OK) {
         release(c);
@@ -1334,7 +1373,7 @@ u1ml_status u1ml_sweeps(u1ml_ctx* ctx, int n)
         return hipSuccess;
     };
     const std::string before = ctx->err;
-    hipError_t e = ctx->lanes ? on_lanes(ctx, lane_sweeps) : lane_sweeps(ctx->whole);
+    hipError_t e = on_lanes(ctx, lane_sweeps);
     if (e != hipSuccess)
         return ctx->err != before && e == hipErrorUnknown ? U1ML_EDEVICE
                                                           : set_err(ctx, U1ML_EDEVICE, std::string("sweeps: ") + hipGetErrorString(e));
@@ -1368,7 +1407,7 @@ u1ml_status u1ml_multilevel(u1ml_ctx* ctx)
         return hipGraphLaunch(L.g_ml, L.stream);
     };
     const std::string before = ctx->err;
-    hipError_t e = ctx->lanes ? on_lanes(ctx, lane_config) : lane_config(ctx->whole);
+    hipError_t e = on_lanes(ctx, lane_config);
     if (e != hipSuccess)
         return ctx->err != before && e == hipErrorUnknown
                    ? U1ML_EDEVICE
@@ -1386,7 +1425,7 @@ u1ml_status u1ml_copy_results(u1ml_ctx* ctx, double* host, size_t n_doubles, siz
     const size_t nw = std::min(avail, n_doubles);
     if (nw) HIPCHK(ctx, hipMemcpy(host, ctx->res, nw * sizeof(double), hipMemcpyDeviceToHost));
     int zero[4] = {0, 0, 0, 0};
-    for (Lane* L : {&ctx->whole, &ctx->split[0], &ctx->split[1]})
+    for (Lane* L : all_lanes(ctx))
         if (L->n) HIPCHK(ctx, hipMemcpy(L->d_ring, zero, sizeof zero, hipMemcpyHostToDevice));
     ctx->ring_count = 0;
     if (n_written) *n_written = nw;
@@ -1470,7 +1509,7 @@ u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block)
         return set_err(ctx, U1ML_EINVAL, "block must be 64, 128, 256, 512 or 1024");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->block = block;
-    for (Lane* L : {&ctx->whole, &ctx->split[0], &ctx->split[1]}) {
+    for (Lane* L : all_lanes(ctx)) {
         if (!L->n) continue;
         build_update_tabs(ctx, *L);
         HIPCHK(ctx, hipMemcpy(L->d_bstart, L->h_bstart.data(), sizeof(int) * 4 * (L->n + 1), hipMemcpyHostToDevice));
@@ -1483,13 +1522,13 @@ u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block)
 u1ml_status u1ml_set_lanes(u1ml_ctx* ctx, int n_lanes)
 {
     if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
-    if (n_lanes != 1 && n_lanes != 2) return set_err(ctx, U1ML_EINVAL, "n_lanes must be 1 or 2");
-    if (n_lanes == 2 && ctx->P.n_ens < 2) return set_err(ctx, U1ML_EINVAL, "two lanes need two or more ensembles");
+    if (n_lanes < 1 || n_lanes > kMaxLanes) return set_err(ctx, U1ML_EINVAL, "n_lanes must be 1, 2, 3 or 4");
+    if (n_lanes > ctx->P.n_ens) return set_err(ctx, U1ML_EINVAL, "more lanes than ensembles");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    ctx->lanes = n_lanes == 2;
+    if (n_lanes != ctx->n_lanes) HIPCHK(ctx, split_lanes(ctx, n_lanes));
     // the lanes now in use continue the results ring where it stands
     const int ring[4] = {ctx->ring_count, 0, 0, 0};
-    for (Lane* L : {&ctx->whole, &ctx->split[0], &ctx->split[1]})
+    for (Lane* L : all_lanes(ctx))
         if (L->n) HIPCHK(ctx, hipMemcpy(L->d_ring, ring, sizeof ring, hipMemcpyHostToDevice));
     return U1ML_OK;
 }

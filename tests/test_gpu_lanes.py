@@ -1,8 +1,9 @@
-"""A batch run as two lanes on two streams (the default for two or more
-ensembles) gives the same links, counters and estimates, bit for bit, as the
-whole batch on one stream: one and two levels, history and spectral forms
-(the spectral two-level replay copies and clears only its own lane's
-ensembles)."""
+"""A batch run as two, three or four lanes on as many streams (two is the
+default for two or more ensembles) gives the same links, counters and
+estimates, bit for bit, as the whole batch on one stream: one and two levels,
+history and spectral forms (the spectral two-level replay copies and clears
+only its own lane's ensembles), and a lane count changed between
+configurations continues the same chain."""
 import sys
 
 import numpy as np
@@ -54,25 +55,64 @@ def _run(u1, spec, lanes):
 
 @pytest.mark.parametrize("levels", [[(2, 3, 1)], [(4, 2, 1), (2, 2, 1)]], ids=["one_level", "two_levels"])
 @pytest.mark.parametrize("form", [1, 2], ids=["history", "spectral"])
-def test_two_lanes_bit_identical(u1, levels, form):
-    say("lanes", levels, "form", form)
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_lanes_bit_identical(u1, levels, form, lanes):
+    say("lanes", lanes, levels, "form", form)
     r1, l1, c1 = _run(u1, _spec(u1, levels, form), 1)
-    r2, l2, c2 = _run(u1, _spec(u1, levels, form), 2)
+    r2, l2, c2 = _run(u1, _spec(u1, levels, form), lanes)
     assert c1 == c2
     for a, b in zip(l1, l2):
         assert np.array_equal(a, b)
     assert np.array_equal(r1, r2)
 
 
-def test_set_lanes_rejects_single_ensemble(u1):
+def _spec5(u1):
+    return u1.Spec(ensembles=[u1.Ens((6, 6, 6), 8, 1.0, seed=41), u1.Ens((4, 4, 4), 8, 0.95, seed=42, key_id=1),
+                              u1.Ens((8, 6, 6), 8, 1.02, seed=43, key_id=2), u1.Ens((4, 4, 4), 4, 0.99, seed=44, key_id=3),
+                              u1.Ens((6, 4, 4), 6, 1.01, seed=45, key_id=4)],
+                   levels=[(2, 2, 1)], r=[1, 2], dirs=[0], probes=_disk1(), comps=[0, 3], precision=u1.FP32, n_or=2,
+                   form=1, max_configs=3)
+
+
+def test_lane_count_changed_between_configurations(u1):
+    """Five ensembles: four lanes, then one, then three, one configuration
+    each, equal bit for bit to the same three configurations on one lane."""
+    def run(seq):
+        spec = _spec5(u1)
+        ctx = u1.Context(spec)
+        ctx.init_links(u1.HOT)
+        for n in seq:
+            ctx.set_lanes(n)
+            ctx.sweeps(1)
+            ctx.multilevel()
+        return ctx.results(), [ctx.links(e) for e in range(5)], [ctx.counter(e) for e in range(5)]
+
+    say("lanes 4, 1, 3 against 1, 1, 1")
+    ra, la, ca = run([4, 1, 3])
+    rb, lb, cb = run([1, 1, 1])
+    assert ca == cb
+    for a, b in zip(la, lb):
+        assert np.array_equal(a, b)
+    assert ra.shape[0] == 3
+    assert np.array_equal(ra, rb)
+
+
+def test_set_lanes_rejects_bad_counts(u1):
     spec = u1.Spec(ensembles=[u1.Ens((4, 4, 4), 4, 1.0)], levels=[(2, 1, 1)], r=[1])
     ctx = u1.Context(spec)
-    with pytest.raises(u1.U1MLError):
-        ctx.set_lanes(2)
+    for bad in (0, 2, 5):
+        with pytest.raises(u1.U1MLError):
+            ctx.set_lanes(bad)
     ctx.set_lanes(1)
+    c5 = u1.Context(_spec5(u1))
+    for bad in (0, 5, 6):
+        with pytest.raises(u1.U1MLError):
+            c5.set_lanes(bad)
+    for ok in (4, 3, 2, 1):
+        c5.set_lanes(ok)
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lanes", [1, 2, 3])
 def test_results_ring_keeps_every_configuration(u1, lanes):
     """Three configurations left in the device ring equal the same three
     configurations copied out one at a time (every ring slot holds its own

@@ -4,8 +4,8 @@ a plain FP64 product is zero.  The GPU records mantissas relative to 2^E(r)
 and E(r), like the oracle; both are compared on the same start and counters
 (heatbath-only sweeps, so the two trajectories stay within rounding), in the
 history and spectral forms, one and two levels.  Sizes: 2^3 x 3200 (1600
-thin slabs, E(r) near -1400) and 4 x 2^2 x 2400 (complex estimates at r = 1, 2,
-E(r) near -1100)."""
+thin slabs, E(r) near -1400) and 4 x 2^2 x 3200 (complex estimates at r = 1, 2,
+E(r) near -1440 and -1520)."""
 import sys
 
 import numpy as np
@@ -38,7 +38,7 @@ def env():
 CASES = [
     ((2, 2, 2), 3200, [(2, 3, 1)], [1]),
     ((2, 2, 2), 3200, [(4, 2, 1), (2, 2, 1)], [1]),
-    ((4, 2, 2), 2400, [(2, 3, 1)], [1, 2]),
+    ((4, 2, 2), 3200, [(2, 3, 1)], [1, 2]),
 ]
 
 
