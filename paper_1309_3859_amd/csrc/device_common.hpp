@@ -21,15 +21,17 @@ struct Block4 {
     uint32_t w[4];
 };
 
-__host__ __device__ inline Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                                uint32_t k1)
+// a ^ b ^ c in one instruction (gfx950 three-input bitwise op, truth table 0x96)
+__device__ inline uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
+
+__device__ inline Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -149,132 +151,148 @@ __device__ inline float wrap_angle<float>(float a)
 // ---------------------------------------------------------------------------
 template <typename real>
 __device__ inline real vonmises_psi(real kappa, uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t domain,
-                                    int* n_att)
+                                    int* n_att);
+
+// The envelope parameter r and one Philox block's two attempts (2j from words
+// 0, 1 and 2j+1 from words 2, 3) in FP64; the pair returns which attempt
+// accepted first (1 or 2, with its psi) or 0.
+__device__ inline double bf_r_f64(double kappa)
 {
-    using m = M<real>;
-    if (kappa == real(0)) {
+    using m = M<double>;
+    const double s = m::sqrt_(1.0 + 4.0 * kappa * kappa);
+    const double tau = 1.0 + s;
+    const double rho = m::div_(2.0 * kappa * tau, (s + 1.0) * (tau + m::sqrt_(2.0 * tau)));
+    return m::div_(1.0 + rho * rho, 2.0 * rho);
+}
+
+__device__ inline int bf_pair_f64(double kappa, double r, const Block4& b, double* psi)
+{
+    using m = M<double>;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const uint32_t a = half ? b.w[2] : b.w[0];
+        const uint32_t bb = half ? b.w[3] : b.w[1];
+        const double z = m::cos_pi(m::u1(a));
+        double f = m::div_(1.0 + r * z, r + z);
+        f = f > 1.0 ? 1.0 : (f < -1.0 ? -1.0 : f);
+        const double c = kappa * (r - f);
+        const double u2 = m::u2(bb);
+        bool acc = (c * (2.0 - c) - u2 > 0.0);
+        if (!acc) acc = (m::log_(m::div_(c, u2)) + 1.0 - c >= 0.0);
+        if (acc) {
+            const double p = m::acos_(f);
+            *psi = (a & 1u) ? -p : p;
+            return half + 1;
+        }
+    }
+    return 0;
+}
+
+template <>
+__device__ inline double vonmises_psi<double>(double kappa, uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
+                                              uint32_t domain, int* n_att)
+{
+    using m = M<double>;
+    if (kappa == 0.0) {
         const Block4 b = philox4x32_10(c0, c1, 0u, domain, k0, k1);
         *n_att = 1;
-        return m::pi * (real(2) * m::u1(b.w[0]) - real(1));
+        return m::pi * (2.0 * m::u1(b.w[0]) - 1.0);
     }
-    const real s = m::sqrt_(real(1) + real(4) * kappa * kappa);
-    const real tau = real(1) + s;
-    const real rho = m::div_(real(2) * kappa * tau, (s + real(1)) * (tau + m::sqrt_(real(2) * tau)));
-    const real r = m::div_(real(1) + rho * rho, real(2) * rho);
-    Block4 b;
-    for (int j = 0; j < 65536; ++j) {
-        if ((j & 1) == 0) b = philox4x32_10(c0, c1, (uint32_t)(j >> 1), domain, k0, k1);
-        const uint32_t a = (j & 1) ? b.w[2] : b.w[0];
-        const uint32_t bb = (j & 1) ? b.w[3] : b.w[1];
-        const real z = m::cos_pi(m::u1(a));
-        real f = m::div_(real(1) + r * z, r + z);
-        f = f > real(1) ? real(1) : (f < real(-1) ? real(-1) : f);
-        const real c = kappa * (r - f);
-        const real u2 = m::u2(bb);
-        bool acc = (c * (real(2) - c) - u2 > real(0));
-        if (!acc) acc = (m::log_(m::div_(c, u2)) + real(1) - c >= real(0));
-        if (acc) {
-            *n_att = j + 1;
-            const real psi = m::acos_(f);
-            return (a & 1u) ? -psi : psi;
+    const double r = bf_r_f64(kappa);
+    for (uint32_t jp = 0; jp < 32768u; ++jp) {
+        double psi;
+        const int k = bf_pair_f64(kappa, r, philox4x32_10(c0, c1, jp, domain, k0, k1), &psi);
+        if (k) {
+            *n_att = 2 * (int)jp + k;
+            return psi;
         }
     }
     *n_att = -1;
-    return real(0);
+    return 0.0;
 }
 
-// FP32 form of the same sampler, rewritten so that small |psi| (f near 1) and
-// |psi| near pi (f near -1) keep their relative precision: with
-//   r - 1 = (1 - rho)^2 / (2 rho),  1 - z = 2 sin^2(pi U1 / 2),  1 + z = 2 cos^2(pi U1 / 2),
-//   g = 1 - f = (r - 1)(1 - z) / (r + z),   h = 1 + f = (r + 1)(1 + z) / (r + z),
-//   c = kappa (r - f) = kappa ((r - 1) + g),
-// which are the same quantities as above, free of the cancellation in 1 - f.
-// Returns the accepted deviate as cos(psi) = 1 - g = h - 1 and
-// sin(psi) = sign sqrt(g h), which is all the heatbath needs.
+// FP32 form of the same sampler.  With s = sqrt(1 + 4 kappa^2), Best and
+// Fisher's rho and r = (1 + rho^2) / (2 rho) reduce to r = (1 + s) / (2 kappa)
+// (1 / rho = (tau + sqrt(2 tau)) / (2 kappa) because tau (tau - 2) = 4 kappa^2),
+// and since s - 2 kappa = 1 / (s + 2 kappa),
+//   r - 1 = (1 + 1 / (s + 2 kappa)) / (2 kappa)
+// without cancellation at any kappa.  An attempt is rewritten so that small
+// |psi| (f near 1) and |psi| near pi (f near -1) keep their relative
+// precision: with a = pi U1 / 2, 1 - z = 2 sin^2 a, 1 + z = 2 cos^2 a and
+//   g = 1 - f = (r - 1)(1 - z) / (r + z) = (r - 1) sin^2 a / ((r - 1) / 2 + cos^2 a),
+//   h = 1 + f = (r + 1)(1 + z) / (r + z) = (r + 1) cos^2 a / ((r - 1) / 2 + cos^2 a),
+//   c = kappa (r - f) = kappa (r - 1) + kappa g,
+// the same quantities as above.  Since kappa (r - 1) = (1 + s - 2 kappa) / 2
+// >= 1/2, c >= 1/2 and c / U2 is a normal number, so the logarithmic test
+// ln(c / U2) + 1 - c >= 0 is taken in base 2 on the hardware logarithm:
+// log2(c / U2) >= (c - 1) log2(e).  An accepted deviate is returned as
+// cos(psi) = 1 - g (or h - 1 when g > 1) and sin(psi) = sign sqrt(g h).
+struct BfEnvF32 {
+    float kappa, rm1, half_rm1, rp1, krm1;  // kappa, r - 1, (r - 1) / 2, r + 1, kappa (r - 1)
+};
+
+__device__ inline BfEnvF32 bf_env_f32(float kappa)
+{
+    const float s = __builtin_amdgcn_sqrtf(fmaf(4.0f * kappa, kappa, 1.0f));
+    const float rm1 = (1.0f + __builtin_amdgcn_rcpf(fmaf(2.0f, kappa, s))) * (0.5f * __builtin_amdgcn_rcpf(kappa));
+    return BfEnvF32{kappa, rm1, 0.5f * rm1, rm1 + 2.0f, kappa * rm1};
+}
+
+// Attempts 2j and 2j+1 of the block b (words 0, 1 then 2, 3); returns which
+// accepted first (1 or 2, with (cos psi, sin psi) of that attempt) or 0.
+__device__ inline int bf_pair_f32(const BfEnvF32& v, const Block4& b, float* cpsi, float* spsi)
+{
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const uint32_t a = half ? b.w[2] : b.w[0];
+        const uint32_t bb = half ? b.w[3] : b.w[1];
+        // pi U1 / 2 in revolutions, U1 = ((a >> 9) + 1/2) 2^-23 (exact)
+        const float q = fmaf((float)(a >> 9), 1.0f / 33554432.0f, 1.0f / 67108864.0f);
+        const float sh = __builtin_amdgcn_sinf(q), ch = __builtin_amdgcn_cosf(q);
+        const float sh2 = sh * sh, ch2 = ch * ch;
+        const float inv = __builtin_amdgcn_rcpf(v.half_rm1 + ch2);
+        const float g = v.rm1 * sh2 * inv;
+        const float c = fmaf(v.kappa, g, v.krm1);
+        const float u2 = fmaf((float)(bb >> 9), 1.0f / 8388608.0f, 1.0f / 16777216.0f);
+        bool acc = c * (2.0f - c) - u2 > 0.0f;
+        if (!acc) acc = __builtin_amdgcn_logf(c * __builtin_amdgcn_rcpf(u2)) >= (c - 1.0f) * 1.44269504f;
+        if (acc) {
+            const float h = v.rp1 * ch2 * inv;
+            const float sp = __builtin_amdgcn_sqrtf(g * h);
+            *cpsi = g <= 1.0f ? 1.0f - g : h - 1.0f;
+            *spsi = __uint_as_float(__float_as_uint(sp) ^ (a << 31));
+            return half + 1;
+        }
+    }
+    return 0;
+}
+
 __device__ inline void vonmises_cs_f32(float kappa, uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t domain,
                                        float* cpsi, float* spsi, int* n_att)
 {
-    using m = M<float>;
     if (kappa == 0.0f) {
         const Block4 b = philox4x32_10(c0, c1, 0u, domain, k0, k1);
-        const float rev = m::u1(b.w[0]) - 0.5f;  // psi = pi (2 U1 - 1) in revolutions
+        const float rev = M<float>::u1(b.w[0]) - 0.5f;  // psi = pi (2 U1 - 1) in revolutions
         *cpsi = __builtin_amdgcn_cosf(rev);
         *spsi = __builtin_amdgcn_sinf(rev);
         *n_att = 1;
         return;
     }
-    const float s = m::sqrt_(1.0f + 4.0f * kappa * kappa);
-    const float tau = 1.0f + s;
-    const float rho = m::div_(2.0f * kappa * tau, (s + 1.0f) * (tau + m::sqrt_(2.0f * tau)));
-    const float omr = 1.0f - rho;
-    const float rm1 = m::div_(omr * omr, 2.0f * rho);
-    Block4 b;
-    for (int j = 0; j < 65536; ++j) {
-        if ((j & 1) == 0) b = philox4x32_10(c0, c1, (uint32_t)(j >> 1), domain, k0, k1);
-        const uint32_t a = (j & 1) ? b.w[2] : b.w[0];
-        const uint32_t bb = (j & 1) ? b.w[3] : b.w[1];
-        const float q = 0.25f * m::u1(a);  // pi U1 / 2 in revolutions
-        const float sh = __builtin_amdgcn_sinf(q), ch = __builtin_amdgcn_cosf(q);
-        const float omz = 2.0f * sh * sh, opz = 2.0f * ch * ch;
-        const float inv = __builtin_amdgcn_rcpf(rm1 + opz);
-        const float g = rm1 * omz * inv;
-        const float c = kappa * (rm1 + g);
-        const float u2 = m::u2(bb);
-        bool acc = (c * (2.0f - c) - u2 > 0.0f);
-        if (!acc) acc = (m::log_(m::div_(c, u2)) + 1.0f - c >= 0.0f);
-        if (acc) {
-            *n_att = j + 1;
-            const float h = (rm1 + 2.0f) * opz * inv;
-            const float sp = m::sqrt_(g * h);
-            *cpsi = g <= 1.0f ? 1.0f - g : h - 1.0f;
-            *spsi = (a & 1u) ? -sp : sp;
+    const BfEnvF32 v = bf_env_f32(kappa);
+    for (uint32_t jp = 0; jp < 32768u; ++jp) {
+        const Block4 b = philox4x32_10(c0, c1, jp, domain, k0, k1);
+        float cp, sp;
+        const int k = bf_pair_f32(v, b, &cp, &sp);
+        if (k) {
+            *n_att = 2 * (int)jp + k;
+            *cpsi = cp;
+            *spsi = sp;
             return;
         }
     }
     *n_att = -1;
     *cpsi = 1.0f;
     *spsi = 0.0f;
-}
-
-// The FP32 sampler in pieces, for the heatbath kernel's retry queue: the
-// envelope constant r - 1, and one Philox block's two attempts.
-__device__ inline float bf_rm1_f32(float kappa)
-{
-    using m = M<float>;
-    const float s = m::sqrt_(1.0f + 4.0f * kappa * kappa);
-    const float tau = 1.0f + s;
-    const float rho = m::div_(2.0f * kappa * tau, (s + 1.0f) * (tau + m::sqrt_(2.0f * tau)));
-    const float omr = 1.0f - rho;
-    return m::div_(omr * omr, 2.0f * rho);
-}
-
-// Attempts 2j and 2j+1 of the block b; returns true and (cos psi, sin psi) of
-// the first accepted one.
-__device__ inline bool bf_pair_f32(float kappa, float rm1, const Block4& b, float* cpsi, float* spsi)
-{
-    using m = M<float>;
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const uint32_t a = half ? b.w[2] : b.w[0];
-        const uint32_t bb = half ? b.w[3] : b.w[1];
-        const float q = 0.25f * m::u1(a);
-        const float sh = __builtin_amdgcn_sinf(q), ch = __builtin_amdgcn_cosf(q);
-        const float omz = 2.0f * sh * sh, opz = 2.0f * ch * ch;
-        const float inv = __builtin_amdgcn_rcpf(rm1 + opz);
-        const float g = rm1 * omz * inv;
-        const float c = kappa * (rm1 + g);
-        const float u2 = m::u2(bb);
-        bool acc = (c * (2.0f - c) - u2 > 0.0f);
-        if (!acc) acc = (m::log_(m::div_(c, u2)) + 1.0f - c >= 0.0f);
-        if (acc) {
-            const float h = (rm1 + 2.0f) * opz * inv;
-            const float sp = m::sqrt_(g * h);
-            *cpsi = g <= 1.0f ? 1.0f - g : h - 1.0f;
-            *spsi = (a & 1u) ? -sp : sp;
-            return true;
-        }
-    }
-    return false;
 }
 
 template <>

@@ -46,22 +46,59 @@ struct LinkView {
 // Staple sum A = sum_{nu != mu} exp(i phi_f) + exp(i phi_b), nu ascending,
 // forward before backward, phi_f = v0 - v1 - v2, phi_b = v3 - v4 - v5.
 //
-// FP32 heatbath: every lane makes the first two rejection attempts (one Philox
+// Heatbath: every lane makes the first two rejection attempts (one Philox
 // block); the links still pending (about 1 in 10) are compacted, in lane
 // order, into a queue in LDS and finished by consecutive threads, so a wave no
 // longer waits for its slowest lane.  A link's result depends only on its own
-// counters, so the queue changes no result.
-struct RetryQ {
+// counters, so the queue changes no result.  A queue entry holds what the
+// link's final angle needs besides its deviate: FP32 the staple sum A
+// (theta = arg(e^{i psi} conj A) by one atan2), FP64 arg A (theta =
+// wrap(psi - arg A), the definition's order).
+template <typename real>
+struct RetryQ;
+template <>
+struct RetryQ<float> {
     float kappa, ar, ai;
     unsigned lid, off;
 };
+template <>
+struct RetryQ<double> {
+    double kappa, phia;
+    unsigned lid, off;
+};
+
+// the link's new angle from an accepted deviate
+__device__ inline float hb_angle(const RetryQ<float>& q, float cp, float sp)
+{
+    const float th = atan2_fast(sp * q.ar - cp * q.ai, cp * q.ar + sp * q.ai);
+    return th >= 3.14159265f ? -3.14159265f : th;
+}
+__device__ inline double hb_angle(const RetryQ<double>& q, double psi) { return wrap_angle<double>(psi - q.phia); }
+
+// attempts of one Philox block; true with the new angle if one accepted
+__device__ inline bool hb_block(const RetryQ<float>& q, const BfEnvF32& v, const Block4& b, float* th)
+{
+    float cp, sp;
+    if (!bf_pair_f32(v, b, &cp, &sp)) return false;
+    *th = hb_angle(q, cp, sp);
+    return true;
+}
+__device__ inline bool hb_block(const RetryQ<double>& q, double r, const Block4& b, double* th)
+{
+    double psi;
+    if (!bf_pair_f64(q.kappa, r, b, &psi)) return false;
+    *th = hb_angle(q, psi);
+    return true;
+}
+__device__ inline BfEnvF32 hb_env(const RetryQ<float>& q) { return bf_env_f32(q.kappa); }
+__device__ inline double hb_env(const RetryQ<double>& q) { return bf_r_f64(q.kappa); }
 
 template <typename real, int KIND, int MU>
 __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens, const UpdBlock* __restrict__ blocks,
                                                  real* __restrict__ links, const uint32_t* __restrict__ upd,
                                                  int pass_offset, int parity, int tau, float inv_tm1)
 {
-    constexpr bool kQueue = (KIND == 0) && (sizeof(real) == 4);
+    constexpr bool kQueue = KIND == 0;
     // a padding block of the XCD-aware order carries a block index past its
     // ensemble's links, so all its work-items are inactive (no branch on the
     // record, whose fields then all load at once)
@@ -76,8 +113,7 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
     real* lb = links + B.link_off;
     const unsigned vh = (unsigned)B.vh;
     bool pending = false;
-    float q_kappa = 0.0f, q_ar = 0.0f, q_ai = 0.0f;
-    unsigned q_lid = 0, q_off = 0;
+    RetryQ<real> mine{};
     if (active) {
         const int j = fdiv(item, slice, B.inv_slice);
         const int rem = item - (int)__umul24(j, slice);
@@ -132,40 +168,37 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
             ar += co;
             ai += s;
         }
-        if (KIND == 0) {
+        if constexpr (KIND == 0) {
             const real R = M<real>::sqrt_(ar * ar + ai * ai);
             const real kappa = (real)E.beta * R;
-            if constexpr (kQueue) {
+            RetryQ<real> q;
+            real th;
+            bool done = true;
+            if constexpr (sizeof(real) == 4) {
                 // theta = psi - arg A as one angle: exp(i theta) is proportional to
                 // exp(i psi) conj(A), so a single atan2 replaces arccos, atan2 and wrap
-                float cp = 1.0f, sp = 0.0f;
-                bool done;
+                q = RetryQ<float>{kappa, ar, ai, lid, self};
                 if (kappa == 0.0f) {
                     // psi uniform from attempt 0: pi (2 U1 - 1), in revolutions U1 - 1/2
+                    // (with A = 0 as well, theta = psi)
                     const float rev = M<float>::u1(b0.w[0]) - 0.5f;
-                    cp = __builtin_amdgcn_cosf(rev);
-                    sp = __builtin_amdgcn_sinf(rev);
-                    done = true;
+                    if (R == 0.0f) q.ar = 1.0f;
+                    th = hb_angle(q, __builtin_amdgcn_cosf(rev), __builtin_amdgcn_sinf(rev));
                 } else {
-                    done = bf_pair_f32(kappa, bf_rm1_f32(kappa), b0, &cp, &sp);
-                }
-                if (done) {
-                    const float th = atan2_fast(sp * ar - cp * ai, cp * ar + sp * ai);
-                    *dst = th >= 3.14159265f ? -3.14159265f : th;
-                } else {
-                    pending = true;
-                    q_kappa = kappa;
-                    q_ar = ar;
-                    q_ai = ai;
-                    q_lid = lid;
-                    q_off = self;
+                    done = hb_block(q, bf_env_f32(kappa), b0, &th);
                 }
             } else {
-                int na;
-                const real phiA = M<real>::atan2_(ai, ar);
-                const real psi = vonmises_psi<real>(kappa, E.seed, E.key_id, lid, ctr, DOM_HB, &na);
-                if (na < 0) return;
-                *dst = wrap_angle<real>(psi - phiA);
+                q = RetryQ<double>{kappa, M<double>::atan2_(ai, ar), lid, self};
+                if (kappa == 0.0)
+                    th = hb_angle(q, M<double>::pi * (2.0 * M<double>::u1(b0.w[0]) - 1.0));
+                else
+                    done = hb_block(q, bf_r_f64(kappa), b0, &th);
+            }
+            if (done) {
+                *dst = th;
+            } else {
+                pending = true;
+                mine = q;
             }
         } else if (KIND == 2) {
             // Metropolis: theta' = theta + delta (2 U1 - 1), accepted when
@@ -187,7 +220,8 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
         }
     }
     if constexpr (kQueue) {
-        extern __shared__ RetryQ queue[];
+        extern __shared__ __align__(16) unsigned char queue_bytes[];
+        RetryQ<real>* queue = reinterpret_cast<RetryQ<real>*>(queue_bytes);
         __shared__ int wave_count[16];
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const unsigned long long m = __ballot(pending);
@@ -201,24 +235,19 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
         }
         if (pending) {
             const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-            queue[pos] = RetryQ{q_kappa, q_ar, q_ai, q_lid, q_off};
+            queue[pos] = mine;
         }
         __syncthreads();
         const uint32_t ctr = upd[B.res_index] + (uint32_t)pass_offset;
         for (int i = threadIdx.x; i < total; i += blockDim.x) {
-            const RetryQ r = queue[i];
-            const float rm1 = bf_rm1_f32(r.kappa);
-            float cp = 1.0f, sp = 0.0f;
+            const RetryQ<real> r = queue[i];
+            const auto env = hb_env(r);
+            real th = real(0);
             bool done = false;
-            for (uint32_t jp = 1; jp < 32768u && !done; ++jp) {
-                const Block4 b = philox4x32_10(r.lid, ctr, jp, DOM_HB, E.seed, E.key_id);
-                done = bf_pair_f32(r.kappa, rm1, b, &cp, &sp);
-            }
-            if (done) {
-                const float th = atan2_fast(sp * r.ar - cp * r.ai, cp * r.ar + sp * r.ai);
-                *reinterpret_cast<float*>(reinterpret_cast<char*>(lb) + r.off) =
-                    th >= 3.14159265f ? -3.14159265f : th;
-            }
+            // attempts 2 .. 65535 (blocks 1 .. 32767); past the cap the link keeps its angle
+            for (uint32_t jp = 1; jp < 32768u && !done; ++jp)
+                done = hb_block(r, env, philox4x32_10(r.lid, ctr, jp, DOM_HB, E.seed, E.key_id), &th);
+            if (done) *reinterpret_cast<real*>(reinterpret_cast<char*>(lb) + r.off) = th;
         }
     }
 }
@@ -243,7 +272,7 @@ static void launch_update_t(dim3 g, dim3 b, hipStream_t st, hipEvent_t ev0, hipE
                             const UpdBlock* d_bmap, real* links, const uint32_t* d_upd, int pass_offset, int mu,
                             int parity, int tau, float inv_tm1)
 {
-    const size_t lds = (KIND == 0 && sizeof(real) == 4) ? sizeof(RetryQ) * b.x : 0;
+    const size_t lds = KIND == 0 ? sizeof(RetryQ<real>) * b.x : 0;
     switch (mu) {
     case 0: launch_update_mu<real, KIND, 0>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
     case 1: launch_update_mu<real, KIND, 1>(g, b, lds, st, ev0, ev1, d_ens, d_bmap, links, d_upd, pass_offset, parity, tau, inv_tm1); break;
