@@ -256,6 +256,21 @@ u1ml_status u1ml_set_counter(u1ml_ctx* ctx, int ens, uint32_t counter);
  * (E_x, E_y, E_z, B_x, B_y, B_z): out[ens * 6 + o]. */
 u1ml_status u1ml_plaquette(u1ml_ctx* ctx, double* out);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops): the plaquette means of
+ * u1ml_plaquette, from the same kernels in the same order (bit-identical
+ * values), enqueued on the context's stream and written to device memory
+ * d_out[ens * 6 + o] (6 n_ens doubles, owned by the caller).  The
+ * per-work-group partial sums go to a static device array of the library
+ * (1.5 MiB on each GPU it runs on, held until the process ends) instead of
+ * the workspace.  Allocates nothing and does not synchronise.  EINVAL for a
+ * NULL d_out or more than 32 ensembles; ESTATE before the links are set.
+ * Every call on a GPU shares that GPU's array and overwrites all the partial
+ * sums it reads, so no call depends on what an earlier one left there; calls
+ * that overlap in time on one GPU (other streams or contexts) race on the
+ * array, and the caller must order them. */
+u1ml_status u1ml_plaquette_noalloc(u1ml_ctx* ctx, double* d_out);
+
 /* Synchronises.  Number of link angles that are not finite or lie outside
  * [-pi, pi] by more than 2^-20 relative, all ensembles. */
 u1ml_status u1ml_health(u1ml_ctx* ctx, uint64_t* n_bad);

@@ -18,6 +18,8 @@
 #include "device_common.hpp"
 #include <hip/hip_ext.h>
 
+#include <mutex>
+
 #include "u1ml_internal.hpp"
 
 namespace u1ml {
@@ -539,6 +541,35 @@ hipError_t launch_plaquette(const EnsDesc* d_ens, int n_ens, int, int precision,
                            (const float*)links, d_partials);
     hipLaunchKernelGGL(k_plaq_final, dim3(n_ens), dim3(256), 0, st, d_ens, d_partials, d_out);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free plaquette call: the per-work-group
+// partial sums of up to kStaticPlaqEns ensembles (1.5 MiB), one copy per
+// device for the life of the process.  Host code must not pass the array's
+// name to a kernel: it reaches the array only through the address that
+// hipGetSymbolAddress returns with the device current, kept per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[(size_t)kStaticPlaqEns * kPlaqBlocks * 6];
+
+hipError_t static_scratch(double** ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

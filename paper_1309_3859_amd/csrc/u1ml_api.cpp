@@ -537,6 +537,7 @@ struct u1ml_ctx {
     int *d_pgroup = nullptr, *d_gdesc = nullptr;
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
+    double* static_partials = nullptr;  // the library's static scratch on this context's device
     std::vector<EnsDesc> h_ens;  // descriptors in problem order
     Lane whole;                  // every ensemble
     Lane split[kMaxLanes];       // the lanes (batches of two or more ensembles)
@@ -1128,6 +1129,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     c->ws = (char*)d_ws;
     c->stream = (hipStream_t)hip_stream;
     hipError_t he = hipGetDevice(&c->device);
+    if (he == hipSuccess) he = static_scratch(&c->static_partials);
     if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (he != hipSuccess) {
         delete c;
@@ -1485,6 +1487,19 @@ u1ml_status u1ml_plaquette(u1ml_ctx* ctx, double* out)
                                  ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipMemcpy(out, ctx->pout, sizeof(double) * 6 * ctx->P.n_ens, hipMemcpyDeviceToHost));
+    return U1ML_OK;
+}
+
+u1ml_status u1ml_plaquette_noalloc(u1ml_ctx* ctx, double* d_out)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (!d_out) return set_err(ctx, U1ML_EINVAL, "d_out is NULL");
+    if (ctx->P.n_ens > kStaticPlaqEns)
+        return set_err(ctx, U1ML_EINVAL,
+                       "u1ml_plaquette_noalloc takes at most " + std::to_string(kStaticPlaqEns) + " ensembles");
+    if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
+    HIPCHK(ctx, launch_plaquette(ctx->whole.d_ens, ctx->P.n_ens, 0, ctx->P.precision, ctx->links,
+                                 ctx->static_partials, d_out, ctx->stream));
     return U1ML_OK;
 }
 

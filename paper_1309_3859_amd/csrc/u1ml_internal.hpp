@@ -66,6 +66,7 @@ constexpr int kProdChunk = 2048;    // slab products: (axis, site) items per wor
 constexpr int kProdQ = 26;          // slab products: correlator re, im and 12 insertion quantities re, im
 constexpr int kConLds = 49152;      // contraction: LDS budget per work-group (bytes)
 constexpr int kPlaqBlocks = 1024;   // plaquette means: work-groups (and partials) per ensemble
+constexpr int kStaticPlaqEns = 32;  // allocation-free plaquettes: ensembles whose partials fit the static scratch
 
 // --- launchers (k_update.hip) ---
 hipError_t launch_init_links(const EnsDesc* d_ens, const int* d_bstart_all, int n_ens, int total_blocks, int precision,
@@ -79,6 +80,9 @@ hipError_t launch_health(const EnsDesc* d_ens, const int* d_bstart_all, int n_en
                          const void* links, unsigned long long* d_count, hipStream_t st);
 hipError_t launch_plaquette(const EnsDesc* d_ens, int n_ens, int max_blocks_per_ens, int precision, const void* links,
                             double* d_partials, double* d_out, hipStream_t st);
+// device address, on the current device, of the library's static scratch of
+// kStaticPlaqEns * kPlaqBlocks * 6 doubles (resolved once per device)
+hipError_t static_scratch(double** ptr);
 hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, size_t n,
                               uint32_t* d_out, hipStream_t st);
 hipError_t launch_vonmises_fill(double kappa, int precision, uint32_t seed, uint32_t key_id, uint32_t c0, uint32_t c1,

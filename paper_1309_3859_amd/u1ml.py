@@ -98,6 +98,7 @@ def lib():
         "u1ml_get_counter": [vp, i32, C.POINTER(u32)],
         "u1ml_set_counter": [vp, i32, u32],
         "u1ml_plaquette": [vp, pd],
+        "u1ml_plaquette_noalloc": [vp, vp],
         "u1ml_health": [vp, C.POINTER(C.c_uint64)],
         "u1ml_autotune": [vp, C.POINTER(_TuneReport)],
         "u1ml_set_block": [vp, i32],
@@ -302,6 +303,13 @@ class Context:
         out = np.zeros(6 * self.n_ens, dtype=np.float64)
         self._c(lib().u1ml_plaquette(self._h, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out.reshape(self.n_ens, 6)
+
+    def plaquette_noalloc(self, out):
+        """Plaquette means into the float64 device tensor `out` (n_ens * 6
+        elements), asynchronously on the context's stream; the library's
+        static scratch holds the partial sums."""
+        self._c(lib().u1ml_plaquette_noalloc(self._h, C.c_void_p(out.data_ptr())))
+        return out
 
     def health(self) -> int:
         v = C.c_uint64()
