@@ -154,6 +154,10 @@ def parse():
     ap.add_argument("--workload", default="c4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-n-inner", type=int, default=2,
+                    help="inner-level updates of the oracle's sampled configuration (0: the workload's own)")
+    ap.add_argument("--cpu-n-outer", type=int, default=1,
+                    help="outer-level updates of the oracle's sampled configuration (0: the workload's own)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
     ap.add_argument("--block", type=int, default=256,
                     help="work-group size of the update kernels (0: autotune; candidates differ by about 2 percent, "
@@ -170,11 +174,14 @@ def parse():
     return ap.parse_args()
 
 
-def _sample_levels(spec):
+def _sample_levels(spec, n_inner: int = 2, n_outer: int = 1):
+    """The workload's levels with the update counts cut to n_inner (inner
+    level) and n_outer (outer level of two); 0 keeps the workload's count."""
     levels = [list(lv) for lv in spec.levels]
-    levels[-1][1] = 2  # two sublattice updates per level instead of the full count
-    if len(levels) == 2:
-        levels[0][1] = 1
+    if n_inner:
+        levels[-1][1] = n_inner
+    if len(levels) == 2 and n_outer:
+        levels[0][1] = n_outer
     return levels
 
 
@@ -202,7 +209,22 @@ def oracle_configuration(job: dict) -> dict:
     return {"updates": u, "seconds": dt}
 
 
-def cpu_baseline(spec, budget_s: float, workers: int = 16):
+def cpu_model() -> str:
+    """The host CPU's model name (first entry of /proc/cpuinfo), or the
+    platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(spec, budget_s: float, workers: int = 16, n_inner: int = 2, n_outer: int = 1):
     """Time the FP64 oracle on the host cores on a bounded sample of the
     workload: every ensemble of the batch (independent, as on the GPU), one
     multilevel configuration each with the update counts cut down, each in a
@@ -215,7 +237,7 @@ def cpu_baseline(spec, budget_s: float, workers: int = 16):
     from oracle import oracle as O
 
     O.build()
-    levels = _sample_levels(spec)
+    levels = _sample_levels(spec, n_inner, n_outer)
     jobs = [{"ns": list(e.ns), "nt": e.nt, "beta": e.beta, "seed": e.seed, "key_id": e.key_id, "levels": levels,
              "r": list(spec.r), "dirs": list(spec.dirs), "probes": [list(p) for p in spec.probes],
              "comps": list(spec.comps), "n_or": spec.n_or} for e in spec.ensembles]
@@ -243,6 +265,7 @@ def cpu_baseline(spec, budget_s: float, workers: int = 16):
         upd = sum(r["updates"] for r in results)
         cpu_s = sum(r["seconds"] for r in results)
         return {"value": upd / wall, "unit": "link updates/s", "cores": workers, "kind": "oracle",
+                "cpu": cpu_model(), "host_cpus": os.cpu_count(),
                 "sample": f"{len(jobs)} of {len(jobs)} ensembles, one multilevel configuration each with levels "
                           f"{levels} (tau, n_iter, k_sweeps), FP64, one ensemble per process, up to {workers} "
                           f"at a time; {cpu_s:.1f} s of oracle time in {wall:.1f} s",
@@ -260,9 +283,42 @@ def cpu_baseline(spec, budget_s: float, workers: int = 16):
             if t_used > budget_s:
                 break
         return {"value": done_upd / t_used, "unit": "link updates/s", "cores": 1, "kind": "oracle",
+                "cpu": cpu_model(), "host_cpus": os.cpu_count(),
                 "sample": f"{n} of {len(jobs)} ensembles, one multilevel configuration each with levels {levels} "
                           f"(tau, n_iter, k_sweeps), FP64, single thread ({type(exc).__name__} in the "
                           f"per-process run); {t_used:.1f} s"}
+
+
+def step_update_bytes(ctx, spec):
+    """Algorithmic bytes of one step's link updates under the streaming model:
+    the enumerated read and write sets of every phase (u1ml_phase_bytes) of
+    every sweep of the workload's levels, the stochastic pass once and the
+    overrelaxation pass n_or times per sweep."""
+    from paper_1309_3859_amd import u1ml
+
+    stoch = u1ml.METROPOLIS if spec.update == u1ml.UPDATE_METROPOLIS else u1ml.HEATBATH
+    memo = {}
+
+    def sweep(tau):
+        if tau not in memo:
+            b = u = 0.0
+            for mu in range(4):
+                for p in (0, 1):
+                    for kind, times in ((stoch, 1), (u1ml.OVERRELAX, spec.n_or)):
+                        bb, uu = ctx.phase_bytes(kind, mu, p, tau)
+                        b += times * bb
+                        u += times * uu
+            memo[tau] = (b, u)
+        return memo[tau]
+
+    levels = spec.levels
+    ti, ni, ki = levels[-1]
+    bi, ui = sweep(ti)
+    if len(levels) == 1:
+        return ni * ki * bi, ni * ki * ui
+    to, no, ko = levels[0]
+    bo, uo = sweep(to)
+    return no * (ko * bo + ni * ki * bi), no * (ko * uo + ni * ki * ui)
 
 
 def time_steps(ctx, steps: int, warmup: int):
@@ -327,7 +383,9 @@ def copy_reference(nbytes: float, reps: int = 50):
 def run_counter_workload(spec, sched):
     """Kernels for rocprofv3 --pmc runs: a plain copy of 2^28 bytes (its
     FETCH_SIZE / WRITE_SIZE give the counters' scale), then the inner-slab
-    spatial heatbath and overrelaxation phases, 20 launches each."""
+    spatial heatbath and overrelaxation phases (mu = x, parity 0) as the step
+    launches them, one launch per lane, 20 launches of each lane and kind:
+    heatbath lane 0, lane 1, then overrelaxation lane 0, lane 1."""
     import torch
 
     from paper_1309_3859_amd import u1ml
@@ -340,13 +398,18 @@ def run_counter_workload(spec, sched):
     ctx.init_links(sched["start"])
     ctx.sweeps(2)
     tau = spec.levels[-1][0]
+    out = {"copy_bytes": 1 << 28, "lanes": ctx.n_lanes}
     for kind in (0, 1):
-        ctx.time_phase(kind, 0, 0, tau, 20)
+        for lane in range(ctx.n_lanes):
+            us, b, u = ctx.time_phase_lane(lane, kind, 0, 0, tau, 20)
+            out[f"{('hb', 'or')[kind]}_lane{lane}"] = {"bytes": b, "updates": u, "us": us}
     torch.cuda.synchronize()
-    b0, u0 = ctx.phase_bytes(0, 0, 0, tau)
-    b1, u1 = ctx.phase_bytes(1, 0, 0, tau)
-    print(json.dumps({"copy_bytes": 1 << 28, "hb_bytes": b0, "hb_updates": u0, "or_bytes": b1, "or_updates": u1}),
-          flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def progress(msg: str):
+    """One line on stderr per stage of the run (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -395,16 +458,28 @@ def main():
     upd = ctx.plan["updates_per_config"]
     ms = time_steps(ctx, args.steps, args.warmup)
     value = upd * args.steps / (ms / 1e3)
+    progress(f"{args.steps} steps timed: {ms / args.steps:.3f} ms per step")
 
-    # dominant kernel: spatial overrelaxation phase inside inner slabs
+    # dominant kernel: spatial overrelaxation phase inside inner slabs, in the
+    # launch shape of the step (one launch per lane), each lane's launch timed
+    # by its own dispatch events; achieved = the lanes' bytes / their time
     tau = spec.levels[-1][0]
+    lanes = []
+    for lane in range(ctx.n_lanes):
+        lus, lb, lu = ctx.time_phase_lane(lane, 1, 0, 0, tau, 50)
+        lanes.append({"lane": lane, "us_per_launch": lus, "bytes_per_launch": lb, "updates_per_launch": lu,
+                      "GB/s": lb / (lus * 1e-6) / 1e9})
+    us = sum(x["us_per_launch"] for x in lanes) / len(lanes)
+    b = sum(x["bytes_per_launch"] for x in lanes) / len(lanes)
+    u = sum(x["updates_per_launch"] for x in lanes) / len(lanes)
+    achieved = b / (us * 1e-6) / 1e9
+    # every phase kind as one whole-batch launch, for context
     per_phase = {}
     for kind, mu in [(1, 0), (0, 0), (1, 3), (0, 3), (2, 0)]:
-        us = ctx.time_phase(kind, mu, 0, tau, 50)
-        b, u = ctx.phase_bytes(kind, mu, 0, tau)
-        per_phase[(kind, mu)] = (us, b, u)
-    us, b, u = per_phase[(1, 0)]
-    achieved = b / (us * 1e-6) / 1e9
+        pus = ctx.time_phase(kind, mu, 0, tau, 50)
+        pb, pu = ctx.phase_bytes(kind, mu, 0, tau)
+        per_phase[(kind, mu)] = (pus, pb, pu)
+    wus, wb, wu = per_phase[(1, 0)]
     line = {
         "metric": "link updates/s (HB+OR, multilevel)",
         "value": value,
@@ -425,15 +500,27 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counter_traffic() if args.workload == "c4" else None,
-                     "kernel": "k_update<float,1> (overrelaxation, spatial mu, inner slabs)",
-                     "bytes_per_launch": b, "updates_per_launch": u, "us_per_launch": us},
+                     "kernel": "k_update<float,1,0> (overrelaxation, mu = x, inner slabs), one launch per lane "
+                               "as the step launches it; averages over the lanes",
+                     "bytes_per_launch": b, "updates_per_launch": u, "us_per_launch": us, "lanes": lanes,
+                     "whole_batch_launch": {"us_per_launch": wus, "bytes_per_launch": wb, "updates_per_launch": wu,
+                                            "frac": wb / (wus * 1e-6) / 1e9 / HBM_PEAK_GBS}},
         # per launch of each phase over the whole batch; MET = the paper's Metropolis update
         "phases_us": {f"{('HB', 'OR', 'MET')[k]}_mu{m}": v[0] for (k, m), v in per_phase.items()},
     }
-    line["roofline"]["copy_reference"] = copy_reference(b)
+    progress("phases timed")
+    line["roofline"]["copy_reference"] = copy_reference(wb)
+    # the whole step: every update phase's enumerated bytes over the step's time
+    sb, su = step_update_bytes(ctx, spec)
+    assert int(su) == upd, (su, upd)
+    step_gbs = sb / (ms / args.steps * 1e-3) / 1e9
+    line["step_roofline"] = {"bound": "hbm", "achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": step_gbs / HBM_PEAK_GBS, "bytes_per_step": sb, "bytes_per_update": sb / su,
+                             "note": "link-update bytes of every phase of the step (streaming model) / ms_per_step"}
     # the same batch in full-lattice sweeps (thermalisation), next to the multilevel rate of `value`
     line["full_sweeps"] = {"value": time_full_sweeps(ctx), "unit": "link updates/s"}
     line["metropolis"] = metropolis_acceptance(ctx, spec, tau)
+    progress("step bytes, full sweeps and Metropolis acceptance done")
     if not args.no_fp64 and spec.precision == u1ml.FP32:
         # the same workload with FP64 link storage and update arithmetic
         spec64, _ = make()
@@ -449,7 +536,9 @@ def main():
                               "ms_per_step": ms64 / args.steps, "dtype": "f64",
                               "accuracy_of_f32": measurement_accuracy(ctx64, spec)}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
+        progress("FP64 leg done; timing the oracle on the host")
+        line["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds, n_inner=args.cpu_n_inner,
+                                            n_outer=args.cpu_n_outer)
     print(json.dumps(line), flush=True)
 
 

@@ -309,11 +309,23 @@ u1ml_status u1ml_set_lanes(u1ml_ctx* ctx, int n_lanes);
 u1ml_status u1ml_set_graphs(u1ml_ctx* ctx, int enable);
 
 /* Synchronises.  Average device time in microseconds of one launch of the
- * given checkerboard phase: n_rep launches on the context's stream, each with
- * a start/stop event pair that takes the dispatch's own begin and end
- * timestamps (hipExtLaunchKernelGGL), so launch gaps are not counted.  Links
+ * given checkerboard phase over the whole batch: n_rep launches on the
+ * context's stream, each with a start/stop event pair that takes the
+ * dispatch's own begin and end timestamps (hipExtLaunchKernelGGL), so launch
+ * gaps are not counted.  These timestamps bracket the dispatch from its
+ * processing to its completion signal, about 1 us more than the execution
+ * window a kernel trace records for a launch of a few microseconds.  Links
  * change; counters do not. */
 u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int n_rep, double* us);
+
+/* Synchronises.  u1ml_time_phase for one lane of the current split (lane
+ * 0 .. n_lanes - 1; with one lane, the whole batch): that lane's launch of
+ * the phase, as sweeps and configurations launch it, timed alone on the
+ * context's stream; *bytes and *updates receive the lane's streaming-model
+ * bytes and link updates of one launch (as u1ml_phase_bytes).  Links change;
+ * counters do not.  EINVAL for a lane out of range. */
+u1ml_status u1ml_time_phase_lane(u1ml_ctx* ctx, int lane, int kind, int mu, int parity, int tau, int n_rep,
+                                 double* us, double* bytes, long* updates);
 
 /* Algorithmic bytes moved by one launch of that phase under the streaming
  * model: every distinct link angle the phase reads once, every link it writes

@@ -95,28 +95,41 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st)
 // m_in indexes the measurement inside the innermost level, m the measurement
 // inside the configuration.
 // ---------------------------------------------------------------------------
+// Slab sums of the two insertion kinds of one plaquette orientation,
+// accumulated over the slab's time slices and read out once.
 template <typename real>
-__device__ inline void plaq_O(real th, double beta, double sqrt_beta, double* osq, double* olin);
+struct SlabO;
 
 template <>
-__device__ inline void plaq_O<double>(double th, double beta, double sqrt_beta, double* osq, double* olin)
-{
-    double s, c;
-    sincos(th, &s, &c);
-    *osq = 2.0 * beta * (1.0 - c);
-    *olin = sqrt_beta * s;
-}
+struct SlabO<double> {
+    double sq = 0.0, lin = 0.0;
+    __device__ inline void add(double th, double beta, double sqrt_beta)
+    {
+        double s, c;
+        sincos(th, &s, &c);
+        sq += 2.0 * beta * (1.0 - c);
+        lin += sqrt_beta * s;
+    }
+    __device__ inline double osq(double) const { return sq; }
+    __device__ inline double olin(double) const { return lin; }
+};
 
 template <>
-__device__ inline void plaq_O<float>(float th, double beta, double sqrt_beta, double* osq, double* olin)
-{
-    // 1 - cos(th) = 2 sin^2(th / 2), free of cancellation in FP32
-    const float rev = th * 0.159154943f;
-    const float sh = __builtin_amdgcn_sinf(0.5f * rev);
-    const float s = __builtin_amdgcn_sinf(rev);
-    *osq = 4.0 * beta * (double)(sh * sh);
-    *olin = sqrt_beta * (double)s;
-}
+struct SlabO<float> {
+    // 1 - cos(th) = 2 sin^2(th / 2), free of cancellation in FP32; the FP32
+    // sums of sin^2(th / 2) and sin(th) over the slab's few slices are scaled
+    // by 4 beta and sqrt(beta) in FP64
+    float sh2 = 0.0f, s = 0.0f;
+    __device__ inline void add(float th, double, double)
+    {
+        const float rev = th * 0.159154943f;
+        const float sh = __builtin_amdgcn_sinf(0.5f * rev);
+        sh2 += sh * sh;
+        s += __builtin_amdgcn_sinf(rev);
+    }
+    __device__ inline double osq(double beta) const { return 4.0 * beta * (double)sh2; }
+    __device__ inline double olin(double sqrt_beta) const { return sqrt_beta * (double)s; }
+};
 
 // Sum of 12 per-thread doubles over a 256-thread block in a fixed order (lanes
 // l and l + 32 of a wave added by one exchange, the 128 pair sums staged in
@@ -177,47 +190,69 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
         const int y = yz - z * E.ny;
         double Th = 0.0;
         double2 cm = make_double2(1.0, 0.0);  // multihit slab phase
-        double os[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) os[k] = 0.0;
+        SlabO<real> so[6];
         Site c{x, y, z, s * tau, g.sy * yz + g.st * (s * tau)};
-        for (int k = 0; k < tau; ++k) {
-            const unsigned p = (unsigned)((x + y + z + c.t) & 1), q = p ^ 1u;
+        // the 16 link angles of the six plaquettes at (x, t): u[0..3] the four
+        // links at the site, then the ones at x + x, x + y, x + z, x + t
+        auto load_slice = [&](const Site& c, real* u) {
+            // element offsets of the site's parity and the other one (a select,
+            // not a multiplication by the per-thread parity)
+            const bool odd = ((x + y + z + c.t) & 1) != 0;
+            const unsigned po = odd ? vh : 0u, qo = odd ? 0u : vh;
             const Site cx = mv<0, +1>(c, g), cy = mv<1, +1>(c, g), cz = mv<2, +1>(c, g), ct = mv<3, +1>(c, g);
-            auto L = [&](unsigned dir, unsigned par, const Site& st) {
-                return ldo(lb, ((dir * 2u + par) * vh + hidx(st)) * w);
+            auto L = [&](unsigned dir, unsigned par_off, const Site& st) {
+                return ldo(lb, (dir * 2u * vh + par_off + hidx(st)) * w);
             };
-            const real ux = L(0, p, c), uy = L(1, p, c), uz = L(2, p, c), ut = L(3, p, c);
-            const real tx_x = L(3, q, cx), tx_y = L(3, q, cy), tx_z = L(3, q, cz);
-            const real xt = L(0, q, ct), yt = L(1, q, ct), zt = L(2, q, ct);
-            const real zy = L(2, q, cy), yz_ = L(1, q, cz);
-            const real xz = L(0, q, cz), zx = L(2, q, cx);
-            const real yx = L(1, q, cx), xy = L(0, q, cy);
-            Th += (double)ut;
+            u[0] = L(0, po, c), u[1] = L(1, po, c), u[2] = L(2, po, c), u[3] = L(3, po, c);
+            u[4] = L(3, qo, cx), u[5] = L(3, qo, cy), u[6] = L(3, qo, cz);   // t-links at x + x, x + y, x + z
+            u[7] = L(0, qo, ct), u[8] = L(1, qo, ct), u[9] = L(2, qo, ct);   // x, y, z-links at x + t
+            u[10] = L(2, qo, cy), u[11] = L(1, qo, cz);                       // z at x + y, y at x + z
+            u[12] = L(0, qo, cz), u[13] = L(2, qo, cx);                       // x at x + z, z at x + x
+            u[14] = L(1, qo, cx), u[15] = L(0, qo, cy);                       // y at x + x, x at x + y
+        };
+        auto use_slice = [&](const Site& c, const real* u) {
+            Th += (double)u[3];
             if (MULTIHIT) {
                 // conditional mean of the temporal link: e^{-i arg A} I1/I0(beta |A|)
                 real ar, ai;
-                staple_sum<real, 3>(lb, vh, g, c, (int)p, &ar, &ai);
+                const int p = ((x + y + z + c.t) & 1);
+                staple_sum<real, 3>(lb, vh, g, c, p, &ar, &ai);
                 const double R = sqrt((double)ar * (double)ar + (double)ai * (double)ai);
                 const double f = R > 0.0 ? bessel_ratio(E.beta * R) / R : 0.0;
                 const double ur = (double)ar * f, ui = -(double)ai * f;
                 cm = make_double2(cm.x * ur - cm.y * ui, cm.x * ui + cm.y * ur);
             }
             real th[6];
-            th[0] = ux + tx_x - xt - ut;  // P_xt
-            th[1] = uy + tx_y - yt - ut;  // P_yt
-            th[2] = uz + tx_z - zt - ut;  // P_zt
-            th[3] = uy + zy - yz_ - uz;   // P_yz
-            th[4] = uz + xz - zx - ux;    // P_zx
-            th[5] = ux + yx - xy - uy;    // P_xy
+            th[0] = u[0] + u[4] - u[7] - u[3];   // P_xt
+            th[1] = u[1] + u[5] - u[8] - u[3];   // P_yt
+            th[2] = u[2] + u[6] - u[9] - u[3];   // P_zt
+            th[3] = u[1] + u[10] - u[11] - u[2]; // P_yz
+            th[4] = u[2] + u[12] - u[13] - u[0]; // P_zx
+            th[5] = u[0] + u[14] - u[15] - u[1]; // P_xy
 #pragma unroll
-            for (int o = 0; o < 6; ++o) {
-                double a, b;
-                plaq_O<real>(th[o], E.beta, E.sqrt_beta, &a, &b);
-                os[2 * o] += a;
-                os[2 * o + 1] += b;
-            }
-            c = ct;
+            for (int o = 0; o < 6; ++o) so[o].add(th[o], E.beta, E.sqrt_beta);
+        };
+        // slices two at a time, all 32 loads issued before either is used
+        int k = 0;
+        for (; k + 1 < tau; k += 2) {
+            const Site c1 = mv<3, +1>(c, g);
+            real a[16], b[16];
+            load_slice(c, a);
+            load_slice(c1, b);
+            use_slice(c, a);
+            use_slice(c1, b);
+            c = mv<3, +1>(c1, g);
+        }
+        if (k < tau) {
+            real a[16];
+            load_slice(c, a);
+            use_slice(c, a);
+        }
+        double os[12];
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+            os[2 * o] = so[o].osq(E.beta);
+            os[2 * o + 1] = so[o].olin(E.sqrt_beta);
         }
         double sn, cs;
         sincos(Th, &sn, &cs);
@@ -262,27 +297,21 @@ hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_bl
 }
 
 // ---------------------------------------------------------------------------
-// Inner-level contraction, for charge axis mu and slab s (c_m: stored slab
-// phases, O_m: stored slab sums of measurement m):
-//   [T](s,x,r)        = 1/n sum_m conj(c_m(x)) c_m(x + r mu)
-//   [TO](s,x,r,p,c,k) = 1/n sum_m T_m(s,x,r) O_m(x + l mu + p1 e1 + p2 e2, o(c), k)
-// Everything a pair (x, r) reads lies on its own line parallel to mu and, per
-// probe, on the line displaced by (p1, p2).  A group of threads owns one line,
-// one thread per pair (x, r); the line's phases, and the displaced line's O
-// sums for one probe at a time, are staged through LDS in chunks of
-// measurements, so memory delivers each history element once per line
-// (once per probe for the O sums) rather than once per separation.  The sums
+// Inner-level correlator averages, for charge axis mu and slab s (c_m: stored
+// slab phases of measurement m):
+//   [T](s,x,r) = 1/n sum_m conj(c_m(x)) c_m(x + r mu)
+// Everything a pair (x, r) reads lies on its own line parallel to mu.  A group
+// of threads owns one line, one thread per pair (x, r); the line's phases are
+// staged through LDS in chunks of measurements, so memory delivers each
+// history element once per line rather than once per separation.  The sums
 // over measurements run in order m = 0, 1, ... in every thread.
 // Launch: grid (work-groups of the ensembles' lines, slab, axis); a
 // work-group holds E.con_lpb lines of blockDim / con_lpb threads each.
 // ---------------------------------------------------------------------------
-template <typename ot, bool INS>
 __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
                                                    int n_ens, const ObsDesc* __restrict__ obs,
-                                                   const int* __restrict__ rlist, const int* __restrict__ probes,
-                                                   const int* __restrict__ comps, const double2* __restrict__ hist_c,
-                                                   const ot* __restrict__ hist_o, double2* __restrict__ avg_t,
-                                                   double2* __restrict__ avg_to, int n_meas)
+                                                   const int* __restrict__ rlist, const double2* __restrict__ hist_c,
+                                                   double2* __restrict__ avg_t, int n_meas)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int e = find_ens_m(bstart, n_ens, blockIdx.x);
@@ -308,10 +337,8 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
     // LDS, site index k fastest, so that the consecutive pairs (x, r) of a
     // wave read consecutive 16-byte words (no bank conflicts):
     //   cl[q][k], clm[q][k]        phases of site k of the line (double2)
-    //   ol[q][o][k]                (O_sq, O_lin) of orientation o at site k of the displaced line (double2)
     double2* cl = reinterpret_cast<double2*>(lds_raw) + (size_t)grp * row_len;
-    double2* clm = reinterpret_cast<double2*>(lds_raw) + (size_t)(lpb + grp) * row_len;
-    double2* ol = reinterpret_cast<double2*>(lds_raw) + (size_t)nc_rows * lpb * row_len + (size_t)grp * 6 * row_len;
+    double2* clm = reinterpret_cast<double2*>(lds_raw) + (size_t)(nc_rows - 1) * lpb * row_len + (size_t)grp * row_len;
 
     // transverse coordinates of the line; sites along it are `stride` apart
     const int a1 = line_ok ? line % n3[d1] : 0, a2 = line_ok ? line / n3[d1] : 0;
@@ -349,7 +376,7 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
         }
     };
 
-    for (int pass = 0; !INS && pass < npass; ++pass) {
+    for (int pass = 0; pass < npass; ++pass) {
         const int pr = pass * G + lane;
         const bool act = line_ok && pr < pairs;
         const int ir = act ? pr / N : 0;
@@ -384,95 +411,225 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
             avg_t[E.at_off + (((size_t)id * nr + ir) * S + s) * nsig + base + (size_t)x * stride] =
                 make_double2(tre * inv, tim * inv);
     }
-    if (!INS || O.n_probe == 0) return;  // uniform
+}
 
-    // insertions, one probe at a time: all components, both kinds
+// ---------------------------------------------------------------------------
+// Insertion averages of the inner level (history form), for charge axis mu,
+// slab s and frame component c:
+//   [TO](s, x, r, p, c, k) = 1/n sum_m T_m(s, x, r) O_m(x + sh(r, p, c) + p_perp, o(c), k),
+//   T_m(x, r) = conj(c_m(x)) c_m(x + r mu),
+// sh = l + (mode ? floor((r-1)/2) or floor(r/2) : 0) (the probe's offset along
+// the axis, the mid-plane term depending on whether the plaquette spans mu).
+// For one probe block (probes sharing l and mode) the O value at position y
+// of a displaced line pairs with T(y - sh(r), r) for every r, and each T value
+// with every probe of the block; so work-item (y, r-block, probe block) keeps
+// kInsR x kInsP x 4 accumulators and reads kInsR T values and kInsP O pairs
+// per measurement from LDS (2.3 bytes per FMA), where a work-item per (x, r)
+// reads two phases and an O pair per FMA pair.  Work-group: one line of the
+// axis, one slab, one component, ins_pbw probe blocks; per chunk of ins_mc
+// measurements it stages the line's phases, forms T for every (r, x), and
+// stages the displaced lines' O pairs of its probes.  Sums over measurements
+// run in order m = 0, 1, ... for every output.
+// Launch: grid (work-groups of the ensembles' lines x probe chunks, slab,
+// axis x component), kInsThreads work-items.
+// ---------------------------------------------------------------------------
+template <typename ot>
+__global__ void __launch_bounds__(kInsThreads, 3) k_contract_ins(
+    const EnsDesc* __restrict__ ens, const int* __restrict__ bstart, int n_ens, const ObsDesc* __restrict__ obs,
+    const int* __restrict__ rlist, const int* __restrict__ comps, const int* __restrict__ pblk,
+    const double2* __restrict__ hist_c, const ot* __restrict__ hist_o, double2* __restrict__ avg_to, int n_meas)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int e = find_ens_m(bstart, n_ens, blockIdx.x);
+    const EnsDesc& E = ens[e];
+    const ObsDesc& O = *obs;
+    const int S = E.s_in, s = blockIdx.y;
+    if (s >= S) return;  // uniform for the block
     const int nc = O.n_comp;
+    const int id = blockIdx.z / nc, ic = blockIdx.z - id * nc;
+    const int dir = O.dirs[id], comp = comps[ic];
+    const int n3[3] = {E.nx, E.ny, E.nz};
+    const int N = n3[dir];
+    const int d1 = dir == 2 ? 0 : dir + 1, d2 = dir == 0 ? 2 : dir - 1;  // (dir + 1) % 3, (dir + 2) % 3
+    const int nsig = E.nsig, nlines = nsig / N;
+    const int nr = O.n_r, nrb = (nr + kInsR - 1) / kInsR;
+    const int npb = O.n_pblocks, pbw = E.ins_pbw, nchunk = (npb + pbw - 1) / pbw;
+    const int local = blockIdx.x - bstart[e];
+    const int line = local / nchunk, chunk = local - line * nchunk;
+    if (line >= nlines) return;  // uniform: this axis has fewer lines than the ensemble's largest
+    const int pb0 = chunk * pbw, npbw = min(pbw, npb - pb0);
+    const int nslot = npbw * kInsP;
+    const int mc = E.ins_mc;
+    const int orient = comp_orient(comp, dir);
+    const bool spans = comp_spans_axis(comp);
+
+    // LDS: phases cl[q][k]; T[q][ir][x]; O pairs ol[q][slot][y]; then the
+    // element offset of each slot's displaced line and the separations
+    double2* cl = reinterpret_cast<double2*>(lds_raw);
+    double2* tl = cl + (size_t)mc * N;
+    double2* ol = tl + (size_t)mc * nr * N;
+    int* obase = reinterpret_cast<int*>(ol + (size_t)mc * nslot * N);
+    int* rv = obase + nslot;
+
+    const int a1 = line % n3[d1], a2 = line / n3[d1];
+    const int stride = dir == 0 ? 1 : (dir == 1 ? E.nx : E.nx * E.ny);
+    auto site0 = [&](int o1, int o2) {  // line position 0, displaced by (o1, o2) across the axis
+        int c[3];
+        c[dir] = 0;
+        c[d1] = ((a1 + o1) % n3[d1] + n3[d1]) % n3[d1];
+        c[d2] = ((a2 + o2) % n3[d2] + n3[d2]) % n3[d2];
+        return c[0] + E.nx * (c[1] + E.ny * c[2]);
+    };
+    const int base = site0(0, 0);
+    const size_t mstride = (size_t)S * nsig;
     const size_t mstride_o = (size_t)S * 12 * nsig;
-    const ot* ho = hist_o + E.ho_off + (size_t)s * 12 * nsig;
-    int orient[6];
+    const double2* hc = hist_c + E.hc_off + (size_t)s * nsig + base;
+    const ot* ho = hist_o + E.ho_off + (size_t)s * 12 * nsig + (size_t)(2 * orient) * nsig;
+    const double inv = 1.0 / (double)n_meas;
+    const int tid = threadIdx.x;
+    const int ntask = N * nrb * npbw;
+    for (int j = tid; j < nslot; j += blockDim.x) {
+        const int* B = pblk + kInsBlkInts * (pb0 + j / kInsP);
+        const int pi = j - (j / kInsP) * kInsP;
+        obase[j] = pi < B[2] ? site0(B[8 + 2 * pi], B[9 + 2 * pi]) : -1;  // -1: empty slot
+    }
+    for (int j = tid; j < nr; j += blockDim.x) rv[j] = rlist[j];
+    // staging walks a [rows][N] array: this work-item's first element and the
+    // step of blockDim elements as (rows, columns) with a carry, no division
+    const int k0 = tid % N, row0 = tid / N, drow = (int)blockDim.x / N, dk = (int)blockDim.x - drow * N;
+    // the O pairs of a chunk, [q][slot][k]: the first element's (q, slot)
+    const int oq0 = row0 / nslot, os0 = row0 - oq0 * nslot;
+    auto for_rows = [&](int nrows, auto&& f) {
+        int row = row0, k = k0;
+        while (row < nrows) {
+            f(row, k);
+            row += drow;
+            k += dk;
+            if (k >= N) {
+                k -= N;
+                ++row;
+            }
+        }
+    };
+
+    for (int t0 = 0; t0 < ntask; t0 += blockDim.x) {
+        const int task = t0 + tid;
+        const bool act = task < ntask;
+        const int y = act ? task % N : 0;
+        const int rest = task / N;
+        const int rb = act ? rest % nrb : 0, pbl = act ? rest / nrb : 0;
+        const int* PB = pblk + kInsBlkInts * (pb0 + pbl);
+        const int l = PB[0], mode = PB[1], np = PB[2];
+        // T row and position of each of the work-item's separations
+        int trow[kInsR], tx[kInsR];
 #pragma unroll
-    for (int ic = 0; ic < 6; ++ic) orient[ic] = comp_orient(ic < nc ? comps[ic] : 0, dir);
-    for (int p = 0; p < O.n_probe; ++p) {
-        const int l = probes[4 * p], p1 = probes[4 * p + 1], p2 = probes[4 * p + 2], mode = probes[4 * p + 3];
-        const int obase = site0(p1, p2);
-        for (int pass = 0; pass < npass; ++pass) {
-            const int pr = pass * G + lane;
-            const bool act = line_ok && pr < pairs;
-            const int ir = act ? pr / N : 0;
-            const int x = act ? pr - ir * N : 0;
+        for (int j = 0; j < kInsR; ++j) {
+            const int ir = min(rb * kInsR + j, nr - 1);
             const int r = rlist[ir];
-            int xr = x + r;
-            if (xr >= N) xr -= N;
-            const double2* pa = cl + x;
-            const double2* pb = cl + xr;
-            const double2* po[6];
+            const int sh = l + (mode ? (spans ? (r - 1) / 2 : r / 2) : 0);
+            int x = (y - sh) % N;
+            x += x < 0 ? N : 0;
+            trow[j] = ir;
+            tx[j] = x;
+        }
+        double acc[kInsR][kInsP][4];
 #pragma unroll
-            for (int ic = 0; ic < 6; ++ic) {
-                const int c = ic < nc ? comps[ic] : 0;
-                const int sh = l + (mode ? (comp_spans_axis(c) ? (r - 1) / 2 : r / 2) : 0);
-                po[ic] = ol + orient[ic] * N + ((x + sh) % N + N) % N;
+        for (int j = 0; j < kInsR; ++j)
+#pragma unroll
+            for (int k = 0; k < kInsP; ++k)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[j][k][q] = 0.0;
+
+        for (int m0 = 0; m0 < n_meas; m0 += mc) {
+            const int mm = min(mc, n_meas - m0);
+            __syncthreads();
+            // the line's phases and the displaced lines' O pairs of the chunk:
+            // each work-item issues all its loads of a round before it stores
+            // any of them, so their latencies overlap
+            for (int q = 0; q < mm; ++q) {
+                const double2* hq = hc + (size_t)(m0 + q) * mstride;
+                for_rows(1, [&](int, int k) { cl[q * N + k] = hq[(size_t)k * stride]; });
             }
-            double acc[6][4];
+            {
+                int qq = oq0, sl = os0, kk = k0;
+                while (qq < mm) {
+                    double2 v[kInsStage];
+                    int d[kInsStage];
 #pragma unroll
-            for (int ic = 0; ic < 6; ++ic)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) acc[ic][k] = 0.0;
-            for (int m0 = 0; m0 < n_meas; m0 += mc) {
-                const int mm = min(mc, n_meas - m0);
-                __syncthreads();
-                if (line_ok) {
-                    stage_rows(hc, cl, m0, mm);
-                    // (O_sq, O_lin) pairs of the displaced line, element (o, q, k) with k fastest
-                    int o = l_q / mm, q = l_q - (l_q / mm) * mm, k = l_k;
-                    const int n6 = 6 * N;
-                    for (int j = lane; j < 6 * mm * N; j += G) {
-                        const ot* src = ho + (size_t)(m0 + q) * mstride_o + (size_t)(2 * o) * nsig + obase +
-                                        (size_t)k * stride;
-                        ol[q * n6 + o * N + k] = make_double2((double)src[0], (double)src[nsig]);
-                        q += g_q;
-                        k += g_k;
-                        if (k >= N) {
-                            k -= N;
-                            ++q;
+                    for (int it = 0; it < kInsStage; ++it) {
+                        v[it] = make_double2(0.0, 0.0);
+                        d[it] = -1;
+                        if (qq < mm) {
+                            const int ob = obase[sl];
+                            if (ob >= 0) {
+                                const ot* src = ho + (size_t)(m0 + qq) * mstride_o + ob + (size_t)kk * stride;
+                                v[it] = make_double2((double)src[0], (double)src[nsig]);
+                            }
+                            d[it] = (qq * nslot + sl) * N + kk;
                         }
-                        while (q >= mm) {
-                            q -= mm;
-                            ++o;
+                        kk += dk;
+                        int adv = drow;
+                        if (kk >= N) {
+                            kk -= N;
+                            ++adv;
+                        }
+                        sl += adv;
+                        while (sl >= nslot) {
+                            sl -= nslot;
+                            ++qq;
                         }
                     }
-                }
-                __syncthreads();
-                if (act) {
-                    // every component slot is evaluated (slots past n_comp read a valid
-                    // row and are never stored), so the reads issue together
-                    for (int q = 0; q < mm; ++q) {
-                        const double2 a = pa[q * N];
-                        const double2 b = pb[q * N];
-                        const double Tr = a.x * b.x + a.y * b.y;
-                        const double Ti = a.x * b.y - a.y * b.x;
 #pragma unroll
-                        for (int ic = 0; ic < 6; ++ic) {
-                            const double2 ov = po[ic][q * 6 * N];  // (O_sq, O_lin)
-                            acc[ic][0] += Tr * ov.x;
-                            acc[ic][1] += Ti * ov.x;
-                            acc[ic][2] += Tr * ov.y;
-                            acc[ic][3] += Ti * ov.y;
-                        }
-                    }
+                    for (int it = 0; it < kInsStage; ++it)
+                        if (d[it] >= 0) ol[d[it]] = v[it];
                 }
             }
+            __syncthreads();
+            for (int q = 0; q < mm; ++q) {
+                const double2* cq = cl + q * N;
+                double2* dst = tl + (size_t)q * nr * N;
+                for_rows(nr, [&](int ir, int x) {
+                    int xr = x + rv[ir];
+                    xr -= xr >= N ? N : 0;
+                    const double2 a = cq[x], b = cq[xr];
+                    dst[ir * N + x] = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+                });
+            }
+            __syncthreads();
             if (act) {
-                const size_t xs = (size_t)base + (size_t)x * stride;
+                for (int q = 0; q < mm; ++q) {
+                    double2 t[kInsR], o[kInsP];
 #pragma unroll
-                for (int ic = 0; ic < 6; ++ic) {
-                    if (ic < nc) {
-                        const size_t k0 = ((((size_t)id * nr + ir) * O.n_probe + p) * nc + ic) * 2;
-                        avg_to[E.ato_off + ((k0 + 0) * S + s) * nsig + xs] =
-                            make_double2(acc[ic][0] * inv, acc[ic][1] * inv);
-                        avg_to[E.ato_off + ((k0 + 1) * S + s) * nsig + xs] =
-                            make_double2(acc[ic][2] * inv, acc[ic][3] * inv);
-                    }
+                    for (int j = 0; j < kInsR; ++j) t[j] = tl[((size_t)q * nr + trow[j]) * N + tx[j]];
+#pragma unroll
+                    for (int k = 0; k < kInsP; ++k) o[k] = ol[((size_t)q * nslot + pbl * kInsP + k) * N + y];
+#pragma unroll
+                    for (int j = 0; j < kInsR; ++j)
+#pragma unroll
+                        for (int k = 0; k < kInsP; ++k) {
+                            acc[j][k][0] += t[j].x * o[k].x;
+                            acc[j][k][1] += t[j].y * o[k].x;
+                            acc[j][k][2] += t[j].x * o[k].y;
+                            acc[j][k][3] += t[j].y * o[k].y;
+                        }
+                }
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < kInsR; ++j) {
+                const int ir = rb * kInsR + j;
+                if (ir >= nr) continue;
+                const size_t xs = (size_t)base + (size_t)tx[j] * stride;
+#pragma unroll
+                for (int k = 0; k < kInsP; ++k) {
+                    if (k >= np) continue;
+                    const int p = PB[4 + k];
+                    const size_t k0 = ((((size_t)id * nr + ir) * O.n_probe + p) * nc + ic) * 2;
+                    avg_to[E.ato_off + ((k0 + 0) * S + s) * nsig + xs] =
+                        make_double2(acc[j][k][0] * inv, acc[j][k][1] * inv);
+                    avg_to[E.ato_off + ((k0 + 1) * S + s) * nsig + xs] =
+                        make_double2(acc[j][k][2] * inv, acc[j][k][3] * inv);
                 }
             }
         }
@@ -480,26 +637,27 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
 }
 
 hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
-                           size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_probe,
-                           const int* d_comp, const double2* hist_c, const void* hist_o, double2* avg_t,
-                           double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st)
+                           size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const double2* hist_c,
+                           double2* avg_t, int n_meas, int max_slabs, int n_dirs, hipStream_t st)
 {
-    const dim3 g(total_blocks, max_slabs, n_dirs);
-    // slab averages of T, then (if there are probes) the insertions, which
-    // need about twice the registers
-    if (precision == 0) {
-        hipLaunchKernelGGL((k_contract<double, false>), g, dim3(block), lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,
-                           d_r, d_probe, d_comp, hist_c, (const double*)hist_o, avg_t, avg_to, n_meas);
-        if (hist_o)
-            hipLaunchKernelGGL((k_contract<double, true>), g, dim3(block), lds_bytes, st, d_ens, d_bstart, n_ens,
-                               d_obs, d_r, d_probe, d_comp, hist_c, (const double*)hist_o, avg_t, avg_to, n_meas);
-    } else {
-        hipLaunchKernelGGL((k_contract<float, false>), g, dim3(block), lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,
-                           d_r, d_probe, d_comp, hist_c, (const float*)hist_o, avg_t, avg_to, n_meas);
-        if (hist_o)
-            hipLaunchKernelGGL((k_contract<float, true>), g, dim3(block), lds_bytes, st, d_ens, d_bstart, n_ens,
-                               d_obs, d_r, d_probe, d_comp, hist_c, (const float*)hist_o, avg_t, avg_to, n_meas);
-    }
+    hipLaunchKernelGGL(k_contract, dim3(total_blocks, max_slabs, n_dirs), dim3(block), lds_bytes, st, d_ens, d_bstart,
+                       n_ens, d_obs, d_r, hist_c, avg_t, n_meas);
+    return hipGetLastError();
+}
+
+hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+                               size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_comp,
+                               const int* d_pblk, int n_comp, const double2* hist_c, const void* hist_o,
+                               double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    const dim3 g(total_blocks, max_slabs, n_dirs * n_comp);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_contract_ins<double>, g, dim3(kInsThreads), lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,
+                           d_r, d_comp, d_pblk, hist_c, (const double*)hist_o, avg_to, n_meas);
+    else
+        hipLaunchKernelGGL(k_contract_ins<float>, g, dim3(kInsThreads), lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,
+                           d_r, d_comp, d_pblk, hist_c, (const float*)hist_o, avg_to, n_meas);
     return hipGetLastError();
 }
 

@@ -148,7 +148,8 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
 
         // the first Philox block depends only on the link's id and the counter:
         // formed here, it runs while the link angles are still in flight
-        const uint32_t lid = (uint32_t)(MU + 4 * (x + g.nx * (y + g.ny * (z + g.nz * t))));
+        // canonical site x + Nx (y + Ny (z + Nz t)) = x + 2 hrow, so no multiplication
+        const uint32_t lid = (uint32_t)MU + 4u * (uint32_t)x + 8u * (uint32_t)c.hrow;
         const uint32_t ctr = upd[B.res_index] + (uint32_t)pass_offset;
         Block4 b0;
         if (kQueue || KIND == 2)

@@ -41,7 +41,7 @@ struct Layout {
     size_t sz_wf, sz_gf, sz_sph, sz_spo, sz_facc, sz_saved, sz_cpl, sz_opl;
     // scratch sub-offsets (bytes from off_scr)
     size_t s_ens, s_obs, s_r, s_probe, s_comp, s_bstart, s_upd, s_ring, s_vpart, s_ppart, s_pout, s_count,
-        s_stage, s_bmap, s_mmap, s_prodpart, s_pgroup, s_gdesc;
+        s_stage, s_bmap, s_mmap, s_prodpart, s_pgroup, s_gdesc, s_pblk;
     // the lanes' descriptors and tables (each sized for the whole batch)
     size_t s_lens[4], s_lbstart[4], s_lbmap[4], s_lmmap[4], s_lring[4];
     size_t bmap_stride;  // entries per update class (blocks of 64 threads)
@@ -58,7 +58,8 @@ constexpr int kTabSite = 9;   // spectral weights: (axis, r, site) items
 constexpr int kTabPlane = 10; // spectral plane transforms: work-groups
 constexpr int kTabMac = 11;   // spectral sums: work-groups
 constexpr int kTabStage = 12; // spectral staging: work-groups
-constexpr int kNumTabs = 13;
+constexpr int kTabIns = 13;   // insertion contraction: work-groups
+constexpr int kNumTabs = 14;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 constexpr int kMaxLanes = 4;  // streams that sweeps and configurations are spread over
 constexpr int kDefaultLanes = 2;
@@ -84,6 +85,7 @@ struct Problem {
     bool spectral = false;        // insertion contraction in the spectral form
     std::vector<int> pgroup;      // probe -> group of probes sharing (l, mode)
     std::vector<int> gdesc;       // group -> (l, mode)
+    std::vector<int> pblk;        // insertion contraction: probe blocks, kInsBlkInts ints each
     long long nd_cfg = 0;
 };
 
@@ -205,6 +207,27 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
             P->gdesc.push_back(pr.mode);
         }
         P->pgroup.push_back(g);
+    }
+    // probe blocks of the insertion contraction: the probes of each group in
+    // problem order, kInsP at a time
+    P->pblk.clear();
+    for (int g = 0; g < (int)P->gdesc.size() / 2; ++g) {
+        std::vector<int> members;
+        for (int p = 0; p < (int)P->probes.size(); ++p)
+            if (P->pgroup[p] == g) members.push_back(p);
+        for (size_t b = 0; b < members.size(); b += kInsP) {
+            int blk[kInsBlkInts] = {};
+            blk[0] = P->gdesc[2 * g];
+            blk[1] = P->gdesc[2 * g + 1];
+            blk[2] = (int)std::min<size_t>(kInsP, members.size() - b);
+            for (int k = 0; k < blk[2]; ++k) {
+                const u1ml_probe& pr = P->probes[members[b + k]];
+                blk[4 + k] = members[b + k];
+                blk[8 + 2 * k] = pr.p1;
+                blk[9 + 2 * k] = pr.p2;
+            }
+            P->pblk.insert(P->pblk.end(), blk, blk + kInsBlkInts);
+        }
     }
     return true;
 }
@@ -412,6 +435,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     }
     Lo->s_pgroup = take(sizeof(int) * std::max<size_t>(Np, 1));
     Lo->s_gdesc = take(sizeof(int) * std::max<size_t>(2 * NG, 2));
+    Lo->s_pblk = take(sizeof(int) * std::max<size_t>(P.pblk.size(), kInsBlkInts));
     Lo->sz_scr = s;
     size_t off = 0;
     Lo->off_links = off;
@@ -534,7 +558,8 @@ struct u1ml_ctx {
     int spec_npm = 0;                              // largest lattice extent (spectral launches)
     long long spec_n12max = 0;                     // largest transverse plane (sites)
     int spec_tile = 4;                             // plane-transform tile (4, or 2 if an extent is not a multiple of 4)
-    int *d_pgroup = nullptr, *d_gdesc = nullptr;
+    int *d_pgroup = nullptr, *d_gdesc = nullptr, *d_pblk = nullptr;
+    size_t ins_lds = 0;  // insertion contraction dynamic LDS per work-group
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
     double* static_partials = nullptr;  // the library's static scratch on this context's device
@@ -664,7 +689,7 @@ void build_lane_tables(const u1ml_ctx* c, Lane& L)
     L.h_bstart.assign((size_t)kNumTabs * (n + 1), 0);
     build_update_tabs(c, L);
     const size_t R = P.r.size(), NG = P.gdesc.size() / 2;
-    std::vector<long long> all(n), meas(n), con(n), comb(n), prod(n), site(n), plane(n), mac(n), stage(n);
+    std::vector<long long> all(n), meas(n), con(n), comb(n), prod(n), site(n), plane(n), mac(n), stage(n), ins(n);
     L.max_s_in = 1;
     for (int e = 0; e < n; ++e) {
         const EnsDesc& E = L.h_ens[e];
@@ -679,6 +704,10 @@ void build_lane_tables(const u1ml_ctx* c, Lane& L)
         all[e] = 8ll * E.vh;
         meas[e] = (long long)E.nsig * E.s_in;
         con[e] = (lines + E.con_lpb - 1) / E.con_lpb;
+        // insertion contraction: (line, probe chunk) work-groups of the axis with the most lines
+        ins[e] = (!P.probes.empty() && !P.spectral)
+                     ? (long long)lines * ((P.pblk.size() / kInsBlkInts + E.ins_pbw - 1) / E.ins_pbw)
+                     : 0;
         comb[e] = (long long)P.n_dirs * R * E.s_out * E.nsig;
         prod[e] = (long long)R * prod_groups(P) * E.prod_nch;
         site[e] = (long long)P.n_dirs * R * E.nsig;
@@ -697,6 +726,7 @@ void build_lane_tables(const u1ml_ctx* c, Lane& L)
     build_tab(L, kTabPlane, plane, 1);
     build_tab(L, kTabMac, mac, 1);
     build_tab(L, kTabStage, stage, 1);
+    build_tab(L, kTabIns, ins, 1);
     L.h_mmap.clear();
     const int* b = &L.h_bstart[(size_t)kTabMeas * (n + 1)];
     for (int e = 0; e < n; ++e)
@@ -855,8 +885,11 @@ hipError_t enq_levels(u1ml_ctx* c, const Lane& L, hipStream_t st, bool store_o, 
         }
         if (e == hipSuccess)
             e = launch_contract(L.d_ens, L.tab_dev(kTabCon), n, L.tab_total(kTabCon), c->con_block, c->con_lds,
-                                c->d_obs, c->d_r, c->d_probe, c->d_comp, c->hc, ins_hist ? c->ho : nullptr, c->at,
-                                c->ato, P.n_i, P.precision, L.max_s_in, P.n_dirs, st);
+                                c->d_obs, c->d_r, c->hc, c->at, P.n_i, L.max_s_in, P.n_dirs, st);
+        if (e == hipSuccess && ins_hist)
+            e = launch_contract_ins(L.d_ens, L.tab_dev(kTabIns), n, L.tab_total(kTabIns), c->ins_lds, c->d_obs,
+                                    c->d_r, c->d_comp, c->d_pblk, (int)P.comps.size(), c->hc, c->ho, c->ato, P.n_i,
+                                    P.precision, L.max_s_in, P.n_dirs, st);
         if (e == hipSuccess && P.two && !spec_acc)
             e = launch_combine(L.d_ens, L.tab_dev(kTabComb), n, L.tab_total(kTabComb), c->d_obs, c->at,
                                ins_hist ? c->ato : nullptr, c->ot, ins_hist ? c->oto : nullptr, P.tau_o / P.tau_i, st);
@@ -1158,6 +1191,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     c->stage = (double*)(s + Lo.s_stage);
     c->d_pgroup = (int*)(s + Lo.s_pgroup);
     c->d_gdesc = (int*)(s + Lo.s_gdesc);
+    c->d_pblk = (int*)(s + Lo.s_pblk);
     c->wf = (double2*)(w + Lo.off_wf);
     c->gf = (double2*)(w + Lo.off_gf);
     c->sph = (double2*)(w + Lo.off_sph);
@@ -1218,6 +1252,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     O.n_comp = (int)P.comps.size();
     O.store_o = P.probes.empty() ? 0 : 1;
     O.n_groups = (int)(P.gdesc.size() / 2);
+    O.n_pblocks = (int)(P.pblk.size() / kInsBlkInts);
     O.n_ens_total = n;
     O.multihit = P.multihit ? 1 : 0;
     O.n_doubles_per_config = P.nd_cfg;
@@ -1231,8 +1266,10 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     // Contraction shape: a line of N sites along a charge axis has N * n_r
     // pairs (x, r), one thread each; a work-group of con_block threads holds
     // con_lpb such lines, and stages con_mc measurements at a time in LDS.
+    // Insertions: a work-group per (line, slab, axis, component, ins_pbw
+    // probe blocks) with N * ceil(n_r / kInsR) * ins_pbw tasks, staging
+    // ins_mc measurements (phases, T for every (r, x), O pairs of its probes).
     const size_t R = P.r.size();
-    const size_t o_bytes = P.probes.empty() ? 0 : 6 * 16;  // (O_sq, O_lin) of six orientations, FP64 in LDS
     std::vector<int> group(n);
     c->con_block = 256;
     for (int e = 0; e < n; ++e) {
@@ -1248,11 +1285,21 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         EnsDesc& E = c->h_ens[e];
         const int n3[3] = {E.nx, E.ny, E.nz};
         const size_t nmax = (size_t)std::max(E.nx, std::max(E.ny, E.nz));
-        const size_t per = (P.multihit ? 32 : 16) + o_bytes;  // LDS bytes per (measurement, line site)
+        const size_t per = P.multihit ? 32 : 16;  // LDS bytes per (measurement, line site)
         E.con_lpb = c->con_block / group[e];
         const size_t fit = (size_t)kConLds / ((size_t)E.con_lpb * nmax * per);
         E.con_mc = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)P.n_i));
         c->con_lds = std::max(c->con_lds, (size_t)E.con_lpb * E.con_mc * nmax * per);
+        if (!P.probes.empty() && !P.spectral) {
+            const int npb = (int)(P.pblk.size() / kInsBlkInts);
+            const int nrb = (int)((R + kInsR - 1) / kInsR);
+            E.ins_pbw = std::max(1, std::min(npb, kInsThreads / (int)(nmax * nrb)));
+            const size_t nslot = (size_t)E.ins_pbw * kInsP;
+            const size_t per_m = 16 * nmax * (1 + R + nslot);
+            const size_t tail = 4 * (nslot + R);  // slot line offsets and separations
+            E.ins_mc = (int)std::max<size_t>(1, std::min<size_t>((size_t)kInsLds / per_m, (size_t)P.n_i));
+            c->ins_lds = std::max(c->ins_lds, per_m * E.ins_mc + tail);
+        }
         E.prod_nch = (P.n_dirs * E.nsig + kProdChunk - 1) / kProdChunk;
         E.res_index = e;
         long long n12max = 0;
@@ -1286,7 +1333,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         hipError_t ea = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
         const size_t plane_lds = P.spectral ? (2 * (size_t)c->spec_n12max + 2 * (size_t)c->spec_npm) * sizeof(double2) : 0;
         const size_t mac_lds = P.spectral ? spec_mac_lds(c->spec_npm) : 0;
-        const size_t need = std::max(c->con_lds, std::max(plane_lds, mac_lds));
+        const size_t need = std::max(std::max(c->con_lds, c->ins_lds), std::max(plane_lds, mac_lds));
         if (ea != hipSuccess || (size_t)lds_max < need) {
             release(c);
             return set_err(nullptr, ea != hipSuccess ? U1ML_EDEVICE : U1ML_ENOTSUP,
@@ -1307,6 +1354,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     up(c->d_comp, P.comps.data(), sizeof(int) * P.comps.size());
     up(c->d_pgroup, P.pgroup.data(), sizeof(int) * P.pgroup.size());
     up(c->d_gdesc, P.gdesc.data(), sizeof(int) * P.gdesc.size());
+    up(c->d_pblk, P.pblk.data(), sizeof(int) * P.pblk.size());
     up(c->d_upd, zeros.data(), sizeof(uint32_t) * n);
     if (st == U1ML_OK) {
         hipError_t e = upload_lane(c->whole);
@@ -1555,10 +1603,13 @@ u1ml_status u1ml_set_graphs(u1ml_ctx* ctx, int enable)
     return U1ML_OK;
 }
 
-u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int n_rep, double* us)
+namespace {
+// Average device time of n_rep launches of one phase by lane L on the
+// context's stream, each launch with its own start/stop event pair.
+u1ml_status time_lane_phase(u1ml_ctx* ctx, const Lane& L, int kind, int mu, int parity, int tau, int n_rep, double* us)
 {
-    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
-    if (!us || n_rep < 1) return set_err(ctx, U1ML_EINVAL, "bad arguments");
+    if (!us || n_rep < 1 || kind < 0 || kind > 2 || mu < 0 || mu > 3 || (parity & ~1))
+        return set_err(ctx, U1ML_EINVAL, "bad arguments");
     if (!ctx->initialised) return set_err(ctx, U1ML_ESTATE, "links not initialised");
     bool ok;
     update_class(ctx, mu, tau, &ok);
@@ -1570,7 +1621,7 @@ u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau
     for (auto& x : ev) HIPCHK(ctx, hipEventCreate(&x));
     hipError_t he = hipSuccess;
     for (int i = 0; i < n_rep && he == hipSuccess; ++i)
-        he = enq_phase(ctx, ctx->whole, ctx->stream, kind, mu, parity, tau, 0, ev[2 * i], ev[2 * i + 1]);
+        he = enq_phase(ctx, L, ctx->stream, kind, mu, parity, tau, 0, ev[2 * i], ev[2 * i + 1]);
     if (he == hipSuccess) he = hipEventSynchronize(ev.back());
     double total = 0.0;
     for (int i = 0; i < n_rep && he == hipSuccess; ++i) {
@@ -1581,6 +1632,36 @@ u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau
     for (auto& x : ev) (void)hipEventDestroy(x);
     if (he != hipSuccess) return set_err(ctx, U1ML_EDEVICE, std::string("time_phase: ") + hipGetErrorString(he));
     *us = 1000.0 * total / n_rep;
+    return U1ML_OK;
+}
+}  // namespace
+
+u1ml_status u1ml_time_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int n_rep, double* us)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    return time_lane_phase(ctx, ctx->whole, kind, mu, parity, tau, n_rep, us);
+}
+
+u1ml_status u1ml_time_phase_lane(u1ml_ctx* ctx, int lane, int kind, int mu, int parity, int tau, int n_rep,
+                                 double* us, double* bytes, long* updates)
+{
+    if (!ctx) return set_err(nullptr, U1ML_EINVAL, "ctx is NULL");
+    if (lane < 0 || lane >= ctx->n_lanes) return set_err(ctx, U1ML_EINVAL, "lane out of range");
+    if (!bytes || !updates) return set_err(ctx, U1ML_EINVAL, "bad arguments");
+    const Lane& L = ctx->n_lanes <= 1 ? ctx->whole : ctx->split[lane];
+    const u1ml_status st = time_lane_phase(ctx, L, kind, mu, parity, tau, n_rep, us);
+    if (st != U1ML_OK) return st;
+    const double word = ctx->P.precision == U1ML_FP64 ? 8.0 : 4.0;
+    double b = 0;
+    long u = 0;
+    for (int e : L.idx) {
+        long long w, uu;
+        phase_words(ctx->P.ens[e], kind, mu, parity, tau, &w, &uu);
+        b += w * word;
+        u += (long)uu;
+    }
+    *bytes = b;
+    *updates = u;
     return U1ML_OK;
 }
 

@@ -16,7 +16,7 @@ struct EnsDesc {
     int con_lpb, con_mc;  // contraction: lines per work-group, measurements per LDS chunk
     int prod_nch;   // slab products: site chunks per (r, probe)
     int res_index;  // index of the ensemble in the problem (counters, results)
-    int pad0, pad1;
+    int ins_pbw, ins_mc;  // insertion contraction: probe blocks per work-group, measurements per LDS chunk
     float inv_nxh, inv_ny, inv_slice, pad3;  // 1/(Nx/2), 1/Ny, 1/((Nx/2) Ny Nz) for division-free decode
     double beta, sqrt_beta;
     double metro_delta;  // Metropolis proposal step
@@ -58,8 +58,23 @@ struct ObsDesc {
     int n_groups;  // probe groups sharing (l, mode) (spectral form)
     int n_ens_total;  // ensembles of the problem (rows of a results record)
     int multihit;     // correlator averages from multihit slab phases
+    int n_pblocks;    // insertion contraction: blocks of up to kInsP probes sharing (l, mode)
     long long n_doubles_per_config;
 };
+
+// Insertion contraction (history form): a work-item owns one position y of
+// the displaced line, kInsR separations and one block of kInsP probes that
+// share (l, mode), so every staged T value feeds kInsP outputs and every O
+// value kInsR outputs.  A probe block is kInsBlkInts ints: l, mode, number
+// of probes, 0, their indices (kInsP, then padding to 8), then (p1, p2) of
+// each probe.
+constexpr int kInsR = 4;
+constexpr int kInsP = 3;
+constexpr int kInsThreads = 256;
+constexpr int kInsBlkInts = 16;
+constexpr int kInsStage = 4;  // O pairs each work-item loads per staging round
+static_assert(kInsP <= 4 && 8 + 2 * kInsP <= kInsBlkInts, "probe block layout");
+constexpr int kInsLds = 49152;  // LDS budget per work-group (bytes)
 
 constexpr int kUpdateClasses = 4;  // temporal, spatial full, spatial inner tau, spatial outer tau
 constexpr int kProdChunk = 2048;    // slab products: (axis, site) items per work-group
@@ -100,9 +115,13 @@ hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_bl
                           int multihit, hipStream_t st);
 // work-groups of `block` threads, each holding E.con_lpb lines; lds_bytes of dynamic LDS
 hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
-                           size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_probe,
-                           const int* d_comp, const double2* hist_c, const void* hist_o, double2* avg_t,
-                           double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st);
+                           size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const double2* hist_c,
+                           double2* avg_t, int n_meas, int max_slabs, int n_dirs, hipStream_t st);
+// insertion averages [TO] of the inner level from the stored measurements
+hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+                               size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_comp,
+                               const int* d_pblk, int n_comp, const double2* hist_c, const void* hist_o,
+                               double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st);
 hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                           const double2* avg_t, const double2* avg_to, double2* out_t, double2* out_to, int q,
                           hipStream_t st);

@@ -105,6 +105,7 @@ def lib():
         "u1ml_set_graphs": [vp, i32],
         "u1ml_set_lanes": [vp, i32],
         "u1ml_time_phase": [vp, i32, i32, i32, i32, i32, pd],
+        "u1ml_time_phase_lane": [vp, i32, i32, i32, i32, i32, i32, pd, pd, C.POINTER(C.c_long)],
         "u1ml_phase_bytes": [vp, i32, i32, i32, i32, pd, C.POINTER(C.c_long)],
         "u1ml_philox_fill": [u32, u32, u32, u32, u32, u32, sz, vp, vp],
         "u1ml_vonmises_fill": [dbl, i32, u32, u32, u32, u32, sz, vp, vp, vp],
@@ -245,6 +246,7 @@ class Context:
         self._h = h
         self.n_ens = len(spec.ensembles)
         self.nd = self.plan["n_doubles_per_config"]
+        self._n_lanes = 2 if self.n_ens >= 2 else 1  # the library's default
 
     def close(self):
         if getattr(self, "_h", None):
@@ -331,11 +333,23 @@ class Context:
 
     def set_lanes(self, n_lanes: int):
         self._c(lib().u1ml_set_lanes(self._h, int(n_lanes)))
+        self._n_lanes = int(n_lanes)
 
     def time_phase(self, kind: int, mu: int, parity: int, tau: int, n_rep: int) -> float:
         us = C.c_double()
         self._c(lib().u1ml_time_phase(self._h, kind, mu, parity, tau, n_rep, C.byref(us)))
         return us.value
+
+    def time_phase_lane(self, lane: int, kind: int, mu: int, parity: int, tau: int, n_rep: int):
+        """(us per launch, bytes, updates) of one lane's launch of a phase."""
+        us, b, u = C.c_double(), C.c_double(), C.c_long()
+        self._c(lib().u1ml_time_phase_lane(self._h, lane, kind, mu, parity, tau, n_rep, C.byref(us), C.byref(b),
+                                           C.byref(u)))
+        return us.value, b.value, u.value
+
+    @property
+    def n_lanes(self) -> int:
+        return self._n_lanes
 
     def phase_bytes(self, kind: int, mu: int, parity: int, tau: int):
         b, u = C.c_double(), C.c_long()

@@ -216,6 +216,26 @@ def test_sweep_parity_per_pass_fp64(env):
         assert d <= 10 * o + 1e-13
 
 
+def test_first_sweep_of_c1_within_1e12(env):
+    """The bar on its own workload: C1 (4^3 x 4, beta = 1, cold start, Philox
+    seed 1), the first full FP64 sweep (1 heatbath + 3 overrelaxation passes)
+    through u1ml_sweeps; every link angle within 1e-12 of the oracle's.  From
+    the cold start the staple sums are large, so the passes amplify rounding
+    little (the oracle against itself from links perturbed by 1e-15: at most
+    2.1e-13 after the sweep)."""
+    u1, O, torch = env
+    spec, ctx = _ctx(u1, (4, 4, 4), 4, beta=1.0, levels=[(2, 10, 1)], seed=1)
+    ref = O.Lattice(4, [4, 4, 4, 4], 1.0, seed=1)
+    ctx.init_links(u1.COLD)
+    ref.init(0)
+    ctx.sweeps(1)
+    ref.sweeps(1, n_or=3)
+    d = circ_dist(ctx.links(0), ref.links())
+    say("C1 first sweep: max |d theta|", d.max(), "counter", ctx.counter(0), ref.counter)
+    assert ctx.counter(0) == ref.counter == 1
+    assert d.max() < 1e-12
+
+
 def _multilevel_pair(env, ns, nt, levels, n_or, r, dirs, probes, comps, beta=1.0, seed=3, precision=0, start_seed=21):
     u1, O, torch = env
     V = int(np.prod(ns)) * nt
