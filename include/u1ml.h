@@ -347,6 +347,13 @@ u1ml_status u1ml_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
 u1ml_status u1ml_vonmises_fill(double kappa, int precision, uint32_t seed, uint32_t key_id, uint32_t c0,
                                uint32_t c1, size_t n, double* d_out, int* d_attempts, void* hip_stream);
 
+/* Async, no context.  The library's FP64 sine and cosine (the staple sums of
+ * Sec. II, the heatbath's envelope attempts, the slab phases and insertion
+ * plaquettes of Sec. II.C) on n arguments with |x| < 2^22: d_s[i] = sin
+ * d_x[i], d_c[i] = cos d_x[i], all three device arrays of n doubles owned by
+ * the caller. */
+u1ml_status u1ml_sincos_fill(const double* d_x, size_t n, double* d_s, double* d_c, void* hip_stream);
+
 const char* u1ml_status_str(u1ml_status s);
 /* Last error message of ctx, or of the last context-free call if ctx is NULL. */
 const char* u1ml_last_error(const u1ml_ctx* ctx);

@@ -76,7 +76,52 @@ __device__ inline float atan2_fast(float y, float x)
 }
 
 // ---------------------------------------------------------------------------
-// Precision traits.  FP64: library math (ocml), same formulas and order as the
+// FP64 sine and cosine for |x| < 2^22, the arguments of this library (angle
+// sums of a few links, pi u with u in (0, 1), slab sums of temporal links).
+// Cody-Waite reduction x = q pi/2 + r, |r| <= pi/4 + tiny, with pi/2 split
+// into three parts of which the first two carry 30 significant bits (q pi/2
+// parts exact for |q| < 2^23, and x - q P1 exact by Sterbenz's lemma since
+// x / (q P1) lies in [1/2, 2]); then sin r = r + r^3 S(r^2) and
+// cos r = 1 - r^2/2 + r^4 C(r^2) (with 1 - r^2/2 carried as a rounded value
+// plus its exact rounding error), S and C of degree 5 fitted for this library
+// by a Remez exchange in 50-digit arithmetic (polynomial error below
+// 1e-17 absolute on [-pi/4, pi/4]; what remains is FP64 rounding, about an
+// ulp), and the quadrant q mod 4 selects and signs the pair.
+// ---------------------------------------------------------------------------
+__device__ inline void sincos_bounded(double x, double* sp, double* cp)
+{
+    const double q = rint(x * 0.63661977236758138);  // x * 2/pi
+    double r = fma(-q, 1.570796325802803, x);         // pi/2, first 30 bits
+    r = fma(-q, 9.920935791635221e-10, r);            // next 30 bits
+    r = fma(-q, 5.170182981794105e-19, r);            // the rest
+    const double z = r * r;
+    double ps = 1.5918142569704652e-10;
+    ps = fma(ps, z, -2.505113204972727e-08);
+    ps = fma(ps, z, 2.7557316103657487e-06);
+    ps = fma(ps, z, -0.00019841269836761008);
+    ps = fma(ps, z, 0.00833333333333095);
+    ps = fma(ps, z, -0.16666666666666666);
+    const double s = fma(r * z, ps, r);
+    double pc = -1.1382639805756885e-11;
+    pc = fma(pc, z, 2.0876146382220145e-09);
+    pc = fma(pc, z, -2.7557317272344146e-07);
+    pc = fma(pc, z, 2.480158729876704e-05);
+    pc = fma(pc, z, -0.0013888888888887398);
+    pc = fma(pc, z, 0.041666666666666664);
+    // cos: w = 1 - z/2 rounded, plus its rounding error (1 - w) - z/2, exact
+    // by Sterbenz's lemma, so the sum keeps the low bits w dropped
+    const double w = fma(-0.5, z, 1.0);
+    const double c = w + fma(z * z, pc, (1.0 - w) - 0.5 * z);
+    const int n = (int)q & 3;
+    const double a = (n & 1) ? c : s;   // sine before the sign
+    const double b = (n & 1) ? s : c;   // cosine before the sign
+    *sp = (n & 2) ? -a : a;
+    *cp = ((n + 1) & 2) ? -b : b;
+}
+
+// ---------------------------------------------------------------------------
+// Precision traits.  FP64: the bounded sincos above where arguments are
+// bounded, library math (ocml) otherwise, same formulas and order as the
 // definitions; FP32: hardware transcendentals where the error budget allows.
 // ---------------------------------------------------------------------------
 template <typename real>
@@ -86,8 +131,13 @@ template <>
 struct M<double> {
     static constexpr double pi = 3.141592653589793;
     static constexpr double two_pi = 6.283185307179586;
-    __device__ static inline void sincos_(double a, double* s, double* c) { sincos(a, s, c); }
-    __device__ static inline double cos_pi(double u) { return cos(pi * u); }  // cos(pi u)
+    __device__ static inline void sincos_(double a, double* s, double* c) { sincos_bounded(a, s, c); }
+    __device__ static inline double cos_pi(double u)  // cos(pi u), 0 < u < 1
+    {
+        double s, c;
+        sincos_bounded(pi * u, &s, &c);
+        return c;
+    }
     __device__ static inline double atan2_(double y, double x) { return atan2(y, x); }
     __device__ static inline double acos_(double x) { return acos(x); }
     __device__ static inline double log_(double x) { return log(x); }

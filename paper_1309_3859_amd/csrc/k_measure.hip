@@ -106,7 +106,7 @@ struct SlabO<double> {
     __device__ inline void add(double th, double beta, double sqrt_beta)
     {
         double s, c;
-        sincos(th, &s, &c);
+        sincos_bounded(th, &s, &c);
         sq += 2.0 * beta * (1.0 - c);
         lin += sqrt_beta * s;
     }
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens
             os[2 * o + 1] = so[o].olin(E.sqrt_beta);
         }
         double sn, cs;
-        sincos(Th, &sn, &cs);
+        sincos_bounded(Th, &sn, &cs);  // |Th| <= tau pi
         hist_c[E.hc_off + ((size_t)m_in * S + s) * nsig + xs] = make_double2(cs, sn);
         if (MULTIHIT) hist_c[E.hcm_off + ((size_t)m_in * S + s) * nsig + xs] = cm;
         if (store_o) {

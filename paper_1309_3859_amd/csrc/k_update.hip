@@ -624,6 +624,24 @@ hipError_t launch_vonmises_fill(double kappa, int precision, uint32_t seed, uint
     return hipGetLastError();
 }
 
+// the library's FP64 sine and cosine on given arguments
+__global__ void k_sincos_fill(const double* __restrict__ x, size_t n, double* __restrict__ s, double* __restrict__ c)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double sv, cv;
+    sincos_bounded(x[i], &sv, &cv);
+    s[i] = sv;
+    c[i] = cv;
+}
+
+hipError_t launch_sincos_fill(const double* d_x, size_t n, double* d_s, double* d_c, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sincos_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d_x, n, d_s, d_c);
+    return hipGetLastError();
+}
+
 // advances the counters of the n_ens ensembles described by ens[]
 __global__ void k_advance(const EnsDesc* __restrict__ ens, uint32_t* __restrict__ upd, int n_ens, int delta)
 {

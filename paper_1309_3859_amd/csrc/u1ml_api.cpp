@@ -1764,6 +1764,15 @@ u1ml_status u1ml_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
     return U1ML_OK;
 }
 
+u1ml_status u1ml_sincos_fill(const double* d_x, size_t n, double* d_s, double* d_c, void* hip_stream)
+{
+    if ((!d_x || !d_s || !d_c) && n) return set_err(nullptr, U1ML_EINVAL, "NULL device pointer");
+    if (n > 0xFFFFFFFFull) return set_err(nullptr, U1ML_EINVAL, "n must be < 2^32");
+    hipError_t e = launch_sincos_fill(d_x, n, d_s, d_c, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return set_err(nullptr, U1ML_EDEVICE, hipGetErrorString(e));
+    return U1ML_OK;
+}
+
 u1ml_status u1ml_vonmises_fill(double kappa, int precision, uint32_t seed, uint32_t key_id, uint32_t c0, uint32_t c1,
                                size_t n, double* d_out, int* d_attempts, void* hip_stream)
 {

@@ -102,6 +102,7 @@ hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1
                               uint32_t* d_out, hipStream_t st);
 hipError_t launch_vonmises_fill(double kappa, int precision, uint32_t seed, uint32_t key_id, uint32_t c0, uint32_t c1,
                                 size_t n, double* d_out, int* d_att, hipStream_t st);
+hipError_t launch_sincos_fill(const double* d_x, size_t n, double* d_s, double* d_c, hipStream_t st);
 hipError_t launch_advance_counters(const EnsDesc* d_ens, uint32_t* d_upd, int n_ens, int delta, hipStream_t st);
 hipError_t launch_gather_links(const EnsDesc* d_ens, int ens, int precision, const void* links, double* d_canon,
                                long long n_sites, hipStream_t st);

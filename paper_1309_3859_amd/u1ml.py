@@ -109,6 +109,7 @@ def lib():
         "u1ml_phase_bytes": [vp, i32, i32, i32, i32, pd, C.POINTER(C.c_long)],
         "u1ml_philox_fill": [u32, u32, u32, u32, u32, u32, sz, vp, vp],
         "u1ml_vonmises_fill": [dbl, i32, u32, u32, u32, u32, sz, vp, vp, vp],
+        "u1ml_sincos_fill": [vp, sz, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -377,3 +378,16 @@ def vonmises_fill(kappa: float, n: int, precision: int = FP64, seed: int = 0, ke
     _check(lib().u1ml_vonmises_fill(float(kappa), precision, seed, key_id, c0, c1, n, C.c_void_p(out.data_ptr()),
                                     C.c_void_p(att.data_ptr()), C.c_void_p(_stream_handle(None))))
     return out, att
+
+
+def sincos_fill(x):
+    """The library's FP64 sine and cosine of the float64 device tensor x;
+    returns (sin x, cos x) as torch tensors."""
+    import torch
+
+    x = x.contiguous()
+    s = torch.empty_like(x)
+    c = torch.empty_like(x)
+    _check(lib().u1ml_sincos_fill(C.c_void_p(x.data_ptr()), x.numel(), C.c_void_p(s.data_ptr()),
+                                  C.c_void_p(c.data_ptr()), C.c_void_p(_stream_handle(None))))
+    return s, c
