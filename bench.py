@@ -385,7 +385,10 @@ def run_counter_workload(spec, sched):
     FETCH_SIZE / WRITE_SIZE give the counters' scale), then the inner-slab
     spatial heatbath and overrelaxation phases (mu = x, parity 0) as the step
     launches them, one launch per lane, 20 launches of each lane and kind:
-    heatbath lane 0, lane 1, then overrelaxation lane 0, lane 1."""
+    heatbath lane 0, lane 1, then overrelaxation lane 0, lane 1; first with
+    the workload's FP32 links, then the same in FP64."""
+    import dataclasses
+
     import torch
 
     from paper_1309_3859_amd import u1ml
@@ -394,16 +397,22 @@ def run_counter_workload(spec, sched):
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    ctx = u1ml.Context(spec)
-    ctx.init_links(sched["start"])
-    ctx.sweeps(2)
-    tau = spec.levels[-1][0]
-    out = {"copy_bytes": 1 << 28, "lanes": ctx.n_lanes}
-    for kind in (0, 1):
-        for lane in range(ctx.n_lanes):
-            us, b, u = ctx.time_phase_lane(lane, kind, 0, 0, tau, 20)
-            out[f"{('hb', 'or')[kind]}_lane{lane}"] = {"bytes": b, "updates": u, "us": us}
-    torch.cuda.synchronize()
+    out = {"copy_bytes": 1 << 28}
+    for prec in (spec.precision, u1ml.FP64 if spec.precision == u1ml.FP32 else None):
+        if prec is None:
+            continue
+        sp = dataclasses.replace(spec, precision=prec, _keep=[])
+        ctx = u1ml.Context(sp)
+        ctx.init_links(sched["start"])
+        ctx.sweeps(2)
+        tau = sp.levels[-1][0]
+        name = "f32" if prec == u1ml.FP32 else "f64"
+        for kind in (0, 1):
+            for lane in range(ctx.n_lanes):
+                us, b, u = ctx.time_phase_lane(lane, kind, 0, 0, tau, 20)
+                out[f"{name}_{('hb', 'or')[kind]}_lane{lane}"] = {"bytes": b, "updates": u, "us": us}
+        torch.cuda.synchronize()
+        ctx.close()
     print(json.dumps(out), flush=True)
 
 
