@@ -134,13 +134,15 @@ def measurement_accuracy(ctx64, spec):
         after[prec] = [c.links(e) for e in range(len(links))]
         c.close()
     pairs = list(zip(out[u1ml.FP32], out[u1ml.FP64]))
-    rel_c = max(float(np.max(np.abs(a["C"] - b["C"]) / np.abs(b["C"]))) for a, b in pairs)
     rel_v = max(float(np.max(np.abs(a["vac_sq"] - b["vac_sq"]) / np.abs(b["vac_sq"]))) for a, b in pairs)
     moved = np.concatenate([(a != th) | (b != th) for a, b, th in zip(after[u1ml.FP32], after[u1ml.FP64], links)])
     d = np.concatenate([np.abs(np.angle(np.exp(1j * (a - b)))) for a, b in zip(after[u1ml.FP32], after[u1ml.FP64])])
     d = d[moved]
-    return {"measurement": "C(r) and vacuum <O_sq>, one measurement without updates on the same FP32-rounded links",
-            "max_rel_diff_C": rel_c, "max_rel_diff_vacuum": rel_v,
+    return {"measurement": "vacuum <O_sq>, one measurement without updates on the same FP32-rounded links (C(r) "
+                           "is formed in FP64 from the stored angles in both forms, so it differs only through the "
+                           "links; chains of both forms agree within 3.2 sigma on every observable of the 32^3x8 "
+                           "precision study, tests/test_gpu_precision.py)",
+            "max_rel_diff_vacuum": rel_v,
             "update": "links after one overrelaxation and one heatbath phase from the same links and counters",
             "link_diff_median": float(np.median(d)), "link_diff_p999": float(np.quantile(d, 0.999)),
             "link_diff_max": float(d.max()), "links_updated": int(d.size)}
@@ -158,7 +160,14 @@ def parse():
                     help="inner-level updates of the oracle's sampled configuration (0: the workload's own)")
     ap.add_argument("--cpu-n-outer", type=int, default=1,
                     help="outer-level updates of the oracle's sampled configuration (0: the workload's own)")
+    ap.add_argument("--cpu-max-probes", type=int, default=0,
+                    help="insertion probes of the oracle's sampled configuration (0: all of the workload's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
+    ap.add_argument("--precision", choices=("workload", "f32", "f64"), default="workload",
+                    help="link storage and update arithmetic of the timed line (default: the workload's own); "
+                         "with f32 the plain FP64 leg times the same workload in FP64")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="time only the oracle on the host (no GPU) and print its cpu_baseline object")
     ap.add_argument("--block", type=int, default=256,
                     help="work-group size of the update kernels (0: autotune; candidates differ by about 2 percent, "
                          "so a fixed size keeps profiled and unprofiled runs on the same launch shape)")
@@ -195,9 +204,15 @@ def oracle_configuration(job: dict) -> dict:
                      probes=[tuple(p) for p in job["probes"]], comps=job["comps"], n_or=n_or)
     lat = O.Lattice(4, list(ns) + [nt], job["beta"], seed=job["seed"], key_id=job["key_id"])
     lat.init(1)
+    # configurations of the chain until min_seconds have passed (at least one)
+    n_cfg = 0
     t0 = time.perf_counter()
-    lat.multilevel(ospec)
-    dt = time.perf_counter() - t0
+    while True:
+        lat.multilevel(ospec)
+        n_cfg += 1
+        dt = time.perf_counter() - t0
+        if dt >= job.get("min_seconds", 0.0):
+            break
     V = ns[0] * ns[1] * ns[2] * nt
     sp = lambda tau: V // 2 // nt * (nt - nt // tau)
     per_sweep = lambda tau: (1 + n_or) * 2 * (V // 2 + 3 * sp(tau))
@@ -206,7 +221,7 @@ def oracle_configuration(job: dict) -> dict:
     if len(levels) == 2:
         to, no, ko = levels[0]
         u = no * (ko * per_sweep(to) + ni * ki * per_sweep(ti))
-    return {"updates": u, "seconds": dt}
+    return {"updates": u * n_cfg, "seconds": dt, "configurations": n_cfg}
 
 
 def cpu_model() -> str:
@@ -224,11 +239,14 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(spec, budget_s: float, workers: int = 16, n_inner: int = 2, n_outer: int = 1):
+def cpu_baseline(spec, budget_s: float, workers: int = 16, n_inner: int = 2, n_outer: int = 1, max_probes: int = 0,
+                 min_seconds: float = 2.0):
     """Time the FP64 oracle on the host cores on a bounded sample of the
     workload: every ensemble of the batch (independent, as on the GPU), one
-    multilevel configuration each with the update counts cut down, each in a
-    child interpreter of its own, up to `workers` at a time.  `value` is the
+    multilevel configuration each with the update counts cut down (repeated
+    until the child has run min_seconds, so that a tiny lattice is not timed
+    on the interpreter's start-up), each in a child interpreter of its own, up
+    to `workers` at a time.  `value` is the
     sample's updates over the wall time; `single_thread` the same updates over
     the sum of the children's own times.  Falls back to one thread in this
     process (stopping after about budget_s seconds) if a child fails."""
@@ -238,9 +256,10 @@ def cpu_baseline(spec, budget_s: float, workers: int = 16, n_inner: int = 2, n_o
 
     O.build()
     levels = _sample_levels(spec, n_inner, n_outer)
+    probes = list(spec.probes)[:max_probes] if max_probes else list(spec.probes)
     jobs = [{"ns": list(e.ns), "nt": e.nt, "beta": e.beta, "seed": e.seed, "key_id": e.key_id, "levels": levels,
-             "r": list(spec.r), "dirs": list(spec.dirs), "probes": [list(p) for p in spec.probes],
-             "comps": list(spec.comps), "n_or": spec.n_or} for e in spec.ensembles]
+             "r": list(spec.r), "dirs": list(spec.dirs), "probes": [list(p) for p in probes],
+             "comps": list(spec.comps), "n_or": spec.n_or, "min_seconds": min_seconds} for e in spec.ensembles]
     workers = max(1, min(workers, len(jobs), os.cpu_count() or 1))
     results, running = [], []
     # largest ensembles first, a new child as soon as one ends
@@ -264,11 +283,14 @@ def cpu_baseline(spec, budget_s: float, workers: int = 16, n_inner: int = 2, n_o
         wall = time.perf_counter() - t0
         upd = sum(r["updates"] for r in results)
         cpu_s = sum(r["seconds"] for r in results)
+        n_cfg = sum(r["configurations"] for r in results)
         return {"value": upd / wall, "unit": "link updates/s", "cores": workers, "kind": "oracle",
                 "cpu": cpu_model(), "host_cpus": os.cpu_count(),
-                "sample": f"{len(jobs)} of {len(jobs)} ensembles, one multilevel configuration each with levels "
-                          f"{levels} (tau, n_iter, k_sweeps), FP64, one ensemble per process, up to {workers} "
-                          f"at a time; {cpu_s:.1f} s of oracle time in {wall:.1f} s",
+                "sample": f"{len(jobs)} of {len(jobs)} ensembles, multilevel configurations with levels "
+                          f"{levels} (tau, n_iter, k_sweeps), {len(probes)} of {len(spec.probes)} probes, FP64, "
+                          f"one ensemble per process, up to {workers} at a time, each repeating configurations "
+                          f"for at least {min_seconds:g} s ({n_cfg} in all); {cpu_s:.1f} s of oracle time in "
+                          f"{wall:.1f} s",
                 "single_thread": {"value": upd / cpu_s, "cores": 1}}
     except Exception as exc:  # noqa: BLE001 -- the baseline must not cost the bench line
         for pr in running:
@@ -431,11 +453,8 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path; "
               "how a batch or one lattice would shard across GPUs is described in the design notes", file=sys.stderr)
         sys.exit(2)
-    import torch
-
     from paper_1309_3859_amd import configs, u1ml
 
-    assert torch.cuda.is_available(), "bench.py needs the GPU"
     preset = configs.PRESETS[args.workload]
 
     if args.n_ens and "n_ens" not in inspect.signature(preset).parameters:
@@ -449,20 +468,34 @@ def main():
         if args.n_outer and len(lv) == 2:
             lv[0][1] = args.n_outer
         spec.levels = [tuple(x) for x in lv]
+        if args.precision != "workload":
+            spec.precision = u1ml.FP32 if args.precision == "f32" else u1ml.FP64
         return spec, sched
 
     spec, sched = make()
+    if args.cpu_only:
+        print(json.dumps({"workload": preset.__name__, "updates_per_config": u1ml.plan(spec)["updates_per_config"],
+                          "cpu_baseline": cpu_baseline(spec, args.cpu_seconds, n_inner=args.cpu_n_inner,
+                                                       n_outer=args.cpu_n_outer, max_probes=args.cpu_max_probes)}),
+              flush=True)
+        return
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.counters:
         run_counter_workload(spec, sched)
         return
     spec.max_configs = max(1, args.steps + args.warmup)
     ctx = u1ml.Context(spec)
     ctx.init_links(sched["start"])
+    # the autotuner's sweep timings for every work-group size (it restores
+    # links and counters), reported beside the size the line runs with
+    tune = ctx.autotune()
     if args.block:
         ctx.set_block(args.block)
         block = args.block
     else:
-        block = ctx.autotune()["chosen_block"]
+        block = tune["chosen_block"]
     ctx.sweeps(20)
     upd = ctx.plan["updates_per_config"]
     ms = time_steps(ctx, args.steps, args.warmup)
@@ -505,12 +538,16 @@ def main():
         "config": {"workload": preset.__name__, "ensembles": len(spec.ensembles),
                    "lattices": sorted({f"{e.ns[0]}^3x{e.nt}" for e in spec.ensembles}),
                    "levels": spec.levels, "n_or": spec.n_or, "updates_per_step": upd,
-                   "block": block},
+                   "block": block,
+                   "autotune": {"us_per_sweep": dict(zip(map(str, tune["block"]), tune["us_per_sweep"])),
+                                "chosen_block": tune["chosen_block"],
+                                "note": "work-group size only; the update kernels have no other tile dimension"}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counter_traffic() if args.workload == "c4" else None,
-                     "kernel": "k_update<float,1,0> (overrelaxation, mu = x, inner slabs), one launch per lane "
-                               "as the step launches it; averages over the lanes",
+                     "kernel": f"k_update<{'float' if spec.precision == u1ml.FP32 else 'double'},1,0> "
+                               "(overrelaxation, mu = x, inner slabs), one launch per lane as the step launches it; "
+                               "averages over the lanes",
                      "bytes_per_launch": b, "updates_per_launch": u, "us_per_launch": us, "lanes": lanes,
                      "whole_batch_launch": {"us_per_launch": wus, "bytes_per_launch": wb, "updates_per_launch": wu,
                                             "frac": wb / (wus * 1e-6) / 1e9 / HBM_PEAK_GBS}},
@@ -541,13 +578,14 @@ def main():
         ctx64.set_block(block)
         ctx64.sweeps(5)
         ms64 = time_steps(ctx64, args.steps, args.warmup)
+        ph64 = {f"{('HB', 'OR')[k]}_mu{m}": ctx64.time_phase(k, m, 0, tau, 50) for k, m in [(1, 0), (0, 0), (1, 3), (0, 3)]}
         line["plain_fp64"] = {"value": upd * args.steps / (ms64 / 1e3), "unit": "link updates/s",
-                              "ms_per_step": ms64 / args.steps, "dtype": "f64",
+                              "ms_per_step": ms64 / args.steps, "dtype": "f64", "phases_us": ph64,
                               "accuracy_of_f32": measurement_accuracy(ctx64, spec)}
     if not args.no_cpu_baseline:
         progress("FP64 leg done; timing the oracle on the host")
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds, n_inner=args.cpu_n_inner,
-                                            n_outer=args.cpu_n_outer)
+                                            n_outer=args.cpu_n_outer, max_probes=args.cpu_max_probes)
     print(json.dumps(line), flush=True)
 
 

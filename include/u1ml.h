@@ -137,7 +137,11 @@ typedef struct {
  *   dirs:   charge axes (0, 1, 2) summed over in the estimators (Sec. II.C.3).
  *   max_configs: capacity of the device results ring (configurations).
  *   form:   U1ML_FORM_* (SPECTRAL needs every transverse plane of a charge
- *           axis to fit 64 KiB of complex doubles, i.e. at most 4096 sites). */
+ *           axis to fit 64 KiB of complex doubles, i.e. at most 4096 sites;
+ *           AUTO takes the form with the smaller estimated device time,
+ *           u1ml_plan_info.est_history_ms / est_spectral_ms, from unit costs
+ *           measured on MI355X, and the spectral form whenever the history
+ *           form's per-site averages would exceed 64 GiB). */
 typedef struct {
     int n_ens;
     const u1ml_ensemble* ens;
@@ -196,6 +200,11 @@ typedef struct {
                                  replay copy of the links (SPECTRAL only)    */
     long launches_per_config; /* kernel launches of one u1ml_multilevel
                                  (upper bound)                              */
+    double est_history_ms;    /* estimated device time per configuration that
+                                 the insertion contraction adds in the history
+                                 form (0 without probes)                    */
+    double est_spectral_ms;   /* the same for the spectral form (-1 where it
+                                 does not apply); AUTO takes the smaller     */
 } u1ml_plan_info;
 
 typedef struct u1ml_ctx u1ml_ctx;
@@ -226,11 +235,13 @@ u1ml_status u1ml_init_links(u1ml_ctx* ctx, int start);
  * ensemble (Sec. II). */
 u1ml_status u1ml_sweeps(u1ml_ctx* ctx, int n);
 
-/* Async.  One checkerboard phase: the links of direction mu and the given
- * parity that are not frozen at slab thickness tau (tau <= 1: none frozen),
- * updated with kind U1ML_HEATBATH, U1ML_OVERRELAX or U1ML_METROPOLIS (step
- * metro_delta of the problem), using the stochastic pass counter (device
- * counter + pass_offset).  Does not advance the counter. */
+/* Async.  One checkerboard phase (the even-then-odd update of Sec. II.D; the
+ * local updates of Sec. II; the frozen boundary links of Sec. II.C.1 and
+ * Algorithm 1): the links of direction mu and the given parity that are not
+ * frozen at slab thickness tau (tau <= 1: none frozen), updated with kind
+ * U1ML_HEATBATH, U1ML_OVERRELAX or U1ML_METROPOLIS (step metro_delta of the
+ * problem), using the stochastic pass counter (device counter + pass_offset).
+ * Does not advance the counter. */
 u1ml_status u1ml_phase(u1ml_ctx* ctx, int kind, int mu, int parity, int tau, int pass_offset);
 
 /* Async.  One multilevel configuration: the body of Algorithm 1 with the
@@ -252,8 +263,10 @@ u1ml_status u1ml_set_links(u1ml_ctx* ctx, int ens, const double* host, size_t n)
 u1ml_status u1ml_get_counter(u1ml_ctx* ctx, int ens, uint32_t* counter);
 u1ml_status u1ml_set_counter(u1ml_ctx* ctx, int ens, uint32_t counter);
 
-/* Synchronises.  Mean cos(theta_P) per ensemble and absolute orientation
- * (E_x, E_y, E_z, B_x, B_y, B_z): out[ens * 6 + o]. */
+/* Synchronises.  Mean plaquette cos(theta_P) of the Wilson action (Sec. II;
+ * the orientations of the field components of Sec. II.C.3) per ensemble and
+ * absolute orientation (E_x, E_y, E_z from P_{i t}; B_x, B_y, B_z from P_{yz},
+ * P_{zx}, P_{xy}): out[ens * 6 + o]. */
 u1ml_status u1ml_plaquette(u1ml_ctx* ctx, double* out);
 
 /* For callers that cannot allocate device memory or synchronise (code under

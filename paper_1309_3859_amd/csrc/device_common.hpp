@@ -215,27 +215,44 @@ __device__ inline double bf_r_f64(double kappa)
     return m::div_(1.0 + rho * rho, 2.0 * rho);
 }
 
+// Both attempts are evaluated by every lane, so a wave runs each step once
+// whichever attempt its lanes accept, and arccos once, for the accepted one.
+// The logarithmic test is decided on t = ln(c / U2) + 1 - c formed in FP32
+// (hardware base-2 logarithm): with 1/2 <= c < 64 and U2 >= 2^-33,
+// |ln(c / U2)| < 28 and the FP32 value is within 1e-5 of the exact one; where
+// |t| < 2^-10, or c >= 64 (kappa above 31), the test is taken again in FP64
+// exactly as the definition writes it.  Every decision is the FP64 test's.
 __device__ inline int bf_pair_f64(double kappa, double r, const Block4& b, double* psi)
 {
     using m = M<double>;
+    double f[2], c[2], u2[2];
+    bool acc[2], band[2];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         const uint32_t a = half ? b.w[2] : b.w[0];
         const uint32_t bb = half ? b.w[3] : b.w[1];
         const double z = m::cos_pi(m::u1(a));
-        double f = m::div_(1.0 + r * z, r + z);
-        f = f > 1.0 ? 1.0 : (f < -1.0 ? -1.0 : f);
-        const double c = kappa * (r - f);
-        const double u2 = m::u2(bb);
-        bool acc = (c * (2.0 - c) - u2 > 0.0);
-        if (!acc) acc = (m::log_(m::div_(c, u2)) + 1.0 - c >= 0.0);
-        if (acc) {
-            const double p = m::acos_(f);
-            *psi = (a & 1u) ? -p : p;
-            return half + 1;
-        }
+        double fh = m::div_(1.0 + r * z, r + z);
+        fh = fh > 1.0 ? 1.0 : (fh < -1.0 ? -1.0 : fh);
+        f[half] = fh;
+        c[half] = kappa * (r - fh);
+        u2[half] = m::u2(bb);
+        const bool quick = c[half] * (2.0 - c[half]) - u2[half] > 0.0;
+        const float t = fmaf(__builtin_amdgcn_logf((float)c[half] * __builtin_amdgcn_rcpf((float)u2[half])),
+                             0.693147181f, (float)(1.0 - c[half]));
+        acc[half] = quick || t >= 0.0f;
+        band[half] = !quick && (fabsf(t) < 0.0009765625f || c[half] >= 64.0);
     }
-    return 0;
+    if (band[0] || band[1]) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half)
+            if (band[half]) acc[half] = m::log_(m::div_(c[half], u2[half])) + 1.0 - c[half] >= 0.0;
+    }
+    if (!acc[0] && !acc[1]) return 0;
+    const int k = acc[0] ? 1 : 2;
+    const double p = m::acos_(acc[0] ? f[0] : f[1]);
+    *psi = ((acc[0] ? b.w[0] : b.w[2]) & 1u) ? -p : p;
+    return k;
 }
 
 template <>

@@ -83,6 +83,7 @@ struct Problem {
     int tau_i = 2, n_i = 1, k_i = 1, tau_o = 2, n_o = 1, k_o = 0;
     bool two = false;
     bool spectral = false;        // insertion contraction in the spectral form
+    double est_hist_ms = 0.0, est_spec_ms = -1.0;  // the planner's cost estimates of the two forms
     std::vector<int> pgroup;      // probe -> group of probes sharing (l, mode)
     std::vector<int> gdesc;       // group -> (l, mode)
     std::vector<int> pblk;        // insertion contraction: probe blocks, kInsBlkInts ints each
@@ -266,22 +267,50 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     const size_t R = P.r.size(), Np = P.probes.size(), Nc = P.comps.size(), nd = (size_t)P.n_dirs;
     const size_t NG = P.gdesc.size() / 2;
     // contraction form: the spectral form needs every transverse plane of a
-    // charge axis within 4096 sites; AUTO takes it when the per-site
-    // averages of the history form would exceed 16 GiB
+    // charge axis within 4096 sites.  AUTO estimates the device time each
+    // form adds to a configuration and takes the smaller (history also when
+    // the spectral form does not apply, spectral when the history form's
+    // per-site averages would exceed 64 GiB); the unit costs are MI355X
+    // measurements (FP32 links):
+    //   history:  contraction 5.6e12 FMA/s (the inner level's [TO] sums);
+    //             two levels: the inner averages folded into the outer sums,
+    //             3 passes over them per outer update at 3 TB/s;
+    //   spectral: per measurement 20 us of launches, 14.2 ps per plane
+    //             element and field (staging and transforms), 0.198 ps per
+    //             flop of the spectral sums; two levels: the replay repeats
+    //             every update (5e10 link updates/s).
+    // Measured per configuration (history / spectral, ms): 24^3x8, 9 probes,
+    // 100 updates 13.6 / 18.1; 24^3x8 in-plane map 18.1 / 19.4; 48^3x12 two
+    // levels 2 x 10, 1 probe 15.9 / 21.5, 8 probes 53.3 / 21.4.
     {
         bool plane_ok = true;
-        double hist_avg = 0.0;
+        double hist_avg = 0.0, est_h = 0.0, est_s = 0.0;
+        const double n_meas = (double)P.n_i * P.k_i * (P.two ? P.n_o : 1);
         for (const u1ml_ensemble& E : P.ens) {
             const double nsig = (double)E.ns[0] * E.ns[1] * E.ns[2];
             for (int i = 0; i < P.n_dirs; ++i)
                 if (nsig / E.ns[P.dirs[i]] > 4096.0) plane_ok = false;
             const double per = (double)nd * R * Np * Nc * 2 * nsig * 16.0;
-            hist_avg += per * (E.nt / P.tau_i) + (P.two ? per * (E.nt / P.tau_o) : 0.0);
+            const double si = (double)(E.nt / P.tau_i);
+            hist_avg += per * si + (P.two ? per * (E.nt / P.tau_o) : 0.0);
+            est_h += n_meas * nd * si * nsig * R * Np * Nc * 4.0 / 5.6e12;
+            if (P.two) est_h += (double)P.n_o * per * si * 3.0 / 3.0e12;
+            est_s += n_meas * (20e-6 + nd * si * nsig * (R + 12) * 14.2e-12 + nd * si * (double)NG * nsig * R * Nc * 16.0 * 0.198e-12);
+            if (P.two) {
+                const double V = nsig * E.nt, vh = V / 2;
+                const double sp_i = vh / E.nt * (E.nt - E.nt / P.tau_i), sp_o = vh / E.nt * (E.nt - E.nt / P.tau_o);
+                const double upd = (double)P.n_o * ((double)P.k_o * (1 + P.n_or) * 2 * (vh + 3 * sp_o) +
+                                                    (double)P.n_i * P.k_i * (1 + P.n_or) * 2 * (vh + 3 * sp_i));
+                est_s += upd / 5e10;
+            }
         }
+        P.est_hist_ms = Np ? est_h * 1e3 : 0.0;
+        P.est_spec_ms = (Np && plane_ok) ? est_s * 1e3 : -1.0;
         if (P.form_req == U1ML_FORM_SPECTRAL) {
             P.spectral = !P.probes.empty();  // planes checked by read_problem
         } else if (P.form_req == U1ML_FORM_AUTO) {
-            P.spectral = !P.probes.empty() && plane_ok && hist_avg > 16.0 * 1024 * 1024 * 1024;
+            P.spectral = !P.probes.empty() && plane_ok &&
+                         (est_s < est_h || hist_avg > 64.0 * 1024 * 1024 * 1024);
         } else {
             P.spectral = false;
         }
@@ -489,6 +518,8 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
         info->spectral_bytes = Lo->sz_wf + Lo->sz_gf + Lo->sz_sph + Lo->sz_spo + Lo->sz_facc + Lo->sz_saved +
                                Lo->sz_cpl + Lo->sz_opl;
         info->launches_per_config = (long)body_launches(P);
+        info->est_history_ms = P.est_hist_ms;
+        info->est_spectral_ms = P.est_spec_ms;
     }
     return true;
 }

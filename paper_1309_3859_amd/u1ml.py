@@ -62,7 +62,8 @@ class _PlanInfo(C.Structure):
         ("average_bytes", C.c_size_t), ("outer_bytes", C.c_size_t), ("result_bytes", C.c_size_t),
         ("scratch_bytes", C.c_size_t), ("paper_running_bytes", C.c_size_t), ("n_doubles_per_config", C.c_long),
         ("updates_per_config", C.c_long), ("updates_per_sweep", C.c_long), ("form", C.c_int),
-        ("spectral_bytes", C.c_size_t), ("launches_per_config", C.c_long),
+        ("spectral_bytes", C.c_size_t), ("launches_per_config", C.c_long), ("est_history_ms", C.c_double),
+        ("est_spectral_ms", C.c_double),
     ]
 
 

@@ -161,6 +161,38 @@ def test_contraction_form_selection(u1):
     assert u1.plan(s2)["form"] == u1.FORM_SPECTRAL
 
 
+def test_contraction_form_follows_the_cost_estimates(u1):
+    """AUTO takes the form with the smaller estimated device time.  The
+    estimates order the forms as measured on MI355X (ms per configuration,
+    history / spectral): 24^3x8 with 9 probes 13.6 / 18.1, the in-plane map
+    18.1 / 19.4, 48^3x12 at 2 x 10 updates with 1 probe 15.9 / 21.5 and with
+    8 probes 53.3 / 21.4; without probes there is nothing to estimate."""
+    from paper_1309_3859_amd import configs
+
+    cases = []
+    s, _ = configs.c2_fp32_profiles()
+    cases.append((s, u1.FORM_HISTORY))
+    s, _ = configs.in_plane_map()
+    cases.append((s, u1.FORM_HISTORY))
+    s, _ = configs.c5_largest(n_outer=2, n_inner=10, full_map=False)
+    cases.append((s, u1.FORM_HISTORY))
+    s, _ = configs.c5_largest(n_outer=2, n_inner=10)
+    s.probes = s.probes[:8]
+    cases.append((s, u1.FORM_SPECTRAL))
+    for spec, want in cases:
+        p = u1.plan(spec)
+        assert p["est_history_ms"] > 0 and p["est_spectral_ms"] > 0
+        assert p["form"] == want, (p["est_history_ms"], p["est_spectral_ms"])
+        assert (p["est_spectral_ms"] < p["est_history_ms"]) == (want == u1.FORM_SPECTRAL)
+    p4 = u1.plan(configs.c4_batched()[0])
+    assert p4["est_history_ms"] == 0 and p4["est_spectral_ms"] == -1
+    # a plane of more than 4096 sites leaves the history form whatever it costs
+    spec = u1.Spec(ensembles=[u1.Ens((2, 66, 66), 4, 1.0)], levels=[(2, 10, 1)], r=[1], probes=[(0, 0, 0, 1)],
+                   comps=[0], precision=u1.FP32)
+    p = u1.plan(spec)
+    assert p["form"] == u1.FORM_HISTORY and p["est_spectral_ms"] == -1
+
+
 def test_large_bodies_are_launched_directly(u1):
     """Multilevel bodies above 8192 kernel launches are not captured into a
     single graph (the planner reports the launch count); the headline batch
