@@ -162,6 +162,8 @@ def parse():
                     help="outer-level updates of the oracle's sampled configuration (0: the workload's own)")
     ap.add_argument("--cpu-max-probes", type=int, default=0,
                     help="insertion probes of the oracle's sampled configuration (0: all of the workload's)")
+    ap.add_argument("--cpu-timeout", type=float, default=600.0,
+                    help="seconds the oracle's child processes may run before the single-thread fallback")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
     ap.add_argument("--precision", choices=("workload", "f32", "f64"), default="workload",
                     help="link storage and update arithmetic of the timed line (default: the workload's own); "
@@ -240,7 +242,7 @@ def cpu_model() -> str:
 
 
 def cpu_baseline(spec, budget_s: float, workers: int = 16, n_inner: int = 2, n_outer: int = 1, max_probes: int = 0,
-                 min_seconds: float = 2.0):
+                 min_seconds: float = 2.0, timeout_s: float = 600.0):
     """Time the FP64 oracle on the host cores on a bounded sample of the
     workload: every ensemble of the batch (independent, as on the GPU), one
     multilevel configuration each with the update counts cut down (repeated
@@ -278,8 +280,8 @@ def cpu_baseline(spec, budget_s: float, workers: int = 16, n_inner: int = 2, n_o
                 if pr.returncode != 0:
                     raise RuntimeError(f"oracle child exited with {pr.returncode}")
                 results.append(json.loads(out.strip().splitlines()[-1]))
-            if time.perf_counter() - t0 > 600:
-                raise TimeoutError("oracle children still running after 600 s")
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"oracle children still running after {timeout_s:g} s")
         wall = time.perf_counter() - t0
         upd = sum(r["updates"] for r in results)
         cpu_s = sum(r["seconds"] for r in results)
@@ -476,7 +478,8 @@ def main():
     if args.cpu_only:
         print(json.dumps({"workload": preset.__name__, "updates_per_config": u1ml.plan(spec)["updates_per_config"],
                           "cpu_baseline": cpu_baseline(spec, args.cpu_seconds, n_inner=args.cpu_n_inner,
-                                                       n_outer=args.cpu_n_outer, max_probes=args.cpu_max_probes)}),
+                                                       n_outer=args.cpu_n_outer, max_probes=args.cpu_max_probes,
+                                                       timeout_s=args.cpu_timeout)}),
               flush=True)
         return
     import torch
@@ -585,7 +588,8 @@ def main():
     if not args.no_cpu_baseline:
         progress("FP64 leg done; timing the oracle on the host")
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds, n_inner=args.cpu_n_inner,
-                                            n_outer=args.cpu_n_outer, max_probes=args.cpu_max_probes)
+                                            n_outer=args.cpu_n_outer, max_probes=args.cpu_max_probes,
+                                            timeout_s=args.cpu_timeout)
     print(json.dumps(line), flush=True)
 
 

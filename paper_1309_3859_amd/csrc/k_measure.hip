@@ -20,6 +20,8 @@
 // average in registers and writes it once.  Products over slabs are carried
 // as (mantissa, binary exponent) pairs so they cannot underflow, and all sums
 // over sites are double-double in a fixed order, so results are reproducible.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "scaled.hpp"
 #include "u1ml_internal.hpp"
@@ -414,62 +416,107 @@ __global__ void __launch_bounds__(512) k_contract(const EnsDesc* __restrict__ en
 }
 
 // ---------------------------------------------------------------------------
-// Insertion averages of the inner level (history form), for charge axis mu,
-// slab s and frame component c:
+// Insertion averages of the inner level (history form), for charge axis mu and
+// slab s:
 //   [TO](s, x, r, p, c, k) = 1/n sum_m T_m(s, x, r) O_m(x + sh(r, p, c) + p_perp, o(c), k),
 //   T_m(x, r) = conj(c_m(x)) c_m(x + r mu),
 // sh = l + (mode ? floor((r-1)/2) or floor(r/2) : 0) (the probe's offset along
-// the axis, the mid-plane term depending on whether the plaquette spans mu).
-// For one probe block (probes sharing l and mode) the O value at position y
-// of a displaced line pairs with T(y - sh(r), r) for every r, and each T value
-// with every probe of the block; so work-item (y, r-block, probe block) keeps
-// kInsR x kInsP x 4 accumulators and reads kInsR T values and kInsP O pairs
-// per measurement from LDS (2.3 bytes per FMA), where a work-item per (x, r)
-// reads two phases and an O pair per FMA pair.  Work-group: one line of the
-// axis, one slab, one component, ins_pbw probe blocks; per chunk of ins_mc
-// measurements it stages the line's phases, forms T for every (r, x), and
-// stages the displaced lines' O pairs of its probes.  Sums over measurements
-// run in order m = 0, 1, ... for every output.
-// Launch: grid (work-groups of the ensembles' lines x probe chunks, slab,
-// axis x component), kInsThreads work-items.
+// the axis, the mid-plane term depending on whether the component's plaquette
+// spans mu).  The (probe, component) slots with the same (l, mode, spans) meet
+// every T value at the same offset, so they are grouped in blocks of KS
+// slots: the O pair at position y of a slot's displaced line pairs with
+// T(y - sh(r), r) for every r, and work-item (y, r-block, slot block) keeps
+// KR x KS x 4 accumulators.  Per measurement it forms its KR values of T from
+// two staged phases each (no separate T pass) and reads one O pair per slot
+// from LDS, converting it to FP64 there.  Work-group: one line of the axis,
+// one slab, ins_pbw slot blocks; per chunk of ins_mc measurements it stages
+// the line's phases and the O rows of its slots (16-byte loads where the line
+// is contiguous in memory).  Sums over measurements run in order m = 0, 1, ...
+// for every output.
+// Launch: grid (work-groups of the ensembles' lines x slot-block chunks, slab,
+// axis), up to kInsThreads work-items.
 // ---------------------------------------------------------------------------
-template <typename ot>
-__global__ void __launch_bounds__(kInsThreads, 3) k_contract_ins(
-    const EnsDesc* __restrict__ ens, const int* __restrict__ bstart, int n_ens, const ObsDesc* __restrict__ obs,
-    const int* __restrict__ rlist, const int* __restrict__ comps, const int* __restrict__ pblk,
-    const double2* __restrict__ hist_c, const ot* __restrict__ hist_o, double2* __restrict__ avg_to, int n_meas)
+template <typename ot, int V>
+__device__ inline void stage_o_rows(ot* __restrict__ ol, const ot* __restrict__ ho, const int* __restrict__ rowoff,
+                                    int mm, int nrows, int N, int stride, size_t mstride_o, int m0)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int e = find_ens_m(bstart, n_ens, blockIdx.x);
+    // vectors of V elements along y: ((q nrows + row) nv + v), walked with a carry
+    const int nv = N / V, per_q = nrows * nv, total = mm * per_q;
+    const int B = blockDim.x;
+    const int dq = B / per_q, drem = B - dq * per_q;
+    int f = threadIdx.x;
+    int q = f / per_q, rem = f - q * per_q;
+    constexpr int U = 4;  // vectors per work-item and round, all loads before any store
+    using vec = typename std::conditional<V == 1, ot, typename std::conditional<sizeof(ot) == 4, float4, double2>::type>::type;
+    while (f < total) {
+        vec v[U];
+        int dst[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dst[u] = -1;
+            if (f < total) {
+                const int row = rem / nv, iv = rem - row * nv;
+                const int off = rowoff[row];
+                const size_t ob = (size_t)(m0 + q) * mstride_o + (size_t)off;
+                if constexpr (V == 1) {
+                    v[u] = off >= 0 ? ho[ob + (size_t)iv * stride] : ot(0);
+                } else {
+                    v[u] = off >= 0 ? *reinterpret_cast<const vec*>(ho + ob + (size_t)iv * V) : vec{};
+                }
+                dst[u] = (q * nrows + row) * N + iv * V;
+            }
+            f += B;
+            q += dq;
+            rem += drem;
+            if (rem >= per_q) {
+                rem -= per_q;
+                ++q;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (dst[u] >= 0) *reinterpret_cast<vec*>(ol + dst[u]) = v[u];
+    }
+}
+
+template <typename ot, int KR, int KS>
+__global__ void __launch_bounds__(kInsThreads, 2) k_contract_ins(
+    const EnsDesc* __restrict__ ens, const int* __restrict__ bstart, int n_ens, const ObsDesc* __restrict__ obs,
+    const int* __restrict__ rlist, const int* __restrict__ comps, const int* __restrict__ sblk,
+    const double2* __restrict__ hist_c, const ot* __restrict__ hist_o, double2* __restrict__ avg_to, int n_meas,
+    int n_blocks)
+{
+    // two chunk buffers as separate LDS objects, so that the compiler can tell
+    // the copies into one from the reads of the other (no wait between them)
+    __shared__ double2 lph0[kInsPh], lph1[kInsPh];                            // phases [q][x]
+    __shared__ __align__(16) unsigned char lo0[kInsOb], lo1[kInsOb];          // O rows [q][row][y]
+    __shared__ int rowoff[kInsRowsMax];  // each O row's element offset within one (measurement, slab) block, -1: empty slot
+    // XCD-aware order: the hardware deals consecutive work-groups to the eight
+    // XCDs in turn, so work-group b takes logical block (b mod 8) G/8 + b/8
+    // (G, a multiple of 8, launched); each XCD then sums a contiguous run of
+    // lines, whose displaced O lines overlap, from its own L2
+    const int bid = (int)(blockIdx.x & 7u) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3);
+    if (bid >= n_blocks) return;  // uniform: padding of the launch to a multiple of 8
+    const int e = find_ens_m(bstart, n_ens, bid);
     const EnsDesc& E = ens[e];
     const ObsDesc& O = *obs;
     const int S = E.s_in, s = blockIdx.y;
     if (s >= S) return;  // uniform for the block
-    const int nc = O.n_comp;
-    const int id = blockIdx.z / nc, ic = blockIdx.z - id * nc;
-    const int dir = O.dirs[id], comp = comps[ic];
+    const int id = blockIdx.z;
+    const int dir = O.dirs[id];
     const int n3[3] = {E.nx, E.ny, E.nz};
     const int N = n3[dir];
     const int d1 = dir == 2 ? 0 : dir + 1, d2 = dir == 0 ? 2 : dir - 1;  // (dir + 1) % 3, (dir + 2) % 3
     const int nsig = E.nsig, nlines = nsig / N;
-    const int nr = O.n_r, nrb = (nr + kInsR - 1) / kInsR;
-    const int npb = O.n_pblocks, pbw = E.ins_pbw, nchunk = (npb + pbw - 1) / pbw;
-    const int local = blockIdx.x - bstart[e];
+    const int nr = O.n_r, nrb = (nr + KR - 1) / KR;
+    const int nsb = O.n_pblocks, bpw = E.ins_pbw, nchunk = (nsb + bpw - 1) / bpw;
+    const int local = bid - bstart[e];
     const int line = local / nchunk, chunk = local - line * nchunk;
     if (line >= nlines) return;  // uniform: this axis has fewer lines than the ensemble's largest
-    const int pb0 = chunk * pbw, npbw = min(pbw, npb - pb0);
-    const int nslot = npbw * kInsP;
+    const int sb0 = chunk * bpw, nbw = min(bpw, nsb - sb0);
+    const int nrows = nbw * KS * 2;  // O rows of one measurement: (slot block, slot, kind)
     const int mc = E.ins_mc;
-    const int orient = comp_orient(comp, dir);
-    const bool spans = comp_spans_axis(comp);
 
-    // LDS: phases cl[q][k]; T[q][ir][x]; O pairs ol[q][slot][y]; then the
-    // element offset of each slot's displaced line and the separations
-    double2* cl = reinterpret_cast<double2*>(lds_raw);
-    double2* tl = cl + (size_t)mc * N;
-    double2* ol = tl + (size_t)mc * nr * N;
-    int* obase = reinterpret_cast<int*>(ol + (size_t)mc * nslot * N);
-    int* rv = obase + nslot;
 
     const int a1 = line % n3[d1], a2 = line / n3[d1];
     const int stride = dir == 0 ? 1 : (dir == 1 ? E.nx : E.nx * E.ny);
@@ -484,151 +531,182 @@ __global__ void __launch_bounds__(kInsThreads, 3) k_contract_ins(
     const size_t mstride = (size_t)S * nsig;
     const size_t mstride_o = (size_t)S * 12 * nsig;
     const double2* hc = hist_c + E.hc_off + (size_t)s * nsig + base;
-    const ot* ho = hist_o + E.ho_off + (size_t)s * 12 * nsig + (size_t)(2 * orient) * nsig;
+    const ot* ho = hist_o + E.ho_off + (size_t)s * 12 * nsig;
     const double inv = 1.0 / (double)n_meas;
     const int tid = threadIdx.x;
-    const int ntask = N * nrb * npbw;
-    for (int j = tid; j < nslot; j += blockDim.x) {
-        const int* B = pblk + kInsBlkInts * (pb0 + j / kInsP);
-        const int pi = j - (j / kInsP) * kInsP;
-        obase[j] = pi < B[2] ? site0(B[8 + 2 * pi], B[9 + 2 * pi]) : -1;  // -1: empty slot
+    for (int j = tid; j < nrows; j += blockDim.x) {
+        const int bl = j / (2 * KS), rem = j - bl * 2 * KS, k = rem >> 1, kind = rem & 1;
+        const int* B = sblk + kInsBlkInts * (sb0 + bl);
+        int off = -1;
+        if (k < B[3]) {
+            const int* sl = B + 4 + 4 * k;  // probe, component index, p1, p2
+            off = (2 * comp_orient(comps[sl[1]], dir) + kind) * nsig + site0(sl[2], sl[3]);
+        }
+        rowoff[j] = off;
     }
-    for (int j = tid; j < nr; j += blockDim.x) rv[j] = rlist[j];
-    // staging walks a [rows][N] array: this work-item's first element and the
-    // step of blockDim elements as (rows, columns) with a carry, no division
-    const int k0 = tid % N, row0 = tid / N, drow = (int)blockDim.x / N, dk = (int)blockDim.x - drow * N;
-    // the O pairs of a chunk, [q][slot][k]: the first element's (q, slot)
-    const int oq0 = row0 / nslot, os0 = row0 - oq0 * nslot;
-    auto for_rows = [&](int nrows, auto&& f) {
-        int row = row0, k = k0;
-        while (row < nrows) {
-            f(row, k);
-            row += drow;
-            k += dk;
-            if (k >= N) {
-                k -= N;
+    // A line contiguous in memory (the x axis) with N a multiple of the
+    // 16-byte vector: every row offset is then a multiple of the vector
+    // (a line starts at a multiple of Nx, rows at multiples of nsig), and
+    // each wave copies 64 vectors of a chunk straight from memory into LDS
+    // (global_load_lds), so the next chunk streams in while this one is
+    // summed.  Otherwise the chunk is staged through registers.
+    constexpr int VW = 16 / (int)sizeof(ot);
+    const bool dma = stride == 1 && N % VW == 0 && (reinterpret_cast<uintptr_t>(ho) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(hc) & 15) == 0;
+    const int nv = N / VW, per_q = nrows * nv;
+    const int lane = tid & 63, wv = tid >> 6, nw = ((int)blockDim.x + 63) >> 6;
+    // this lane's first O vector of a chunk and the step between its spans, as (q, row, iv)
+    const int ostep = nw * 64;
+    const int odq = ostep / per_q, odrem = ostep - odq * per_q;
+    const int odrow = odrem / nv, odiv = odrem - odrow * nv;
+    const int ou0 = wv * 64 + lane, oq0 = ou0 / per_q, orem0 = ou0 - oq0 * per_q;
+    const int orow0 = orem0 / nv, oiv0 = orem0 - orow0 * nv;
+    auto issue = [&](int m0, int mm, double2* php, unsigned char* op) {
+        // phases: vector v = q N + x
+        for (int j = wv; j * 64 < mm * N; j += nw) {
+            const int v = j * 64 + lane;
+            if (v < mm * N) {
+                const int q = v / N, x = v - q * N;
+                __builtin_amdgcn_global_load_lds((const void*)(hc + (size_t)(m0 + q) * mstride + x),
+                                                 (__attribute__((address_space(3))) void*)(php + j * 64), 16, 0, 0);
+            }
+        }
+        // O rows: vector u = (q nrows + row) nv + iv
+        int q = oq0, row = orow0, iv = oiv0;
+        for (int j = wv; j * 64 < mm * per_q; j += nw) {
+            if (q < mm) {
+                const int off = rowoff[row];
+                if (off >= 0)
+                    __builtin_amdgcn_global_load_lds((const void*)(ho + (size_t)(m0 + q) * mstride_o + off + iv * VW),
+                                                     (__attribute__((address_space(3))) void*)(op + (size_t)j * 1024),
+                                                     16, 0, 0);
+            }
+            q += odq;
+            iv += odiv;
+            if (iv >= nv) {
+                iv -= nv;
                 ++row;
+            }
+            row += odrow;
+            if (row >= nrows) {
+                row -= nrows;
+                ++q;
             }
         }
     };
+    // phases of a chunk through registers, [q][x]: this work-item's first element and its step
+    const int k0 = tid % N, q0 = tid / N, dqp = (int)blockDim.x / N, dkp = (int)blockDim.x - dqp * N;
+    auto stage = [&](int m0, int mm, double2* ph, unsigned char* op) {
+        int q = q0, k = k0;
+        while (q < mm) {
+            ph[q * N + k] = hc[(size_t)(m0 + q) * mstride + (size_t)k * stride];
+            q += dqp;
+            k += dkp;
+            if (k >= N) {
+                k -= N;
+                ++q;
+            }
+        }
+        stage_o_rows<ot, 1>(reinterpret_cast<ot*>(op), ho, rowoff, mm, nrows, N, stride, mstride_o, m0);
+    };
 
+    const int ntask = nbw * nrb * N;
+    const int nch = (n_meas + mc - 1) / mc;
     for (int t0 = 0; t0 < ntask; t0 += blockDim.x) {
         const int task = t0 + tid;
         const bool act = task < ntask;
         const int y = act ? task % N : 0;
         const int rest = task / N;
-        const int rb = act ? rest % nrb : 0, pbl = act ? rest / nrb : 0;
-        const int* PB = pblk + kInsBlkInts * (pb0 + pbl);
-        const int l = PB[0], mode = PB[1], np = PB[2];
-        // T row and position of each of the work-item's separations
-        int trow[kInsR], tx[kInsR];
+        const int rb = act ? rest % nrb : 0, bl = act ? rest / nrb : 0;
+        const int* B = sblk + kInsBlkInts * (sb0 + min(bl, nbw - 1));
+        const int l = B[0], mode = B[1], spans = B[2], ns = B[3];
+        // positions of T(y - sh(r), r): x and x + r of each of the work-item's separations
+        int xa[KR], xb[KR];
 #pragma unroll
-        for (int j = 0; j < kInsR; ++j) {
-            const int ir = min(rb * kInsR + j, nr - 1);
-            const int r = rlist[ir];
+        for (int j = 0; j < KR; ++j) {
+            const int r = rlist[min(rb * KR + j, nr - 1)];
             const int sh = l + (mode ? (spans ? (r - 1) / 2 : r / 2) : 0);
             int x = (y - sh) % N;
             x += x < 0 ? N : 0;
-            trow[j] = ir;
-            tx[j] = x;
+            xa[j] = x;
+            xb[j] = (x + r) % N;
         }
-        double acc[kInsR][kInsP][4];
+        double acc[KR][KS][4];
 #pragma unroll
-        for (int j = 0; j < kInsR; ++j)
+        for (int j = 0; j < KR; ++j)
 #pragma unroll
-            for (int k = 0; k < kInsP; ++k)
+            for (int k = 0; k < KS; ++k)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[j][k][q] = 0.0;
 
-        for (int m0 = 0; m0 < n_meas; m0 += mc) {
-            const int mm = min(mc, n_meas - m0);
-            __syncthreads();
-            // the line's phases and the displaced lines' O pairs of the chunk:
-            // each work-item issues all its loads of a round before it stores
-            // any of them, so their latencies overlap
+        // the sums over chunk ci (measurements ci mc, ...) from one buffer pair
+        auto sum_chunk = [&](const double2* ph, const unsigned char* op, int ci) {
+            if (!act) return;
+            const int mm = min(mc, n_meas - ci * mc);
+            const ot* ob = reinterpret_cast<const ot*>(op) + (size_t)bl * 2 * KS * N + y;
             for (int q = 0; q < mm; ++q) {
-                const double2* hq = hc + (size_t)(m0 + q) * mstride;
-                for_rows(1, [&](int, int k) { cl[q * N + k] = hq[(size_t)k * stride]; });
-            }
-            {
-                int qq = oq0, sl = os0, kk = k0;
-                while (qq < mm) {
-                    double2 v[kInsStage];
-                    int d[kInsStage];
+                const double2* pq = ph + q * N;
+                double2 t[KR];
 #pragma unroll
-                    for (int it = 0; it < kInsStage; ++it) {
-                        v[it] = make_double2(0.0, 0.0);
-                        d[it] = -1;
-                        if (qq < mm) {
-                            const int ob = obase[sl];
-                            if (ob >= 0) {
-                                const ot* src = ho + (size_t)(m0 + qq) * mstride_o + ob + (size_t)kk * stride;
-                                v[it] = make_double2((double)src[0], (double)src[nsig]);
-                            }
-                            d[it] = (qq * nslot + sl) * N + kk;
-                        }
-                        kk += dk;
-                        int adv = drow;
-                        if (kk >= N) {
-                            kk -= N;
-                            ++adv;
-                        }
-                        sl += adv;
-                        while (sl >= nslot) {
-                            sl -= nslot;
-                            ++qq;
-                        }
+                for (int j = 0; j < KR; ++j) {
+                    const double2 a = pq[xa[j]], b = pq[xb[j]];
+                    t[j] = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+                }
+                const ot* oq = ob + (size_t)q * nrows * N;
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    const double o0 = (double)oq[(2 * k) * N], o1 = (double)oq[(2 * k + 1) * N];
+#pragma unroll
+                    for (int j = 0; j < KR; ++j) {
+                        acc[j][k][0] += t[j].x * o0;
+                        acc[j][k][1] += t[j].y * o0;
+                        acc[j][k][2] += t[j].x * o1;
+                        acc[j][k][3] += t[j].y * o1;
                     }
-#pragma unroll
-                    for (int it = 0; it < kInsStage; ++it)
-                        if (d[it] >= 0) ol[d[it]] = v[it];
                 }
             }
-            __syncthreads();
-            for (int q = 0; q < mm; ++q) {
-                const double2* cq = cl + q * N;
-                double2* dst = tl + (size_t)q * nr * N;
-                for_rows(nr, [&](int ir, int x) {
-                    int xr = x + rv[ir];
-                    xr -= xr >= N ? N : 0;
-                    const double2 a = cq[x], b = cq[xr];
-                    dst[ir * N + x] = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-                });
+        };
+        __syncthreads();  // row offsets written; the previous pass done with both buffers
+        if (dma) {
+            // chunk ci streams into lph0/lo0 (even ci) or lph1/lo1 (odd ci) while the
+            // previous one is summed; before a buffer is summed, this wave's
+            // copies into it have landed (vmcnt 0) and the barrier makes every
+            // wave's visible and ends the sums over the chunk before, whose
+            // buffer the next copies overwrite
+            issue(0, min(mc, n_meas), lph0, lo0);
+            for (int ci = 0; ci < nch; ci += 2) {
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+                __syncthreads();
+                if (ci + 1 < nch) issue((ci + 1) * mc, min(mc, n_meas - (ci + 1) * mc), lph1, lo1);
+                sum_chunk(lph0, lo0, ci);
+                if (ci + 1 >= nch) break;
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+                __syncthreads();
+                if (ci + 2 < nch) issue((ci + 2) * mc, min(mc, n_meas - (ci + 2) * mc), lph0, lo0);
+                sum_chunk(lph1, lo1, ci + 1);
             }
-            __syncthreads();
-            if (act) {
-                for (int q = 0; q < mm; ++q) {
-                    double2 t[kInsR], o[kInsP];
-#pragma unroll
-                    for (int j = 0; j < kInsR; ++j) t[j] = tl[((size_t)q * nr + trow[j]) * N + tx[j]];
-#pragma unroll
-                    for (int k = 0; k < kInsP; ++k) o[k] = ol[((size_t)q * nslot + pbl * kInsP + k) * N + y];
-#pragma unroll
-                    for (int j = 0; j < kInsR; ++j)
-#pragma unroll
-                        for (int k = 0; k < kInsP; ++k) {
-                            acc[j][k][0] += t[j].x * o[k].x;
-                            acc[j][k][1] += t[j].y * o[k].x;
-                            acc[j][k][2] += t[j].x * o[k].y;
-                            acc[j][k][3] += t[j].y * o[k].y;
-                        }
-                }
+        } else {
+            for (int ci = 0; ci < nch; ++ci) {
+                if (ci > 0) __syncthreads();
+                stage(ci * mc, min(mc, n_meas - ci * mc), lph0, lo0);
+                __syncthreads();
+                sum_chunk(lph0, lo0, ci);
             }
         }
         if (act) {
 #pragma unroll
-            for (int j = 0; j < kInsR; ++j) {
-                const int ir = rb * kInsR + j;
+            for (int j = 0; j < KR; ++j) {
+                const int ir = rb * KR + j;
                 if (ir >= nr) continue;
-                const size_t xs = (size_t)base + (size_t)tx[j] * stride;
+                const size_t xs = (size_t)base + (size_t)xa[j] * stride;
 #pragma unroll
-                for (int k = 0; k < kInsP; ++k) {
-                    if (k >= np) continue;
-                    const int p = PB[4 + k];
-                    const size_t k0 = ((((size_t)id * nr + ir) * O.n_probe + p) * nc + ic) * 2;
-                    avg_to[E.ato_off + ((k0 + 0) * S + s) * nsig + xs] =
+                for (int k = 0; k < KS; ++k) {
+                    if (k >= ns) continue;
+                    const int p = B[4 + 4 * k], ic = B[5 + 4 * k];
+                    const size_t kq = ((((size_t)id * nr + ir) * O.n_probe + p) * O.n_comp + ic) * 2;
+                    avg_to[E.ato_off + ((kq + 0) * S + s) * nsig + xs] =
                         make_double2(acc[j][k][0] * inv, acc[j][k][1] * inv);
-                    avg_to[E.ato_off + ((k0 + 1) * S + s) * nsig + xs] =
+                    avg_to[E.ato_off + ((kq + 1) * S + s) * nsig + xs] =
                         make_double2(acc[j][k][2] * inv, acc[j][k][3] * inv);
                 }
             }
@@ -645,19 +723,32 @@ hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens,
     return hipGetLastError();
 }
 
-hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
                                size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_comp,
-                               const int* d_pblk, int n_comp, const double2* hist_c, const void* hist_o,
+                               const int* d_sblk, int slots_per_block, const double2* hist_c, const void* hist_o,
                                double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st)
 {
     if (total_blocks <= 0) return hipSuccess;
-    const dim3 g(total_blocks, max_slabs, n_dirs * n_comp);
-    if (precision == 0)
-        hipLaunchKernelGGL(k_contract_ins<double>, g, dim3(kInsThreads), lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,
-                           d_r, d_comp, d_pblk, hist_c, (const double*)hist_o, avg_to, n_meas);
-    else
-        hipLaunchKernelGGL(k_contract_ins<float>, g, dim3(kInsThreads), lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,
-                           d_r, d_comp, d_pblk, hist_c, (const float*)hist_o, avg_to, n_meas);
+    const dim3 g((total_blocks + 7) / 8 * 8, max_slabs, n_dirs), b(block);
+#define U1ML_INS(OT, KR, KS)                                                                                          \
+    hipLaunchKernelGGL((k_contract_ins<OT, KR, KS>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, d_comp, \
+                       d_sblk, hist_c, (const OT*)hist_o, avg_to, n_meas, total_blocks)
+    if (precision == 0) {
+        switch (slots_per_block) {
+        case 9: U1ML_INS(double, ins_kr(9), 9); break;
+        case 6: U1ML_INS(double, ins_kr(6), 6); break;
+        case 3: U1ML_INS(double, ins_kr(3), 3); break;
+        default: U1ML_INS(double, ins_kr(1), 1); break;
+        }
+    } else {
+        switch (slots_per_block) {
+        case 9: U1ML_INS(float, ins_kr(9), 9); break;
+        case 6: U1ML_INS(float, ins_kr(6), 6); break;
+        case 3: U1ML_INS(float, ins_kr(3), 3); break;
+        default: U1ML_INS(float, ins_kr(1), 1); break;
+        }
+    }
+#undef U1ML_INS
     return hipGetLastError();
 }
 

@@ -86,9 +86,14 @@ struct Problem {
     double est_hist_ms = 0.0, est_spec_ms = -1.0;  // the planner's cost estimates of the two forms
     std::vector<int> pgroup;      // probe -> group of probes sharing (l, mode)
     std::vector<int> gdesc;       // group -> (l, mode)
-    std::vector<int> pblk;        // insertion contraction: probe blocks, kInsBlkInts ints each
+    std::vector<int> pblk;        // insertion contraction: slot blocks, kInsBlkInts ints each
+    int ins_ks = 1;               // insertion contraction: slots per block
     long long nd_cfg = 0;
 };
+
+// frame components whose plaquette spans the charge axis: E_par (P_{par t}),
+// B_perp1 (P_{perp2 par}) and B_perp2 (P_{par perp1})
+bool comp_spans_axis_host(int c) { return c == 0 || c == 4 || c == 5; }
 
 bool fail(std::string* err, const std::string& msg)
 {
@@ -209,26 +214,54 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
         }
         P->pgroup.push_back(g);
     }
-    // probe blocks of the insertion contraction: the probes of each group in
-    // problem order, kInsP at a time
+    // slot blocks of the insertion contraction: the (probe, component) pairs
+    // of each probe group whose plaquettes span the axis, then those whose
+    // plaquettes do not (probes, then components, in problem order), KS at a
+    // time; KS in {9, 6, 3, 1} leaves the fewest empty slots (the larger on a tie)
     P->pblk.clear();
-    for (int g = 0; g < (int)P->gdesc.size() / 2; ++g) {
-        std::vector<int> members;
-        for (int p = 0; p < (int)P->probes.size(); ++p)
-            if (P->pgroup[p] == g) members.push_back(p);
-        for (size_t b = 0; b < members.size(); b += kInsP) {
-            int blk[kInsBlkInts] = {};
-            blk[0] = P->gdesc[2 * g];
-            blk[1] = P->gdesc[2 * g + 1];
-            blk[2] = (int)std::min<size_t>(kInsP, members.size() - b);
-            for (int k = 0; k < blk[2]; ++k) {
-                const u1ml_probe& pr = P->probes[members[b + k]];
-                blk[4 + k] = members[b + k];
-                blk[8 + 2 * k] = pr.p1;
-                blk[9 + 2 * k] = pr.p2;
+    P->ins_ks = 1;
+    {
+        std::vector<std::vector<std::pair<int, int>>> keys;  // slots (probe, component index) per key
+        std::vector<int> key_l, key_mode, key_spans;
+        for (int g = 0; g < (int)P->gdesc.size() / 2; ++g)
+            for (int sp = 1; sp >= 0; --sp) {
+                std::vector<std::pair<int, int>> slots;
+                for (int p = 0; p < (int)P->probes.size(); ++p)
+                    if (P->pgroup[p] == g)
+                        for (int ic = 0; ic < (int)P->comps.size(); ++ic)
+                            if ((int)comp_spans_axis_host(P->comps[ic]) == sp) slots.emplace_back(p, ic);
+                if (slots.empty()) continue;
+                keys.push_back(slots);
+                key_l.push_back(P->gdesc[2 * g]);
+                key_mode.push_back(P->gdesc[2 * g + 1]);
+                key_spans.push_back(sp);
             }
-            P->pblk.insert(P->pblk.end(), blk, blk + kInsBlkInts);
+        size_t best = ~(size_t)0;
+        for (int ks : {9, 6, 3, 1}) {
+            size_t padded = 0;
+            for (const auto& k : keys) padded += (k.size() + ks - 1) / ks * ks;
+            if (padded < best) {
+                best = padded;
+                P->ins_ks = ks;
+            }
         }
+        const int ks = P->ins_ks;
+        for (size_t kk = 0; kk < keys.size(); ++kk)
+            for (size_t b = 0; b < keys[kk].size(); b += ks) {
+                int blk[kInsBlkInts] = {};
+                blk[0] = key_l[kk];
+                blk[1] = key_mode[kk];
+                blk[2] = key_spans[kk];
+                blk[3] = (int)std::min<size_t>(ks, keys[kk].size() - b);
+                for (int k = 0; k < blk[3]; ++k) {
+                    const int p = keys[kk][b + k].first, ic = keys[kk][b + k].second;
+                    blk[4 + 4 * k] = p;
+                    blk[5 + 4 * k] = ic;
+                    blk[6 + 4 * k] = P->probes[p].p1;
+                    blk[7 + 4 * k] = P->probes[p].p2;
+                }
+                P->pblk.insert(P->pblk.end(), blk, blk + kInsBlkInts);
+            }
     }
     return true;
 }
@@ -591,6 +624,7 @@ struct u1ml_ctx {
     int spec_tile = 4;                             // plane-transform tile (4, or 2 if an extent is not a multiple of 4)
     int *d_pgroup = nullptr, *d_gdesc = nullptr, *d_pblk = nullptr;
     size_t ins_lds = 0;  // insertion contraction dynamic LDS per work-group
+    int ins_block = 64;  // insertion contraction work-group size
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
     double* static_partials = nullptr;  // the library's static scratch on this context's device
@@ -735,7 +769,7 @@ void build_lane_tables(const u1ml_ctx* c, Lane& L)
         all[e] = 8ll * E.vh;
         meas[e] = (long long)E.nsig * E.s_in;
         con[e] = (lines + E.con_lpb - 1) / E.con_lpb;
-        // insertion contraction: (line, probe chunk) work-groups of the axis with the most lines
+        // insertion contraction: (line, slot-block chunk) work-groups of the axis with the most lines
         ins[e] = (!P.probes.empty() && !P.spectral)
                      ? (long long)lines * ((P.pblk.size() / kInsBlkInts + E.ins_pbw - 1) / E.ins_pbw)
                      : 0;
@@ -918,8 +952,8 @@ hipError_t enq_levels(u1ml_ctx* c, const Lane& L, hipStream_t st, bool store_o, 
             e = launch_contract(L.d_ens, L.tab_dev(kTabCon), n, L.tab_total(kTabCon), c->con_block, c->con_lds,
                                 c->d_obs, c->d_r, c->hc, c->at, P.n_i, L.max_s_in, P.n_dirs, st);
         if (e == hipSuccess && ins_hist)
-            e = launch_contract_ins(L.d_ens, L.tab_dev(kTabIns), n, L.tab_total(kTabIns), c->ins_lds, c->d_obs,
-                                    c->d_r, c->d_comp, c->d_pblk, (int)P.comps.size(), c->hc, c->ho, c->ato, P.n_i,
+            e = launch_contract_ins(L.d_ens, L.tab_dev(kTabIns), n, L.tab_total(kTabIns), c->ins_block, c->ins_lds,
+                                    c->d_obs, c->d_r, c->d_comp, c->d_pblk, P.ins_ks, c->hc, c->ho, c->ato, P.n_i,
                                     P.precision, L.max_s_in, P.n_dirs, st);
         if (e == hipSuccess && P.two && !spec_acc)
             e = launch_combine(L.d_ens, L.tab_dev(kTabComb), n, L.tab_total(kTabComb), c->d_obs, c->at,
@@ -1297,10 +1331,11 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
     // Contraction shape: a line of N sites along a charge axis has N * n_r
     // pairs (x, r), one thread each; a work-group of con_block threads holds
     // con_lpb such lines, and stages con_mc measurements at a time in LDS.
-    // Insertions: a work-group per (line, slab, axis, component, ins_pbw
-    // probe blocks) with N * ceil(n_r / kInsR) * ins_pbw tasks, staging
-    // ins_mc measurements (phases, T for every (r, x), O pairs of its probes).
+    // Insertions: a work-group per (line, slab, axis, ins_pbw slot blocks)
+    // with N * ceil(n_r / KR) * ins_pbw tasks, staging ins_mc measurements
+    // (the line's phases and the O rows of its slots).
     const size_t R = P.r.size();
+    const size_t word = P.precision == U1ML_FP64 ? 8 : 4;  // O history element
     std::vector<int> group(n);
     c->con_block = 256;
     for (int e = 0; e < n; ++e) {
@@ -1322,14 +1357,28 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         E.con_mc = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)P.n_i));
         c->con_lds = std::max(c->con_lds, (size_t)E.con_lpb * E.con_mc * nmax * per);
         if (!P.probes.empty() && !P.spectral) {
-            const int npb = (int)(P.pblk.size() / kInsBlkInts);
-            const int nrb = (int)((R + kInsR - 1) / kInsR);
-            E.ins_pbw = std::max(1, std::min(npb, kInsThreads / (int)(nmax * nrb)));
-            const size_t nslot = (size_t)E.ins_pbw * kInsP;
-            const size_t per_m = 16 * nmax * (1 + R + nslot);
-            const size_t tail = 4 * (nslot + R);  // slot line offsets and separations
-            E.ins_mc = (int)std::max<size_t>(1, std::min<size_t>((size_t)kInsLds / per_m, (size_t)P.n_i));
-            c->ins_lds = std::max(c->ins_lds, per_m * E.ins_mc + tail);
+            const int nsb = (int)(P.pblk.size() / kInsBlkInts);
+            const int ks = P.ins_ks, kr = ins_kr(ks);
+            const int unit = (int)(nmax * ((R + kr - 1) / kr));  // tasks of one slot block
+            E.ins_pbw = std::max(1, std::min(std::min(nsb, kInsThreads / unit), kInsRowsMax / (2 * ks)));
+            // ins_mc measurements per LDS chunk buffer (static LDS of the kernel):
+            // fewer slot blocks per work-group while a chunk would hold fewer than 8
+            auto fit_mc = [&](int bpw) {
+                int mc = std::min(P.n_i, kInsPh);
+                while (mc > 1 && !ins_chunk_fits(mc, (int)nmax, bpw * ks * 2, (int)word)) --mc;
+                return mc;
+            };
+            while (E.ins_pbw > 1 && fit_mc(E.ins_pbw) < std::min(8, P.n_i)) --E.ins_pbw;
+            c->ins_block = std::max(c->ins_block, std::min(kInsThreads, (E.ins_pbw * unit + 63) / 64 * 64));
+            const int nrows = E.ins_pbw * ks * 2;
+            const int mc = fit_mc(E.ins_pbw);
+            if (!ins_chunk_fits(mc, (int)nmax, nrows, (int)word)) {
+                release(c);
+                return set_err(nullptr, U1ML_ENOTSUP,
+                               "history-form insertions: one measurement of a work-group's phases or O rows exceeds "
+                               "its LDS buffer (use the spectral form)");
+            }
+            E.ins_mc = mc;
         }
         E.prod_nch = (P.n_dirs * E.nsig + kProdChunk - 1) / kProdChunk;
         E.res_index = e;

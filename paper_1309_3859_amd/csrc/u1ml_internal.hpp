@@ -16,7 +16,7 @@ struct EnsDesc {
     int con_lpb, con_mc;  // contraction: lines per work-group, measurements per LDS chunk
     int prod_nch;   // slab products: site chunks per (r, probe)
     int res_index;  // index of the ensemble in the problem (counters, results)
-    int ins_pbw, ins_mc;  // insertion contraction: probe blocks per work-group, measurements per LDS chunk
+    int ins_pbw, ins_mc;  // insertion contraction: slot blocks per work-group, measurements per LDS chunk
     float inv_nxh, inv_ny, inv_slice, pad3;  // 1/(Nx/2), 1/Ny, 1/((Nx/2) Ny Nz) for division-free decode
     double beta, sqrt_beta;
     double metro_delta;  // Metropolis proposal step
@@ -58,23 +58,33 @@ struct ObsDesc {
     int n_groups;  // probe groups sharing (l, mode) (spectral form)
     int n_ens_total;  // ensembles of the problem (rows of a results record)
     int multihit;     // correlator averages from multihit slab phases
-    int n_pblocks;    // insertion contraction: blocks of up to kInsP probes sharing (l, mode)
+    int n_pblocks;    // insertion contraction: slot blocks (probe, component pairs sharing (l, mode, spans))
     long long n_doubles_per_config;
 };
 
-// Insertion contraction (history form): a work-item owns one position y of
-// the displaced line, kInsR separations and one block of kInsP probes that
-// share (l, mode), so every staged T value feeds kInsP outputs and every O
-// value kInsR outputs.  A probe block is kInsBlkInts ints: l, mode, number
-// of probes, 0, their indices (kInsP, then padding to 8), then (p1, p2) of
-// each probe.
-constexpr int kInsR = 4;
-constexpr int kInsP = 3;
-constexpr int kInsThreads = 256;
-constexpr int kInsBlkInts = 16;
-constexpr int kInsStage = 4;  // O pairs each work-item loads per staging round
-static_assert(kInsP <= 4 && 8 + 2 * kInsP <= kInsBlkInts, "probe block layout");
-constexpr int kInsLds = 49152;  // LDS budget per work-group (bytes)
+// Insertion contraction (history form): the (probe, component) slots that
+// share (l, mode, spans) meet every T value at the same offset along the axis
+// and form blocks of KS slots (9, 6, 3 or 1, the planner's choice); a
+// work-item owns one position y of the displaced lines, ins_kr(KS)
+// separations and one slot block (KR x KS x 4 FP64 accumulators).  A slot
+// block is kInsBlkInts ints: l, mode, spans (0 or 1), number of slots, then
+// per slot its probe index, component index (into the problem's list), p1, p2.
+constexpr int kInsSlotMax = 9;
+constexpr int kInsBlkInts = 4 + 4 * kInsSlotMax;
+constexpr int kInsThreads = 256;  // largest work-group
+constexpr int kInsPh = 384;       // phases of one LDS chunk buffer (16-byte vectors, a multiple of 64)
+constexpr int kInsOb = 25600;     // O rows of one LDS chunk buffer (bytes, a multiple of 1024)
+constexpr int kInsRowsMax = 512;  // O rows (slot block, slot, kind) of one work-group
+__host__ __device__ constexpr int ins_kr(int ks) { return ks == 9 ? 2 : (ks == 6 ? 3 : (ks == 3 ? 4 : 8)); }
+// measurements per chunk buffer of the contraction: the phases [q][x] and the
+// O rows [q][row][y] (word bytes each) of mc measurements, each region
+// rounded up to whole waves of 64 16-byte vectors, must fit kInsPh and kInsOb
+__host__ __device__ inline bool ins_chunk_fits(int mc, int N, int nrows, int word)
+{
+    const size_t ph = ((size_t)mc * N + 63) / 64 * 64;
+    const size_t ob = ((size_t)mc * nrows * N * word + 1023) / 1024 * 1024;
+    return ph <= (size_t)kInsPh && ob <= (size_t)kInsOb;
+}
 
 constexpr int kUpdateClasses = 4;  // temporal, spatial full, spatial inner tau, spatial outer tau
 constexpr int kProdChunk = 2048;    // slab products: (axis, site) items per work-group
@@ -119,9 +129,10 @@ hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens,
                            size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const double2* hist_c,
                            double2* avg_t, int n_meas, int max_slabs, int n_dirs, hipStream_t st);
 // insertion averages [TO] of the inner level from the stored measurements
-hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks,
+// work-groups of `block` threads; slots_per_block selects the kernel's tile (KS, ins_kr(KS))
+hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
                                size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_comp,
-                               const int* d_pblk, int n_comp, const double2* hist_c, const void* hist_o,
+                               const int* d_sblk, int slots_per_block, const double2* hist_c, const void* hist_o,
                                double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st);
 hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                           const double2* avg_t, const double2* avg_to, double2* out_t, double2* out_to, int q,
