@@ -310,7 +310,8 @@ u1ml_status u1ml_set_block(u1ml_ctx* ctx, int block);
  * lanes side by side fill the device where one does not, and the
  * arithmetic-bound heatbath phases of one lane overlap the memory-bound
  * overrelaxation phases of another.  n_lanes = 1 runs the whole batch on the
- * context's stream.  Default: 2 for two or more ensembles.  Every ensemble's
+ * context's stream.  Default: 2 lanes for FP32 links and 4 for FP64 links,
+ * at most one per ensemble.  Every ensemble's
  * links and estimates are bit-identical for every lane count.  EINVAL for
  * n_lanes outside 1..4 or above the number of ensembles. */
 u1ml_status u1ml_set_lanes(u1ml_ctx* ctx, int n_lanes);

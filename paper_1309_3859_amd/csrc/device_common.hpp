@@ -216,13 +216,14 @@ __device__ inline double bf_r_f64(double kappa)
 }
 
 // Both attempts are evaluated by every lane, so a wave runs each step once
-// whichever attempt its lanes accept, and arccos once, for the accepted one.
+// whichever attempt its lanes accept; the accepted attempt is returned as
+// cos(psi) = f and the sign of psi (psi = -arccos f when negative).
 // The logarithmic test is decided on t = ln(c / U2) + 1 - c formed in FP32
 // (hardware base-2 logarithm): with 1/2 <= c < 64 and U2 >= 2^-33,
 // |ln(c / U2)| < 28 and the FP32 value is within 1e-5 of the exact one; where
 // |t| < 2^-10, or c >= 64 (kappa above 31), the test is taken again in FP64
 // exactly as the definition writes it.  Every decision is the FP64 test's.
-__device__ inline int bf_pair_f64(double kappa, double r, const Block4& b, double* psi)
+__device__ inline int bf_pair_f64(double kappa, double r, const Block4& b, double* cpsi, bool* neg)
 {
     using m = M<double>;
     double f[2], c[2], u2[2];
@@ -249,10 +250,9 @@ __device__ inline int bf_pair_f64(double kappa, double r, const Block4& b, doubl
             if (band[half]) acc[half] = m::log_(m::div_(c[half], u2[half])) + 1.0 - c[half] >= 0.0;
     }
     if (!acc[0] && !acc[1]) return 0;
-    const int k = acc[0] ? 1 : 2;
-    const double p = m::acos_(acc[0] ? f[0] : f[1]);
-    *psi = ((acc[0] ? b.w[0] : b.w[2]) & 1u) ? -p : p;
-    return k;
+    *cpsi = acc[0] ? f[0] : f[1];
+    *neg = ((acc[0] ? b.w[0] : b.w[2]) & 1u) != 0;
+    return acc[0] ? 1 : 2;
 }
 
 template <>
@@ -267,11 +267,13 @@ __device__ inline double vonmises_psi<double>(double kappa, uint32_t k0, uint32_
     }
     const double r = bf_r_f64(kappa);
     for (uint32_t jp = 0; jp < 32768u; ++jp) {
-        double psi;
-        const int k = bf_pair_f64(kappa, r, philox4x32_10(c0, c1, jp, domain, k0, k1), &psi);
+        double f;
+        bool neg;
+        const int k = bf_pair_f64(kappa, r, philox4x32_10(c0, c1, jp, domain, k0, k1), &f, &neg);
         if (k) {
             *n_att = 2 * (int)jp + k;
-            return psi;
+            const double p = m::acos_(f);
+            return neg ? -p : p;
         }
     }
     *n_att = -1;

@@ -53,9 +53,8 @@ struct LinkView {
 // order, into a queue in LDS and finished by consecutive threads, so a wave no
 // longer waits for its slowest lane.  A link's result depends only on its own
 // counters, so the queue changes no result.  A queue entry holds what the
-// link's final angle needs besides its deviate: FP32 the staple sum A
-// (theta = arg(e^{i psi} conj A) by one atan2), FP64 arg A (theta =
-// wrap(psi - arg A), the definition's order).
+// link's final angle needs besides its deviate: the staple sum A, theta =
+// arg(e^{i psi} conj A) by one atan2 (wrap(psi - arg A) up to rounding).
 template <typename real>
 struct RetryQ;
 template <>
@@ -65,7 +64,7 @@ struct RetryQ<float> {
 };
 template <>
 struct RetryQ<double> {
-    double kappa, phia;
+    double kappa, ar, ai;
     unsigned lid, off;
 };
 
@@ -75,7 +74,14 @@ __device__ inline float hb_angle(const RetryQ<float>& q, float cp, float sp)
     const float th = atan2_fast(sp * q.ar - cp * q.ai, cp * q.ar + sp * q.ai);
     return th >= 3.14159265f ? -3.14159265f : th;
 }
-__device__ inline double hb_angle(const RetryQ<double>& q, double psi) { return wrap_angle<double>(psi - q.phia); }
+// FP64: e^{i theta} = e^{i psi} conj(A) / |A| with e^{i psi} = f + i sin psi,
+// sin psi = +-sqrt((1 - f)(1 + f)) (1 - f and 1 + f exact where they
+// cancel), so one atan2 gives theta = psi - arg A in [-pi, pi)
+__device__ inline double hb_angle(const RetryQ<double>& q, double cp, double sp)
+{
+    const double th = M<double>::atan2_(sp * q.ar - cp * q.ai, cp * q.ar + sp * q.ai);
+    return th >= M<double>::pi ? -M<double>::pi : th;
+}
 
 // attempts of one Philox block; true with the new angle if one accepted
 __device__ inline bool hb_block(const RetryQ<float>& q, const BfEnvF32& v, const Block4& b, float* th)
@@ -87,9 +93,11 @@ __device__ inline bool hb_block(const RetryQ<float>& q, const BfEnvF32& v, const
 }
 __device__ inline bool hb_block(const RetryQ<double>& q, double r, const Block4& b, double* th)
 {
-    double psi;
-    if (!bf_pair_f64(q.kappa, r, b, &psi)) return false;
-    *th = hb_angle(q, psi);
+    double f;
+    bool neg;
+    if (!bf_pair_f64(q.kappa, r, b, &f, &neg)) return false;
+    const double sp = M<double>::sqrt_((1.0 - f) * (1.0 + f));
+    *th = hb_angle(q, f, neg ? -sp : sp);
     return true;
 }
 __device__ inline BfEnvF32 hb_env(const RetryQ<float>& q) { return bf_env_f32(q.kappa); }
@@ -191,11 +199,16 @@ __global__ void __launch_bounds__(1024) k_update(const EnsDesc* __restrict__ ens
                     done = hb_block(q, bf_env_f32(kappa), b0, &th);
                 }
             } else {
-                q = RetryQ<double>{kappa, M<double>::atan2_(ai, ar), lid, self};
-                if (kappa == 0.0)
-                    th = hb_angle(q, M<double>::pi * (2.0 * M<double>::u1(b0.w[0]) - 1.0));
-                else
+                q = RetryQ<double>{kappa, ar, ai, lid, self};
+                if (kappa == 0.0) {
+                    // psi uniform from attempt 0: pi (2 U1 - 1) (with A = 0 as well, theta = psi)
+                    double sp, cp;
+                    sincos_bounded(M<double>::pi * (2.0 * M<double>::u1(b0.w[0]) - 1.0), &sp, &cp);
+                    if (R == 0.0) q.ar = 1.0;
+                    th = hb_angle(q, cp, sp);
+                } else {
                     done = hb_block(q, bf_r_f64(kappa), b0, &th);
+                }
             }
             if (done) {
                 *dst = th;

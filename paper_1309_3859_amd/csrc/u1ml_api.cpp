@@ -62,7 +62,11 @@ constexpr int kTabIns = 13;   // insertion contraction: work-groups
 constexpr int kNumTabs = 14;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 constexpr int kMaxLanes = 4;  // streams that sweeps and configurations are spread over
-constexpr int kDefaultLanes = 2;
+// lanes a context starts with: FP32 phases are short enough that two lanes
+// fill the device and a third adds under 1 %; the longer, arithmetic-bound
+// FP64 phases gain about 2.5 % more from four (C4 on MI355X: FP32 8.50,
+// 8.43, 8.64 ms per configuration with 2, 3, 4 lanes; FP64 17.96, 17.78, 17.56)
+int default_lanes(int precision) { return precision == U1ML_FP64 ? 4 : 2; }
 
 struct Problem {
     int n_ens = 0;
@@ -305,7 +309,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     // the spectral form does not apply, spectral when the history form's
     // per-site averages would exceed 64 GiB); the unit costs are MI355X
     // measurements (FP32 links):
-    //   history:  contraction 5.6e12 FMA/s (the inner level's [TO] sums);
+    //   history:  contraction 6.6e12 FMA/s (the inner level's [TO] sums);
     //             two levels: the inner averages folded into the outer sums,
     //             3 passes over them per outer update at 3 TB/s;
     //   spectral: per measurement 20 us of launches, 14.2 ps per plane
@@ -313,8 +317,8 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     //             flop of the spectral sums; two levels: the replay repeats
     //             every update (5e10 link updates/s).
     // Measured per configuration (history / spectral, ms): 24^3x8, 9 probes,
-    // 100 updates 13.6 / 18.1; 24^3x8 in-plane map 18.1 / 19.4; 48^3x12 two
-    // levels 2 x 10, 1 probe 15.9 / 21.5, 8 probes 53.3 / 21.4.
+    // 100 updates 11.9 / 18.0; 24^3x8 in-plane map 18.1 / 19.4; 48^3x12 two
+    // levels 2 x 10, 1 probe 8.8 / 21.5, 8 probes 39.9 / 21.6.
     {
         bool plane_ok = true;
         double hist_avg = 0.0, est_h = 0.0, est_s = 0.0;
@@ -326,7 +330,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
             const double per = (double)nd * R * Np * Nc * 2 * nsig * 16.0;
             const double si = (double)(E.nt / P.tau_i);
             hist_avg += per * si + (P.two ? per * (E.nt / P.tau_o) : 0.0);
-            est_h += n_meas * nd * si * nsig * R * Np * Nc * 4.0 / 5.6e12;
+            est_h += n_meas * nd * si * nsig * R * Np * Nc * 4.0 / 6.6e12;
             if (P.two) est_h += (double)P.n_o * per * si * 3.0 / 3.0e12;
             est_s += n_meas * (20e-6 + nd * si * nsig * (R + 12) * 14.2e-12 + nd * si * (double)NG * nsig * R * Nc * 16.0 * 0.198e-12);
             if (P.two) {
@@ -1446,7 +1450,7 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
             e = hipStreamCreateWithFlags(&c->lane_stream[l], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join[l], hipEventDisableTiming);
         }
-        if (e == hipSuccess) e = split_lanes(c, std::min(n, kDefaultLanes));
+        if (e == hipSuccess) e = split_lanes(c, std::min(n, default_lanes(P.precision)));
         if (e != hipSuccess) st = set_err(nullptr, U1ML_EDEVICE, std::string("lanes: ") + hipGetErrorString(e));
     }
     if (st != U1ML_OK) {

@@ -248,7 +248,7 @@ class Context:
         self._h = h
         self.n_ens = len(spec.ensembles)
         self.nd = self.plan["n_doubles_per_config"]
-        self._n_lanes = 2 if self.n_ens >= 2 else 1  # the library's default
+        self._n_lanes = min(self.n_ens, 4 if spec.precision == FP64 else 2)  # the library's default
 
     def close(self):
         if getattr(self, "_h", None):

@@ -164,9 +164,9 @@ def test_contraction_form_selection(u1):
 def test_contraction_form_follows_the_cost_estimates(u1):
     """AUTO takes the form with the smaller estimated device time.  The
     estimates order the forms as measured on MI355X (ms per configuration,
-    history / spectral): 24^3x8 with 9 probes 13.6 / 18.1, the in-plane map
-    18.1 / 19.4, 48^3x12 at 2 x 10 updates with 1 probe 15.9 / 21.5 and with
-    8 probes 53.3 / 21.4; without probes there is nothing to estimate."""
+    history / spectral): 24^3x8 with 9 probes 11.9 / 18.0, the in-plane map
+    18.1 / 19.4, 48^3x12 at 2 x 10 updates with 1 probe 8.8 / 21.5 and with
+    8 probes 39.9 / 21.6; without probes there is nothing to estimate."""
     from paper_1309_3859_amd import configs
 
     cases = []
