@@ -227,10 +227,14 @@ __device__ inline FftPlan fft_plan(int n)
 // (se = 1), else the same butterfly of consecutive sequences (sq = 1), so the
 // 16-byte LDS accesses of a wave stay on distinct banks and the last stage's
 // global stores are contiguous.
-template <int R>
+// NC, RC, SC: the length, the number of sequences and Ns as compile-time
+// constants (0: taken from the arguments), so that a fixed plane size folds
+// the index arithmetic
+template <int R, int NC = 0, int RC = 0, int SC = 0>
 __device__ inline void fft_stage(const double2* __restrict__ src, int sq, int se, double2* __restrict__ dst, int dq,
-                                 int de, int n, int rows, int Ns, const double2* __restrict__ tw, double sg)
+                                 int de, int n_, int rows_, int Ns_, const double2* __restrict__ tw, double sg)
 {
+    const int n = NC ? NC : n_, rows = RC ? RC : rows_, Ns = SC ? SC : Ns_;
     const int m = n / R;
     const int tstep = n / (Ns * R);
     const int total = rows * m;
@@ -303,6 +307,40 @@ __device__ inline void fft_axis(const FftPlan& P, double2* cur, double2* other, 
         double2* t = cur;
         cur = other;
         other = t;
+    }
+}
+
+// The same FFT for an axis of compile-time length N on an N x N plane: the
+// stages of fft_plan(N) in the same order with the same arithmetic, every
+// length, count and stride constant.
+__host__ __device__ constexpr int cplan_stage(int n, int st, bool want_ns)
+{
+    int i = 0, ns = 1;
+    const int radices[4] = {4, 2, 3, 5};
+    for (int ri = 0; ri < 4; ++ri) {
+        const int r = radices[ri];
+        while (n % r == 0) {
+            if (i == st) return want_ns ? ns : r;
+            ++i;
+            ns *= r;
+            n /= r;
+        }
+    }
+    return want_ns ? ns : (n == 1 ? -i : 0);  // past the last stage: minus the stage count
+}
+__host__ __device__ constexpr int cplan_nst(int n) { return -cplan_stage(n, 64, false); }
+
+template <int N, int ST>
+__device__ inline void fft_axis_c(double2* cur, double2* other, int sq, int se, const double2* tw, double sg,
+                                  double2* out, int oq, int oe)
+{
+    constexpr int NST = cplan_nst(N);
+    if constexpr (ST < NST) {
+        constexpr int R = cplan_stage(N, ST, false), NS = cplan_stage(N, ST, true);
+        constexpr bool last = ST == NST - 1;
+        fft_stage<R, N, N, NS>(cur, sq, se, last ? out : other, last ? oq : sq, last ? oe : se, N, N, NS, tw, sg);
+        __syncthreads();
+        fft_axis_c<N, ST + 1>(other, cur, sq, se, tw, sg, out, oq, oe);
     }
 }
 
@@ -411,7 +449,7 @@ __global__ void __launch_bounds__(256) k_plane_stage(const EnsDesc* __restrict__
 // ---------------------------------------------------------------------------
 constexpr int kPlaneThreads = 512;  // two work-groups fill a CU's LDS; more threads per plane hide latency
 
-template <typename ot, int T>
+template <typename ot, int T, int NP>
 __global__ void __launch_bounds__(kPlaneThreads) k_dft_planes(const EnsDesc* __restrict__ ens, const int* __restrict__ bstart,
                                                     int n_ens, const ObsDesc* __restrict__ obs,
                                                     const int* __restrict__ rlist, const double2* __restrict__ cpl,
@@ -497,6 +535,13 @@ __global__ void __launch_bounds__(kPlaneThreads) k_dft_planes(const EnsDesc* __r
         // along v (sequences u, contiguous), result left in X or Y, then along u
         // (sequences k2, stride n2), the last stage writing out[k1 n2 + k2]
         double2* mid = (P2.n_st & 1) ? Y : X;
+        if constexpr (NP > 0) {
+            if (n1 == NP && n2 == NP) {  // uniform for the block
+                fft_axis_c<NP, 0>(X, Y, n2, 1, w2, sg, mid, n2, 1);
+                fft_axis_c<NP, 0>(mid, mid == X ? Y : X, 1, n2, w1, sg, out, 1, n2);
+                return;
+            }
+        }
         fft_axis(P2, X, Y, n2, 1, n2, n1, w2, sg, mid, n2, 1);
         fft_axis(P1, mid, mid == X ? Y : X, 1, n2, n1, n2, w1, sg, out, 1, n2);
         return;
@@ -748,20 +793,21 @@ hipError_t launch_dft_planes(const EnsDesc* d_ens, const int* d_bstart, int n_en
                              hipStream_t st)
 {
     const dim3 g(total_blocks), b(kPlaneThreads);
+    // 48 x 48 planes (the 48^3 lattice) take the transform with constant sizes
     if (precision == 0) {
         if (tile == 4)
-            hipLaunchKernelGGL((k_dft_planes<double, 4>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, cpl,
-                               (const double*)opl, gf, sph, spo);
+            hipLaunchKernelGGL((k_dft_planes<double, 4, 48>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r,
+                               cpl, (const double*)opl, gf, sph, spo);
         else
-            hipLaunchKernelGGL((k_dft_planes<double, 2>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, cpl,
-                               (const double*)opl, gf, sph, spo);
+            hipLaunchKernelGGL((k_dft_planes<double, 2, 0>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r,
+                               cpl, (const double*)opl, gf, sph, spo);
     } else {
         if (tile == 4)
-            hipLaunchKernelGGL((k_dft_planes<float, 4>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, cpl,
-                               (const float*)opl, gf, sph, spo);
+            hipLaunchKernelGGL((k_dft_planes<float, 4, 48>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r,
+                               cpl, (const float*)opl, gf, sph, spo);
         else
-            hipLaunchKernelGGL((k_dft_planes<float, 2>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, cpl,
-                               (const float*)opl, gf, sph, spo);
+            hipLaunchKernelGGL((k_dft_planes<float, 2, 0>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r,
+                               cpl, (const float*)opl, gf, sph, spo);
     }
     return hipGetLastError();
 }
