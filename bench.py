@@ -103,6 +103,56 @@ def metropolis_acceptance(ctx, spec, tau):
     return {"delta": spec.metro_delta, "acceptance": moved / total, "links": total}
 
 
+def staple_abs(th, ns, nt):
+    """|A| of every link from canonical angles th[4 s + mu], s = x + Nx (y +
+    Ny (z + Nz t)): A = sum over nu != mu of the forward and backward
+    staples' phases, returned in the same (s, mu) order."""
+    import numpy as np
+
+    nx, ny, nz = ns
+    th = np.asarray(th).reshape(nt, nz, ny, nx, 4)
+    ax = (3, 2, 1, 0)  # array axis of direction x, y, z, t
+    sh = lambda a, d, k: np.roll(a, -k, axis=ax[d])  # sh(a, d, 1)[x] = a[x + d]
+    out = np.empty(th.shape)
+    for mu in range(4):
+        A = np.zeros(th.shape[:4], dtype=np.complex128)
+        for nu in range(4):
+            if nu == mu:
+                continue
+            tm, tn = th[..., mu], th[..., nu]
+            A += np.exp(1j * (sh(tn, mu, 1) - sh(tm, nu, 1) - tn))
+            A += np.exp(1j * (sh(tn, nu, -1) - sh(sh(tn, mu, 1), nu, -1) - sh(tm, nu, -1)))
+        out[..., mu] = np.abs(A)
+    return out.ravel()
+
+
+def heatbath_attempts(ctx, spec, n_bins: int = 48, draws: int = 8192):
+    """Best-Fisher attempts per accepted link on the batch's current links:
+    kappa = beta |A| of every link (staple sums formed on the host from the
+    canonical angles), binned, and the mean attempt count of each bin's
+    kappa from `draws` device draws of the heatbath's own sampler
+    (u1ml_vonmises_fill, the workload's precision), weighted by the bin's
+    links."""
+    import numpy as np
+
+    from paper_1309_3859_amd import u1ml
+
+    kap = np.concatenate([ens.beta * staple_abs(ctx.links(e), ens.ns, ens.nt) for e, ens in enumerate(spec.ensembles)])
+    edges = np.linspace(0.0, kap.max() * (1 + 1e-9), n_bins + 1)
+    counts, _ = np.histogram(kap, edges)
+    mean_att = 0.0
+    for b in range(n_bins):
+        if counts[b] == 0:
+            continue
+        k = 0.5 * (edges[b] + edges[b + 1])
+        _, att = u1ml.vonmises_fill(k, draws, precision=spec.precision, seed=11, key_id=b)
+        mean_att += counts[b] * float(att.double().mean())
+    return {"attempts_per_link": mean_att / counts.sum(), "kappa_mean": float(kap.mean()),
+            "links": int(kap.size),
+            "method": f"kappa = beta |A| of every link of the batch after the timed steps, {n_bins} bins, "
+                      f"{draws} draws of the device sampler per bin"}
+
+
 def measurement_accuracy(ctx64, spec):
     """Accuracy of the FP32 form against the FP64 form on identical inputs:
     the FP64 context's current links, rounded to FP32 for both sides, (1)
@@ -569,7 +619,8 @@ def main():
     # the same batch in full-lattice sweeps (thermalisation), next to the multilevel rate of `value`
     line["full_sweeps"] = {"value": time_full_sweeps(ctx), "unit": "link updates/s"}
     line["metropolis"] = metropolis_acceptance(ctx, spec, tau)
-    progress("step bytes, full sweeps and Metropolis acceptance done")
+    line["heatbath"] = heatbath_attempts(ctx, spec)
+    progress("step bytes, full sweeps, Metropolis acceptance and heatbath attempts done")
     if not args.no_fp64 and spec.precision == u1ml.FP32:
         # the same workload with FP64 link storage and update arithmetic
         spec64, _ = make()

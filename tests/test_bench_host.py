@@ -49,3 +49,20 @@ def test_cpu_baseline_runs_one_oracle_process_per_ensemble():
     spec.levels = [tuple(lv) for lv in bench._sample_levels(spec)]
     spec.ensembles = spec.ensembles[:1]
     assert bench.oracle_configuration(job)["updates"] == u1ml.plan(spec)["updates_per_config"]
+
+
+def test_staple_magnitudes_match_the_oracle():
+    """bench.py's host staple sums (for the heatbath attempt count) give the
+    oracle's |A| on a random 4 x 3 x 5 x 6 lattice."""
+    import numpy as np
+
+    from oracle import oracle as O
+
+    ns, nt = (4, 3, 5), 6
+    lat = O.Lattice(4, list(ns) + [nt], 1.0, seed=3, key_id=0)
+    lat.init(1)
+    th = lat.links()
+    got = bench.staple_abs(th, ns, nt)
+    V = ns[0] * ns[1] * ns[2] * nt
+    want = np.array([abs(lat.staple(s, mu)) for s in range(V) for mu in range(4)])
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
