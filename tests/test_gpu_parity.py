@@ -277,6 +277,37 @@ def test_measurement_and_estimators_match_oracle(env, levels, precision):
     assert np.max(np.abs(got["vac_lin"] - want["vac_lin"])) < (1e-12 if precision == 0 else 1e-6)
 
 
+# (probes, components): the history-form contraction groups (probe, component)
+# slots sharing (l, mode, spans) in blocks of 9, 6, 3 or 1, whichever leaves
+# the fewest empty slots (the larger on a tie); these cases reach each block
+# size (9: 9 probes x 3 components per spans class; 6: 2 probes x 3; 3: 1 probe
+# x 3; 1: one slot)
+SLOT_CASES = {
+    "blocks_of_9": ([(0, p1, p2, 1) for p1 in (-1, 0, 1) for p2 in (-1, 0, 1)], [0, 1, 2, 3, 4, 5]),
+    "blocks_of_6": ([(1, 0, 0, 1), (1, 1, 1, 1)], [0, 1, 2, 3, 4, 5]),
+    "blocks_of_3": ([(-1, 1, 0, 0)], [0, 1, 2, 3, 4, 5]),
+    "block_of_1": ([(0, 1, 1, 1)], [4]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SLOT_CASES))
+@pytest.mark.parametrize("ns,dirs", [((8, 6, 6), [0]), ((6, 8, 6), [1]), ((8, 8, 8), [0, 1, 2])])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_insertion_contraction_slot_blocks_match_oracle(env, case, ns, dirs, precision):
+    """The history-form insertion averages for every slot-block size, along a
+    contiguous axis (x: chunks copied straight into LDS) and strided ones
+    (y, z: staged through registers), against the oracle on the same links
+    (no updates)."""
+    probes, comps = SLOT_CASES[case]
+    say("slot blocks", case, ns, dirs, precision)
+    got, want, ctx, _ = _multilevel_pair(env, ns, 8, [(2, 5, 0)], 3, [1, 2, 3], dirs, probes, comps,
+                                         precision=precision)
+    assert ctx.plan["form"] == env[0].FORM_HISTORY
+    tol_o = 1e-12 if precision == 0 else 1e-5
+    assert np.max(np.abs(got["C"] - want["C"])) < 1e-12
+    assert np.max(np.abs(got["CO"] - want["CO"])) < tol_o * max(1.0, np.abs(want["CO"]).max())
+
+
 @pytest.mark.parametrize("levels", [[(2, 4, 1)], [(4, 2, 1), (2, 3, 1)]])
 def test_multilevel_trajectory_parity_heatbath_only(env, levels):
     """Whole multilevel configurations (updates included) with heatbath-only
