@@ -229,6 +229,8 @@ def parse():
                     help="for kernel traces of the two-level presets: updates of the outer level (0: the preset's)")
     ap.add_argument("--n-ens", type=int, default=0,
                     help="for the replicas preset: number of replicas in the batch (0: the preset's 16)")
+    ap.add_argument("--ins-kernel", type=int, choices=(0, 1, 2), default=0,
+                    help="history-form insertion sums: 0 the planner's choice, 1 the vector kernel, 2 the matrix cores")
     ap.add_argument("--counters", action="store_true",
                     help="for hardware-counter runs: one 256 MiB device copy (calibration of the byte counters), "
                          "then 20 launches each of the heatbath and overrelaxation phases of the dominant kernel")
@@ -522,6 +524,7 @@ def main():
         spec.levels = [tuple(x) for x in lv]
         if args.precision != "workload":
             spec.precision = u1ml.FP32 if args.precision == "f32" else u1ml.FP64
+        spec.ins_kernel = args.ins_kernel
         return spec, sched
 
     spec, sched = make()

@@ -168,6 +168,11 @@ typedef struct {
                             separations whose temporal links share a
                             plaquette (r = 1 or Ns - 1) only the first end;
                             the insertion averages keep the plain links     */
+    int ins_kernel;      /* history-form insertion contraction: 0 the kernel
+                            estimated faster, 1 the vector kernel (FP64 FMA
+                            per work-item), 2 the matrix-core kernel (FP64
+                            MFMA steps; U1ML_ENOTSUP where its chunk does not
+                            fit LDS); both compute the same sums            */
 } u1ml_problem;
 
 /* Planner output (bytes of each workspace section, 256-byte aligned). */
@@ -205,6 +210,12 @@ typedef struct {
                                  form (0 without probes)                    */
     double est_spectral_ms;   /* the same for the spectral form (-1 where it
                                  does not apply); AUTO takes the smaller     */
+    int ins_slots;            /* history form: (probe, component) slots per
+                                 block of the insertion contraction; 8 means
+                                 the matrix-core kernel (16 x 16 x 4 FP64
+                                 MFMA steps), 9, 6, 3 or 1 the vector kernel,
+                                 whichever is estimated faster (0 without
+                                 probes or in the spectral form)             */
 } u1ml_plan_info;
 
 typedef struct u1ml_ctx u1ml_ctx;

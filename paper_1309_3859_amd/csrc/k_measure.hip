@@ -714,6 +714,307 @@ __global__ void __launch_bounds__(kInsThreads, 2) k_contract_ins(
     }
 }
 
+// ---------------------------------------------------------------------------
+// The insertion averages of k_contract_ins on the matrix cores.  For one slot
+// block (kMfSlots slots sharing (l, mode, spans)) and one position y of the
+// displaced lines,
+//   S[(r, c)][(k, kind)] = sum_m T_m^c(y - sh(r), r) O_m(y + ..., k, kind)
+// (c: real or imaginary part of T) is a product of a (separation, part) x
+// measurement matrix and a measurement x (slot, kind) matrix.  A tile
+// (y, 8 separations) is one 16 x 16 FP64 accumulator and every MFMA step
+// (v_mfma_f64_16x16x4) adds 4 measurements.  Lane L of a wave supplies
+// A[i][q] and B[q][j] with i = j = L mod 16, q = L / 16, and holds
+// D[L / 16 + 4 v][L mod 16], v = 0..3.  Row i stands for separation
+// (i mod 4) + 4 (i / 8) of the tile and part (i / 4) mod 2, so that v = 0, 1
+// are the real and imaginary part of separation L / 16 and v = 2, 3 of
+// separation L / 16 + 4; column j is slot j / 2, kind j mod 2.
+// Per chunk of mc measurements (a multiple of 4): the line's phases (16 bytes
+// per work-item) and the O rows (4 bytes per work-item, so any axis and an
+// odd row stride) are copied straight from memory into LDS while the
+// previous chunk is summed; every T_m(x, r) of the chunk is then formed once
+// into LDS; then the MFMA steps.  Measurements past the end add exact zeros
+// (zero T values times finite O words).
+// Work-group: one line, one slab, ins_pbw slot blocks, kMfThreads work-items;
+// tiles (slot block, y, separation octet) in passes of 4 kMfTiles.
+// ---------------------------------------------------------------------------
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+template <typename ot>
+__global__ void __launch_bounds__(kMfThreads, 2) k_contract_mfma(
+    const EnsDesc* __restrict__ ens, const int* __restrict__ bstart, int n_ens, const ObsDesc* __restrict__ obs,
+    const int* __restrict__ rlist, const int* __restrict__ comps, const int* __restrict__ sblk,
+    const double2* __restrict__ hist_c, const ot* __restrict__ hist_o, double2* __restrict__ avg_to, int n_meas,
+    int n_blocks)
+{
+    // double-buffered chunks as separate LDS objects (no wait between the
+    // copies into one and the reads of the other), T values of a chunk
+    __shared__ double2 mph0[kMfPh], mph1[kMfPh];                  // phases [q][x]
+    __shared__ __align__(16) unsigned mob0[kMfOb / 4], mob1[kMfOb / 4];  // O rows [q][row][y], padded
+    __shared__ double mt[kMfT];                                    // T [q][x][r][part]
+    __shared__ int rowoff[kMfRows];  // each O row's element offset within one (measurement, slab) block, -1: empty slot
+    __shared__ int lr[kMfR];
+    // XCD-aware order, as k_contract_ins
+    const int bid = (int)(blockIdx.x & 7u) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3);
+    if (bid >= n_blocks) return;
+    const int e = find_ens_m(bstart, n_ens, bid);
+    const EnsDesc& E = ens[e];
+    const ObsDesc& O = *obs;
+    const int S = E.s_in, s = blockIdx.y;
+    if (s >= S) return;
+    const int id = blockIdx.z;
+    const int dir = O.dirs[id];
+    const int n3[3] = {E.nx, E.ny, E.nz};
+    const int N = n3[dir];
+    const int d1 = dir == 2 ? 0 : dir + 1, d2 = dir == 0 ? 2 : dir - 1;
+    const int nsig = E.nsig, nlines = nsig / N;
+    const int nr = O.n_r, nrt = (nr + 7) >> 3;
+    const int nsb = O.n_pblocks, bpw = E.ins_pbw, nchunk = (nsb + bpw - 1) / bpw;
+    const int local = bid - bstart[e];
+    const int line = local / nchunk, chunk = local - line * nchunk;
+    if (line >= nlines) return;  // uniform
+    const int sb0 = chunk * bpw, nbw = min(bpw, nsb - sb0);
+    const int nrows = nbw * 2 * kMfSlots;
+    const int mc = E.ins_mc;
+    constexpr int W = (int)sizeof(ot) / 4;  // 32-bit words per O element
+    const int a1 = line % n3[d1], a2 = line / n3[d1];
+    const int stride = dir == 0 ? 1 : (dir == 1 ? E.nx : E.nx * E.ny);
+    auto site0 = [&](int o1, int o2) {
+        int c[3];
+        c[dir] = 0;
+        c[d1] = ((a1 + o1) % n3[d1] + n3[d1]) % n3[d1];
+        c[d2] = ((a2 + o2) % n3[d2] + n3[d2]) % n3[d2];
+        return c[0] + E.nx * (c[1] + E.ny * c[2]);
+    };
+    const int base = site0(0, 0);
+    const size_t mstride = (size_t)S * nsig;
+    const size_t mstride_o = (size_t)S * 12 * nsig;
+    const double2* hc = hist_c + E.hc_off + (size_t)s * nsig + base;
+    const ot* ho = hist_o + E.ho_off + (size_t)s * 12 * nsig;
+    const double inv = 1.0 / (double)n_meas;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = kMfThreads / 64;
+    const bool vec = stride == 1 && (N * W) % 4 == 0 && (nsig * W) % 4 == 0 && (E.nx * W) % 4 == 0 &&
+                     (mstride_o * W) % 4 == 0 && (reinterpret_cast<uintptr_t>(ho) & 15) == 0;
+    const int rsd = vec ? N * W + 4 : (N + 1) * W;  // O row stride in LDS (words)
+    const int qd = nrows * rsd;                     // words of one measurement's O rows in LDS
+    for (int j = tid; j < nrows; j += kMfThreads) {
+        const int bl = j / (2 * kMfSlots), rem = j - bl * 2 * kMfSlots, k = rem >> 1, kind = rem & 1;
+        const int* B = sblk + kInsBlkInts * (sb0 + bl);
+        int off = -1;
+        if (k < B[3]) {
+            const int* sl = B + 4 + 4 * k;  // probe, component index, p1, p2
+            off = (2 * comp_orient(comps[sl[1]], dir) + kind) * nsig + site0(sl[2], sl[3]);
+        }
+        rowoff[j] = off;
+    }
+    for (int j = tid; j < nr; j += kMfThreads) lr[j] = rlist[j];
+    // words of the O buffers that no copy writes (empty slots, row padding,
+    // measurements past the end) stay finite: zero at the start, earlier
+    // measurements' O values later
+    for (int j = tid; j < kMfOb / 4; j += kMfThreads) {
+        mob0[j] = 0u;
+        mob1[j] = 0u;
+    }
+    // O rows of a chunk in units of U words: U = 4 (16-byte copies) where the
+    // rows are contiguous and 16-byte aligned in memory (the x axis) and the
+    // LDS row stride is N W + 4 words; else U = 1 with the odd stride
+    // (N + 1) W, whose reads at one y fall in distinct banks.  Unit
+    // u = (q nrows + row) (rsd / U) + c, of which the first N W / U of a row
+    // carry data; each lane walks its units with a carry and keeps the
+    // element offset q mstride_o of its measurement
+    constexpr int VW = 4 / W;  // O elements per 16 bytes
+    const int U = vec ? 4 : 1;
+    const int nru = rsd / U, ndu = N * W / U, qu = nrows * nru;
+    const int ostep = NW * 64;
+    const int odq = ostep / qu, odr = ostep - odq * qu, odrow = odr / nru, odc = odr - odrow * nru;
+    const int ou0 = wv * 64 + lane, oq0 = ou0 / qu, or0 = ou0 - oq0 * qu, orow0 = or0 / nru, oc0 = or0 - orow0 * nru;
+    auto issue = [&](int m0, int mm, double2* php, unsigned* op) {
+        for (int j = wv; j * 64 < mm * N; j += NW) {
+            const int v = j * 64 + lane;
+            if (v < mm * N) {
+                const int q = v / N, x = v - q * N;
+                __builtin_amdgcn_global_load_lds((const void*)(hc + (size_t)(m0 + q) * mstride + (size_t)x * stride),
+                                                 (__attribute__((address_space(3))) void*)(php + j * 64), 16, 0, 0);
+            }
+        }
+        const ot* hm = ho + (size_t)m0 * mstride_o;
+        int q = oq0, row = orow0, c = oc0;
+        size_t qoff = (size_t)oq0 * mstride_o;
+        const size_t dqoff = (size_t)odq * mstride_o;
+        for (int j = wv; j * 64 < mm * qu; j += NW) {
+            if (q < mm && c < ndu) {
+                const int off = rowoff[row];
+                if (off >= 0) {
+                    if (vec) {
+                        __builtin_amdgcn_global_load_lds((const void*)(hm + qoff + off + c * VW),
+                                                         (__attribute__((address_space(3))) void*)(op + j * 256), 16, 0,
+                                                         0);
+                    } else {
+                        const int y = c / W, h = c - y * W;
+                        const unsigned* src = reinterpret_cast<const unsigned*>(hm + qoff + off + (size_t)y * stride) + h;
+                        __builtin_amdgcn_global_load_lds((const void*)src,
+                                                         (__attribute__((address_space(3))) void*)(op + j * 64), 4, 0, 0);
+                    }
+                }
+            }
+            c += odc;
+            if (c >= nru) {
+                c -= nru;
+                ++row;
+            }
+            row += odrow;
+            if (row >= nrows) {
+                row -= nrows;
+                ++q;
+                qoff += mstride_o;
+            }
+            q += odq;
+            qoff += dqoff;
+        }
+    };
+    // T_m(x, r) of a chunk, element f = (q N + x) nr + ir of [q][x][r] for
+    // f = tid, tid + kMfThreads, ... (walked with a carry); zeros for the
+    // measurements that pad the last MFMA step
+    const int tqx = nr * N;
+    const int tdq = kMfThreads / tqx, trm = kMfThreads - tdq * tqx, tdx = trm / nr, tdr = trm - tdx * nr;
+    const int tq0 = tid / tqx, tr0 = tid - tq0 * tqx, tx0 = tr0 / nr, tir0 = tr0 - tx0 * nr;
+    auto form_t = [&](int mm, const double2* ph) {
+        const int mq = (mm + 3) & ~3;
+        int q = tq0, x = tx0, ir = tir0;
+        double2* tp = reinterpret_cast<double2*>(mt);
+#pragma unroll 2
+        for (int f = tid; f < mq * tqx; f += kMfThreads) {
+            double2 t = make_double2(0.0, 0.0);
+            if (q < mm) {
+                int xb = x + lr[ir];
+                xb -= xb >= N ? N : 0;
+                const double2 a = ph[q * N + x], b = ph[q * N + xb];
+                t = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+            }
+            tp[f] = t;
+            ir += tdr;
+            if (ir >= nr) {
+                ir -= nr;
+                ++x;
+            }
+            x += tdx;
+            if (x >= N) {
+                x -= N;
+                ++q;
+            }
+            q += tdq;
+        }
+    };
+    const int g16 = lane & 15, kq = lane >> 4;
+    const int ntile = nbw * N * nrt, cap = NW * kMfTiles;
+    const int nch = (n_meas + mc - 1) / mc;
+    for (int tb = 0; tb < ntile; tb += cap) {
+        const int t0 = tb + wv * kMfTiles;
+        const int ntl = __builtin_amdgcn_readfirstlane(max(0, min(kMfTiles, ntile - t0)));  // uniform for the wave
+        __syncthreads();  // row offsets and separations written; the previous pass done with every buffer
+        // tile t = (bl N + y) nrt + rt: the wave's first by division, the next ones by a carry
+        const int tbl0 = t0 / (N * nrt), trem0 = t0 - tbl0 * N * nrt, ty0 = trem0 / nrt, trt0 = trem0 - ty0 * nrt;
+        auto next_tile = [&](int& bl, int& y, int& rt) {
+            if (++rt == nrt) {
+                rt = 0;
+                if (++y == N) {
+                    y = 0;
+                    ++bl;
+                }
+            }
+        };
+        int a_off[kMfTiles], b_off[kMfTiles];
+        int bl = tbl0, y = ty0, rt = trt0;
+#pragma unroll
+        for (int i = 0; i < kMfTiles; ++i) {
+            if (i > 0 && i < ntl) next_tile(bl, y, rt);
+            const int* B = sblk + kInsBlkInts * (sb0 + min(bl, nbw - 1));
+            const int ir = min(rt * 8 + (g16 & 3) + 4 * (g16 >> 3), nr - 1), c = (g16 >> 2) & 1;
+            const int r = lr[ir];
+            const int sh = B[0] + (B[1] ? (B[2] ? (r - 1) / 2 : r / 2) : 0);
+            int x = (y - sh) % N;
+            x += x < 0 ? N : 0;
+            a_off[i] = (x * nr + ir) * 2 + c;
+            b_off[i] = (min(bl, nbw - 1) * 2 * kMfSlots + g16) * rsd + y * W;
+        }
+        mf_d4 acc[kMfTiles];
+#pragma unroll
+        for (int i = 0; i < kMfTiles; ++i) acc[i] = mf_d4{0.0, 0.0, 0.0, 0.0};
+        auto mfma_chunk = [&](int mm, const unsigned* op) {
+            // the T values of measurements past mm are zero and every O word is finite
+            for (int st = 0; st < mm; st += 4) {
+                const int q = st + kq;
+                const int qa = q * N * nr * 2, qb = q * qd;
+                // operands of 4 tiles at a time, then their 4 steps
+#pragma unroll
+                for (int i0 = 0; i0 < kMfTiles; i0 += 4) {
+                    double av[4], bv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 + u;
+                        if (i < ntl) {
+                            av[u] = mt[qa + a_off[i]];
+                            if constexpr (W == 1) {
+                                bv[u] = (double)__uint_as_float(op[qb + b_off[i]]);
+                            } else {
+                                bv[u] = *reinterpret_cast<const double*>(op + qb + b_off[i]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (i0 + u < ntl)
+                            acc[i0 + u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc[i0 + u], 0, 0, 0);
+                }
+            }
+        };
+        // chunk ci lives in buffers ci mod 2: before its T values are formed,
+        // this wave's copies into it have landed (vmcnt 0) and the barrier
+        // makes every wave's visible and ends the sums over chunk ci - 1,
+        // whose buffers the copies of chunk ci + 1 then overwrite; the second
+        // barrier publishes the T values
+        auto step = [&](int ci, const double2* ph, const unsigned* op, double2* nph, unsigned* nop) {
+            const int mm = min(mc, n_meas - ci * mc);
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+            __syncthreads();
+            if (ci + 1 < nch) issue((ci + 1) * mc, min(mc, n_meas - (ci + 1) * mc), nph, nop);
+            form_t(mm, ph);
+            __syncthreads();
+            mfma_chunk(mm, op);
+        };
+        issue(0, min(mc, n_meas), mph0, mob0);
+        for (int ci = 0; ci < nch; ci += 2) {
+            step(ci, mph0, mob0, mph1, mob1);
+            if (ci + 1 >= nch) break;
+            step(ci + 1, mph1, mob1, mph0, mob0);
+        }
+        bl = tbl0;
+        y = ty0;
+        rt = trt0;
+#pragma unroll
+        for (int i = 0; i < kMfTiles; ++i) {
+            if (i >= ntl) continue;
+            if (i > 0) next_tile(bl, y, rt);
+            const int* B = sblk + kInsBlkInts * (sb0 + bl);
+            const int k = g16 >> 1, kind = g16 & 1;
+            if (k >= B[3]) continue;
+            const int p = B[4 + 4 * k], ic = B[5 + 4 * k];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ir = rt * 8 + kq + 4 * h;
+                if (ir >= nr) continue;
+                const int r = lr[ir];
+                const int sh = B[0] + (B[1] ? (B[2] ? (r - 1) / 2 : r / 2) : 0);
+                int x = (y - sh) % N;
+                x += x < 0 ? N : 0;
+                const size_t kk = ((((size_t)id * nr + ir) * O.n_probe + p) * O.n_comp + ic) * 2 + kind;
+                avg_to[E.ato_off + (kk * S + s) * nsig + base + (size_t)x * stride] =
+                    make_double2(acc[i][2 * h] * inv, acc[i][2 * h + 1] * inv);
+            }
+        }
+    }
+}
+
 hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
                            size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const double2* hist_c,
                            double2* avg_t, int n_meas, int max_slabs, int n_dirs, hipStream_t st)
@@ -733,6 +1034,15 @@ hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_
 #define U1ML_INS(OT, KR, KS)                                                                                          \
     hipLaunchKernelGGL((k_contract_ins<OT, KR, KS>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, d_comp, \
                        d_sblk, hist_c, (const OT*)hist_o, avg_to, n_meas, total_blocks)
+    if (slots_per_block == kMfSlots) {
+        if (precision == 0)
+            hipLaunchKernelGGL(k_contract_mfma<double>, g, dim3(kMfThreads), 0, st, d_ens, d_bstart, n_ens, d_obs, d_r,
+                               d_comp, d_sblk, hist_c, (const double*)hist_o, avg_to, n_meas, total_blocks);
+        else
+            hipLaunchKernelGGL(k_contract_mfma<float>, g, dim3(kMfThreads), 0, st, d_ens, d_bstart, n_ens, d_obs, d_r,
+                               d_comp, d_sblk, hist_c, (const float*)hist_o, avg_to, n_meas, total_blocks);
+        return hipGetLastError();
+    }
     if (precision == 0) {
         switch (slots_per_block) {
         case 9: U1ML_INS(double, ins_kr(9), 9); break;

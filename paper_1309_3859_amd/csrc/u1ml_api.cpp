@@ -82,6 +82,7 @@ struct Problem {
     int form_req = U1ML_FORM_AUTO;
     int update = U1ML_UPDATE_HEATBATH;
     bool multihit = false;
+    int ins_kernel = 0;  // 0: estimated faster, 1: vector, 2: matrix cores
     double metro_delta = 1.0;
     // derived
     int tau_i = 2, n_i = 1, k_i = 1, tau_o = 2, n_o = 1, k_o = 0;
@@ -91,7 +92,12 @@ struct Problem {
     std::vector<int> pgroup;      // probe -> group of probes sharing (l, mode)
     std::vector<int> gdesc;       // group -> (l, mode)
     std::vector<int> pblk;        // insertion contraction: slot blocks, kInsBlkInts ints each
-    int ins_ks = 1;               // insertion contraction: slots per block
+    int ins_ks = 1;               // insertion contraction: slots per block (kMfSlots: matrix cores)
+    // insertion slot keys: (l, mode, spans) and their (probe, component index) slots
+    std::vector<std::vector<std::pair<int, int>>> skeys;
+    std::vector<int> skey_l, skey_mode, skey_spans;
+    int ins_ks_vec = 1;           // the vector kernel's slots per block
+    bool ins_mfma_est = false;    // the matrix-core kernel is estimated faster (and applies)
     long long nd_cfg = 0;
 };
 
@@ -103,6 +109,32 @@ bool fail(std::string* err, const std::string& msg)
 {
     if (err) *err = msg;
     return false;
+}
+
+// slot blocks of ks slots (kInsBlkInts ints each): l, mode, spans, number of
+// slots, then per slot probe, component index, p1, p2
+void pack_slot_blocks(Problem* P, int ks)
+{
+    P->pblk.clear();
+    P->ins_ks = ks;
+    for (size_t kk = 0; kk < P->skeys.size(); ++kk) {
+        const auto& key = P->skeys[kk];
+        for (size_t b = 0; b < key.size(); b += ks) {
+            int blk[kInsBlkInts] = {};
+            blk[0] = P->skey_l[kk];
+            blk[1] = P->skey_mode[kk];
+            blk[2] = P->skey_spans[kk];
+            blk[3] = (int)std::min<size_t>(ks, key.size() - b);
+            for (int k = 0; k < blk[3]; ++k) {
+                const int p = key[b + k].first, ic = key[b + k].second;
+                blk[4 + 4 * k] = p;
+                blk[5 + 4 * k] = ic;
+                blk[6 + 4 * k] = P->probes[p].p1;
+                blk[7 + 4 * k] = P->probes[p].p2;
+            }
+            P->pblk.insert(P->pblk.end(), blk, blk + kInsBlkInts);
+        }
+    }
 }
 
 bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
@@ -118,6 +150,8 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
     P->update = p->update;
     if (p->multihit != 0 && p->multihit != 1) return fail(err, "multihit must be 0 or 1");
     P->multihit = p->multihit == 1;
+    if (p->ins_kernel < 0 || p->ins_kernel > 2) return fail(err, "ins_kernel must be 0, 1 or 2");
+    P->ins_kernel = p->ins_kernel;
     P->metro_delta = p->metro_delta;
     if (p->n_levels < 1 || p->n_levels > 2) return fail(err, "n_levels must be 1 or 2");
     if (p->max_configs < 1) return fail(err, "max_configs must be >= 1");
@@ -218,55 +252,41 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
         }
         P->pgroup.push_back(g);
     }
-    // slot blocks of the insertion contraction: the (probe, component) pairs
+    // slot keys of the insertion contraction: the (probe, component) pairs
     // of each probe group whose plaquettes span the axis, then those whose
-    // plaquettes do not (probes, then components, in problem order), KS at a
-    // time; KS in {9, 6, 3, 1} leaves the fewest empty slots (the larger on a tie)
-    P->pblk.clear();
-    P->ins_ks = 1;
-    {
-        std::vector<std::vector<std::pair<int, int>>> keys;  // slots (probe, component index) per key
-        std::vector<int> key_l, key_mode, key_spans;
-        for (int g = 0; g < (int)P->gdesc.size() / 2; ++g)
-            for (int sp = 1; sp >= 0; --sp) {
-                std::vector<std::pair<int, int>> slots;
-                for (int p = 0; p < (int)P->probes.size(); ++p)
-                    if (P->pgroup[p] == g)
-                        for (int ic = 0; ic < (int)P->comps.size(); ++ic)
-                            if ((int)comp_spans_axis_host(P->comps[ic]) == sp) slots.emplace_back(p, ic);
-                if (slots.empty()) continue;
-                keys.push_back(slots);
-                key_l.push_back(P->gdesc[2 * g]);
-                key_mode.push_back(P->gdesc[2 * g + 1]);
-                key_spans.push_back(sp);
-            }
-        size_t best = ~(size_t)0;
-        for (int ks : {9, 6, 3, 1}) {
-            size_t padded = 0;
-            for (const auto& k : keys) padded += (k.size() + ks - 1) / ks * ks;
-            if (padded < best) {
-                best = padded;
-                P->ins_ks = ks;
-            }
+    // plaquettes do not (probes, then components, in problem order); blocks
+    // of KS slots of one key, KS in {9, 6, 3, 1} leaving the fewest empty
+    // slots (the larger on a tie), or kMfSlots for the matrix-core kernel
+    // (the planner's choice, pack_slot_blocks)
+    P->skeys.clear();
+    P->skey_l.clear();
+    P->skey_mode.clear();
+    P->skey_spans.clear();
+    for (int g = 0; g < (int)P->gdesc.size() / 2; ++g)
+        for (int sp = 1; sp >= 0; --sp) {
+            std::vector<std::pair<int, int>> slots;
+            for (int p = 0; p < (int)P->probes.size(); ++p)
+                if (P->pgroup[p] == g)
+                    for (int ic = 0; ic < (int)P->comps.size(); ++ic)
+                        if ((int)comp_spans_axis_host(P->comps[ic]) == sp) slots.emplace_back(p, ic);
+            if (slots.empty()) continue;
+            P->skeys.push_back(slots);
+            P->skey_l.push_back(P->gdesc[2 * g]);
+            P->skey_mode.push_back(P->gdesc[2 * g + 1]);
+            P->skey_spans.push_back(sp);
         }
-        const int ks = P->ins_ks;
-        for (size_t kk = 0; kk < keys.size(); ++kk)
-            for (size_t b = 0; b < keys[kk].size(); b += ks) {
-                int blk[kInsBlkInts] = {};
-                blk[0] = key_l[kk];
-                blk[1] = key_mode[kk];
-                blk[2] = key_spans[kk];
-                blk[3] = (int)std::min<size_t>(ks, keys[kk].size() - b);
-                for (int k = 0; k < blk[3]; ++k) {
-                    const int p = keys[kk][b + k].first, ic = keys[kk][b + k].second;
-                    blk[4 + 4 * k] = p;
-                    blk[5 + 4 * k] = ic;
-                    blk[6 + 4 * k] = P->probes[p].p1;
-                    blk[7 + 4 * k] = P->probes[p].p2;
-                }
-                P->pblk.insert(P->pblk.end(), blk, blk + kInsBlkInts);
-            }
+    size_t best = ~(size_t)0;
+    int best_ks = 1;
+    for (int ks : {9, 6, 3, 1}) {
+        size_t padded = 0;
+        for (const auto& k : P->skeys) padded += (k.size() + ks - 1) / ks * ks;
+        if (padded < best) {
+            best = padded;
+            best_ks = ks;
+        }
     }
+    P->ins_ks_vec = best_ks;
+    pack_slot_blocks(P, best_ks);
     return true;
 }
 
@@ -309,7 +329,12 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     // the spectral form does not apply, spectral when the history form's
     // per-site averages would exceed 64 GiB); the unit costs are MI355X
     // measurements (FP32 links):
-    //   history:  contraction 6.6e12 FMA/s (the inner level's [TO] sums);
+    //   history:  contraction 6.6e12 FMA/s (the inner level's [TO] sums,
+    //             vector kernel) or 0.18 of the FP64 matrix-core peak per
+    //             16 x 16 x 4 step, padding included (matrix-core kernel:
+    //             3.25 ms on the 24^3x8 workload below against 1.97 for the
+    //             vector kernel; a plain stream of these steps runs at 46
+    //             TFLOP/s on MI355X, FP64 vector FMA at 61);
     //             two levels: the inner averages folded into the outer sums,
     //             3 passes over them per outer update at 3 TB/s;
     //   spectral: per measurement 20 us of launches, 14.2 ps per plane
@@ -321,16 +346,24 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     // levels 2 x 10, 1 probe 8.8 / 21.5, 8 probes 39.9 / 21.6.
     {
         bool plane_ok = true;
-        double hist_avg = 0.0, est_h = 0.0, est_s = 0.0;
-        const double n_meas = (double)P.n_i * P.k_i * (P.two ? P.n_o : 1);
+        double hist_avg = 0.0, est_h = 0.0, est_s = 0.0, est_v = 0.0, est_m = 0.0;
+        const double n_meas = (double)P.n_i * (P.two ? P.n_o : 1);
+        const double n_steps = (double)((P.n_i + 3) / 4) * (P.two ? P.n_o : 1);  // MFMA steps of 4 measurements
+        size_t nblk8 = 0;
+        for (const auto& k : P.skeys) nblk8 += (k.size() + kMfSlots - 1) / kMfSlots;
+        const int word_o = P.precision == U1ML_FP64 ? 8 : 4;
+        bool mf_ok = R <= (size_t)kMfR;
         for (const u1ml_ensemble& E : P.ens) {
             const double nsig = (double)E.ns[0] * E.ns[1] * E.ns[2];
             for (int i = 0; i < P.n_dirs; ++i)
                 if (nsig / E.ns[P.dirs[i]] > 4096.0) plane_ok = false;
+            const int nmax = std::max(E.ns[0], std::max(E.ns[1], E.ns[2]));  // as the contraction is sized
+            if (!mf_chunk_fits(4, nmax, (int)R, 2 * kMfSlots, word_o)) mf_ok = false;
             const double per = (double)nd * R * Np * Nc * 2 * nsig * 16.0;
             const double si = (double)(E.nt / P.tau_i);
             hist_avg += per * si + (P.two ? per * (E.nt / P.tau_o) : 0.0);
-            est_h += n_meas * nd * si * nsig * R * Np * Nc * 4.0 / 6.6e12;
+            est_v += n_meas * nd * si * nsig * R * Np * Nc * 4.0 / 6.6e12;
+            est_m += n_steps * nd * si * nsig * (double)((R + 7) / 8) * nblk8 * 1024.0 / (0.18 * 39.3e12);
             if (P.two) est_h += (double)P.n_o * per * si * 3.0 / 3.0e12;
             est_s += n_meas * (20e-6 + nd * si * nsig * (R + 12) * 14.2e-12 + nd * si * (double)NG * nsig * R * Nc * 16.0 * 0.198e-12);
             if (P.two) {
@@ -341,6 +374,8 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
                 est_s += upd / 5e10;
             }
         }
+        P.ins_mfma_est = Np && (P.ins_kernel == 2 || (P.ins_kernel == 0 && mf_ok && est_m < est_v));
+        est_h += P.ins_mfma_est ? est_m : est_v;
         P.est_hist_ms = Np ? est_h * 1e3 : 0.0;
         P.est_spec_ms = (Np && plane_ok) ? est_s * 1e3 : -1.0;
         if (P.form_req == U1ML_FORM_SPECTRAL) {
@@ -351,6 +386,11 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
         } else {
             P.spectral = false;
         }
+    }
+    // slot blocks for the kernel that sums the history form
+    if (Np && !P.spectral) {
+        const int ks = P.ins_mfma_est ? kMfSlots : P.ins_ks_vec;
+        if (P.ins_ks != ks) pack_slot_blocks(&P, ks);
     }
     const bool spec = P.spectral;
     size_t L = 0, HC = 0, HO = 0, AT = 0, ATO = 0, OT = 0, OTO = 0, VAC = 0, PP = 0;
@@ -557,6 +597,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
         info->launches_per_config = (long)body_launches(P);
         info->est_history_ms = P.est_hist_ms;
         info->est_spectral_ms = P.est_spec_ms;
+        info->ins_slots = (!P.probes.empty() && !P.spectral) ? P.ins_ks : 0;
     }
     return true;
 }
@@ -1360,7 +1401,30 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         const size_t fit = (size_t)kConLds / ((size_t)E.con_lpb * nmax * per);
         E.con_mc = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)P.n_i));
         c->con_lds = std::max(c->con_lds, (size_t)E.con_lpb * E.con_mc * nmax * per);
-        if (!P.probes.empty() && !P.spectral) {
+        if (!P.probes.empty() && !P.spectral && P.ins_ks == kMfSlots) {
+            // matrix-core kernel: kMfThreads work-items, (slot block, y, 8
+            // separations) tiles, up to 4 kMfTiles per pass over the
+            // measurements; as many slot blocks per work-group as one pass
+            // holds, fewer while a chunk would hold fewer than 8 measurements;
+            // chunks of a multiple of 4 measurements
+            const int nsb = (int)(P.pblk.size() / kInsBlkInts);
+            const int unit = (int)(nmax * ((R + 7) / 8));
+            const int cap = (kMfThreads / 64) * kMfTiles;
+            E.ins_pbw = std::max(1, std::min(std::min(nsb, cap / std::max(1, unit)), kMfRows / (2 * kMfSlots)));
+            auto fit_mc = [&](int bpw) {
+                int mc = (std::min(P.n_i, kMfPh) + 3) / 4 * 4;
+                while (mc > 4 && !mf_chunk_fits(mc, (int)nmax, (int)R, bpw * 2 * kMfSlots, (int)word)) mc -= 4;
+                return mc;
+            };
+            while (E.ins_pbw > 1 && fit_mc(E.ins_pbw) < std::min(8, (P.n_i + 3) / 4 * 4)) --E.ins_pbw;
+            const int mc = fit_mc(E.ins_pbw);
+            if (!mf_chunk_fits(mc, (int)nmax, (int)R, E.ins_pbw * 2 * kMfSlots, (int)word)) {
+                release(c);
+                return set_err(nullptr, U1ML_ENOTSUP, "history-form insertions: matrix-core chunk does not fit LDS");
+            }
+            c->ins_block = kMfThreads;
+            E.ins_mc = mc;
+        } else if (!P.probes.empty() && !P.spectral) {
             const int nsb = (int)(P.pblk.size() / kInsBlkInts);
             const int ks = P.ins_ks, kr = ins_kr(ks);
             const int unit = (int)(nmax * ((R + kr - 1) / kr));  // tasks of one slot block

@@ -86,6 +86,32 @@ __host__ __device__ inline bool ins_chunk_fits(int mc, int N, int nrows, int wor
     return ph <= (size_t)kInsPh && ob <= (size_t)kInsOb;
 }
 
+// The same sums on the matrix cores: for one position y of a slot block the
+// sums over measurements are a product of a (separation, re/im) x measurement
+// matrix of T values and a measurement x (slot, kind) matrix of O values, one
+// 16 x 16 FP64 tile per 8 separations and 8 slots, 4 measurements per MFMA
+// step.  Slot blocks of kMfSlots; a work-group of kMfThreads work-items keeps
+// kMfTiles tiles per wave; per chunk of measurements the LDS holds the line's
+// phases and O rows (copied straight from memory, double-buffered) and the T
+// values of every (measurement, x, separation) computed once from the phases.
+constexpr int kMfSlots = 8;
+constexpr int kMfThreads = 256;
+constexpr int kMfTiles = 12;   // accumulator tiles per wave (4 FP64 each per work-item)
+constexpr int kMfPh = 256;     // phases of one chunk buffer (16-byte vectors)
+constexpr int kMfOb = 16384;   // O rows of one chunk buffer (bytes)
+constexpr int kMfT = 4608;     // T values of a chunk (doubles)
+constexpr int kMfRows = 256;   // O rows (slot block, slot, kind) of one work-group
+constexpr int kMfR = 64;       // separations
+// O rows in LDS: [q][row][y] with a row stride of at most the row's words
+// plus 4 (16-byte copies; else one element more than the row, an odd
+// stride whose reads at one y fall in distinct banks)
+__host__ __device__ inline int mf_row_dwords(int N, int word) { return N * (word / 4) + 4; }
+__host__ __device__ inline bool mf_chunk_fits(int mc, int N, int R, int nrows, int word)
+{
+    return (size_t)mc * N <= (size_t)kMfPh && (size_t)mc * nrows * mf_row_dwords(N, word) * 4 <= (size_t)kMfOb &&
+           (size_t)mc * N * 2 * R <= (size_t)kMfT && nrows <= kMfRows && R <= kMfR;
+}
+
 constexpr int kUpdateClasses = 4;  // temporal, spatial full, spatial inner tau, spatial outer tau
 constexpr int kProdChunk = 2048;    // slab products: (axis, site) items per work-group
 constexpr int kProdQ = 26;          // slab products: correlator re, im and 12 insertion quantities re, im
@@ -129,7 +155,8 @@ hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens,
                            size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const double2* hist_c,
                            double2* avg_t, int n_meas, int max_slabs, int n_dirs, hipStream_t st);
 // insertion averages [TO] of the inner level from the stored measurements
-// work-groups of `block` threads; slots_per_block selects the kernel's tile (KS, ins_kr(KS))
+// work-groups of `block` threads; slots_per_block selects the kernel's tile (KS, ins_kr(KS)),
+// kMfSlots the matrix-core kernel
 hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
                                size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_comp,
                                const int* d_sblk, int slots_per_block, const double2* hist_c, const void* hist_o,

@@ -52,7 +52,7 @@ class _Problem(C.Structure):
         ("n_levels", C.c_int), ("levels", _Level * 2), ("n_dirs", C.c_int), ("dirs", C.c_int * 3),
         ("n_r", C.c_int), ("r", C.POINTER(C.c_int)), ("n_probe", C.c_int), ("probes", C.POINTER(_Probe)),
         ("n_comp", C.c_int), ("comps", C.POINTER(C.c_int)), ("max_configs", C.c_int), ("form", C.c_int),
-        ("update", C.c_int), ("metro_delta", C.c_double), ("multihit", C.c_int),
+        ("update", C.c_int), ("metro_delta", C.c_double), ("multihit", C.c_int), ("ins_kernel", C.c_int),
     ]
 
 
@@ -63,7 +63,7 @@ class _PlanInfo(C.Structure):
         ("scratch_bytes", C.c_size_t), ("paper_running_bytes", C.c_size_t), ("n_doubles_per_config", C.c_long),
         ("updates_per_config", C.c_long), ("updates_per_sweep", C.c_long), ("form", C.c_int),
         ("spectral_bytes", C.c_size_t), ("launches_per_config", C.c_long), ("est_history_ms", C.c_double),
-        ("est_spectral_ms", C.c_double),
+        ("est_spectral_ms", C.c_double), ("ins_slots", C.c_int),
     ]
 
 
@@ -164,6 +164,7 @@ class Spec:
     update: int = 0  # UPDATE_HEATBATH
     metro_delta: float = 1.0
     multihit: bool = False
+    ins_kernel: int = 0  # history-form insertion contraction: 0 auto, 1 vector, 2 matrix cores
     _keep: list = field(default_factory=list, repr=False)
 
     def struct(self) -> _Problem:
@@ -194,6 +195,7 @@ class Spec:
         p.update = self.update
         p.metro_delta = self.metro_delta
         p.multihit = int(bool(self.multihit))
+        p.ins_kernel = int(self.ins_kernel)
         return p
 
     def n_doubles_per_config(self) -> int:

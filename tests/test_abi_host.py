@@ -206,3 +206,30 @@ def test_large_bodies_are_launched_directly(u1):
     assert n["c3"] > 8192
     # C5 (two levels, spectral, replayed): two passes of 40 x (32 + 100 x 33) launches
     assert n["c5"] > 2 * 40 * (32 + 100 * 33)
+
+
+def test_insertion_kernel_choice(u1):
+    """The history form's insertion sums run on the vector kernel (slot blocks
+    of 9, 6, 3 or 1) or on the matrix cores (blocks of 8), whichever is
+    estimated faster: on the 24^3x8 workload with 9 probes x 6 components x
+    11 separations the vector kernel (1.97 ms per configuration on MI355X
+    against 3.25 ms); either can be asked for, and the matrix-core kernel only
+    where its chunk fits LDS (the estimate does not take it otherwise)."""
+    from paper_1309_3859_amd import configs
+
+    spec, _ = configs.c2_fp32_profiles()
+    auto = u1.plan(spec)
+    assert auto["ins_slots"] == 9
+    spec.ins_kernel = 2
+    mf = u1.plan(spec)
+    assert mf["ins_slots"] == 8 and mf["est_history_ms"] > auto["est_history_ms"]
+    spec.ins_kernel = 1
+    assert u1.plan(spec)["ins_slots"] == 9
+    spec.ins_kernel = 3
+    with pytest.raises(u1.U1MLError, match="EINVAL"):
+        u1.plan(spec)
+    # no probes: no insertion kernel; the spectral form: none either
+    assert u1.plan(configs.c4_batched()[0])["ins_slots"] == 0
+    s, _ = configs.c5_largest(n_outer=2, n_inner=10)
+    p = u1.plan(s)
+    assert p["form"] == u1.FORM_SPECTRAL and p["ins_slots"] == 0

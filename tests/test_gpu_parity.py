@@ -42,7 +42,8 @@ def env():
 def _ctx(u1, ns, nt, beta=1.0, levels=((4, 1, 1), (2, 1, 1)), precision=0, n_or=3, seed=1, key_id=0, **kw):
     spec = u1.Spec(ensembles=[u1.Ens(tuple(ns), nt, beta, seed=seed, key_id=key_id)], levels=list(levels),
                    r=kw.pop("r", [1]), dirs=kw.pop("dirs", [0]), probes=kw.pop("probes", ()),
-                   comps=kw.pop("comps", ()), precision=precision, n_or=n_or, max_configs=kw.pop("max_configs", 4))
+                   comps=kw.pop("comps", ()), precision=precision, n_or=n_or, max_configs=kw.pop("max_configs", 4),
+                   ins_kernel=kw.pop("ins_kernel", 0))
     return spec, u1.Context(spec)
 
 
@@ -236,11 +237,12 @@ def test_first_sweep_of_c1_within_1e12(env):
     assert d.max() < 1e-12
 
 
-def _multilevel_pair(env, ns, nt, levels, n_or, r, dirs, probes, comps, beta=1.0, seed=3, precision=0, start_seed=21):
+def _multilevel_pair(env, ns, nt, levels, n_or, r, dirs, probes, comps, beta=1.0, seed=3, precision=0, start_seed=21,
+                     ins_kernel=0):
     u1, O, torch = env
     V = int(np.prod(ns)) * nt
     spec, ctx = _ctx(u1, ns, nt, beta=beta, levels=levels, n_or=n_or, r=r, dirs=dirs, probes=probes, comps=comps,
-                     seed=seed, precision=precision)
+                     seed=seed, precision=precision, ins_kernel=ins_kernel)
     ref = O.Lattice(4, list(ns) + [nt], beta, seed=seed)
     th = random_links_fp32(V, start_seed) if precision else random_links(V, start_seed)
     ctx.set_links(th)
@@ -293,19 +295,65 @@ SLOT_CASES = {
 @pytest.mark.parametrize("case", sorted(SLOT_CASES))
 @pytest.mark.parametrize("ns,dirs", [((8, 6, 6), [0]), ((6, 8, 6), [1]), ((8, 8, 8), [0, 1, 2])])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_insertion_contraction_slot_blocks_match_oracle(env, case, ns, dirs, precision):
-    """The history-form insertion averages for every slot-block size, along a
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_insertion_contraction_slot_blocks_match_oracle(env, case, ns, dirs, precision, kernel):
+    """The history-form insertion averages for every slot-block size of the
+    vector kernel (kernel 1) and the matrix-core kernel's blocks of 8 slots
+    (kernel 2, several blocks per work-group on these short lines), along a
     contiguous axis (x: chunks copied straight into LDS) and strided ones
-    (y, z: staged through registers), against the oracle on the same links
-    (no updates)."""
+    (y, z), against the oracle on the same links (no updates)."""
     probes, comps = SLOT_CASES[case]
-    say("slot blocks", case, ns, dirs, precision)
+    say("slot blocks", case, ns, dirs, precision, kernel)
     got, want, ctx, _ = _multilevel_pair(env, ns, 8, [(2, 5, 0)], 3, [1, 2, 3], dirs, probes, comps,
-                                         precision=precision)
+                                         precision=precision, ins_kernel=kernel)
     assert ctx.plan["form"] == env[0].FORM_HISTORY
+    assert (ctx.plan["ins_slots"] == 8) == (kernel == 2), ctx.plan["ins_slots"]
     tol_o = 1e-12 if precision == 0 else 1e-5
     assert np.max(np.abs(got["C"] - want["C"])) < 1e-12
     assert np.max(np.abs(got["CO"] - want["CO"])) < tol_o * max(1.0, np.abs(want["CO"]).max())
+
+
+# matrix-core contraction shapes: (lattice, axes, separations, levels, precision)
+#   two separation octets on a 24-site line (one pass of 48 tiles), updates
+#   between the 13 measurements (FP64 O rows: chunks of 4, the last one ragged);
+#   a strided 32-site axis with 9 separations (64 tiles: two passes; FP32 O
+#   rows, as FP64 rows of 32 sites exceed the chunk buffer);
+#   FP32 O rows on the 24-site line (9 identical measurements: chunks of 8)
+MFMA_CASES = {
+    "octets_x": ((24, 6, 6), [0], list(range(1, 12)), [(2, 13, 1)], 0),
+    "octets_x_still": ((24, 6, 6), [0], list(range(1, 12)), [(2, 5, 0)], 0),
+    "passes_y": ((4, 32, 6), [1], list(range(1, 10)), [(2, 6, 1)], 1),
+    "fp32_o": ((24, 6, 6), [0], list(range(1, 12)), [(2, 9, 0)], 1),
+    "two_levels": ((24, 6, 4), [0], list(range(1, 12)), [(4, 2, 1), (2, 5, 1)], 0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(MFMA_CASES))
+def test_insertion_contraction_matrix_cores_match_oracle(env, case):
+    """The matrix-core kernel on the shapes that exercise its tiling: more
+    than 8 separations, lines of up to 32 sites, several passes over the
+    measurements, chunks cut short, both O precisions.  With updates between
+    the measurements (every measurement differs) it is compared with the
+    vector kernel on the same device trajectory (the update kernels are the
+    same, so the links are bit-identical and only the order of the FP64 sums
+    differs); without updates also with the oracle."""
+    u1, O, torch = env
+    ns, dirs, r, levels, precision = MFMA_CASES[case]
+    say("matrix-core contraction", case)
+    got, want, ctx, _ = _multilevel_pair(env, ns, 8, levels, 0, r, dirs, PROBES, [0, 1, 2, 3, 4, 5],
+                                         precision=precision, ins_kernel=2)
+    assert ctx.plan["form"] == u1.FORM_HISTORY and ctx.plan["ins_slots"] == 8
+    vec, _, ctx_v, _ = _multilevel_pair(env, ns, 8, levels, 0, r, dirs, PROBES, [0, 1, 2, 3, 4, 5],
+                                        precision=precision, ins_kernel=1)
+    assert ctx_v.plan["ins_slots"] != 8
+    assert np.array_equal(ctx.links(0), ctx_v.links(0))
+    assert np.array_equal(got["C"], vec["C"])
+    scale = max(1.0, np.abs(vec["CO"]).max())
+    assert np.max(np.abs(got["CO"] - vec["CO"])) < 1e-12 * scale
+    if all(lv[2] == 0 for lv in levels):
+        tol = 1e-12 if precision == 0 else 1e-5
+        assert np.max(np.abs(got["C"] - want["C"])) < 1e-12
+        assert np.max(np.abs(got["CO"] - want["CO"])) < tol * max(1.0, np.abs(want["CO"]).max())
 
 
 @pytest.mark.parametrize("levels", [[(2, 4, 1)], [(4, 2, 1), (2, 3, 1)]])
