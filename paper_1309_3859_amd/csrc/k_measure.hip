@@ -479,7 +479,7 @@ __device__ inline void stage_o_rows(ot* __restrict__ ol, const ot* __restrict__ 
     }
 }
 
-template <typename ot, int KR, int KS>
+template <typename ot, int KR, int KS, int NC>
 __global__ void __launch_bounds__(kInsThreads, 2) k_contract_ins(
     const EnsDesc* __restrict__ ens, const int* __restrict__ bstart, int n_ens, const ObsDesc* __restrict__ obs,
     const int* __restrict__ rlist, const int* __restrict__ comps, const int* __restrict__ sblk,
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(kInsThreads, 2) k_contract_ins(
     const int id = blockIdx.z;
     const int dir = O.dirs[id];
     const int n3[3] = {E.nx, E.ny, E.nz};
-    const int N = n3[dir];
+    const int N = NC ? NC : n3[dir];  // NC: every line of the launch has NC sites (constant LDS offsets)
     const int d1 = dir == 2 ? 0 : dir + 1, d2 = dir == 0 ? 2 : dir - 1;  // (dir + 1) % 3, (dir + 2) % 3
     const int nsig = E.nsig, nlines = nsig / N;
     const int nr = O.n_r, nrb = (nr + KR - 1) / KR;
@@ -1027,13 +1027,20 @@ hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens,
 hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
                                size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_comp,
                                const int* d_sblk, int slots_per_block, const double2* hist_c, const void* hist_o,
-                               double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st)
+                               double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, int line_len,
+                               hipStream_t st)
 {
     if (total_blocks <= 0) return hipSuccess;
     const dim3 g((total_blocks + 7) / 8 * 8, max_slabs, n_dirs), b(block);
 #define U1ML_INS(OT, KR, KS)                                                                                          \
-    hipLaunchKernelGGL((k_contract_ins<OT, KR, KS>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs, d_r, d_comp, \
-                       d_sblk, hist_c, (const OT*)hist_o, avg_to, n_meas, total_blocks)
+    do {                                                                                                              \
+        if (line_len == 24)                                                                                           \
+            hipLaunchKernelGGL((k_contract_ins<OT, KR, KS, 24>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,   \
+                               d_r, d_comp, d_sblk, hist_c, (const OT*)hist_o, avg_to, n_meas, total_blocks);         \
+        else                                                                                                          \
+            hipLaunchKernelGGL((k_contract_ins<OT, KR, KS, 0>), g, b, lds_bytes, st, d_ens, d_bstart, n_ens, d_obs,    \
+                               d_r, d_comp, d_sblk, hist_c, (const OT*)hist_o, avg_to, n_meas, total_blocks);         \
+    } while (0)
     if (slots_per_block == kMfSlots) {
         if (precision == 0)
             hipLaunchKernelGGL(k_contract_mfma<double>, g, dim3(kMfThreads), 0, st, d_ens, d_bstart, n_ens, d_obs, d_r,

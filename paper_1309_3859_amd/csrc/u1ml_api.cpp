@@ -670,6 +670,7 @@ struct u1ml_ctx {
     int *d_pgroup = nullptr, *d_gdesc = nullptr, *d_pblk = nullptr;
     size_t ins_lds = 0;  // insertion contraction dynamic LDS per work-group
     int ins_block = 64;  // insertion contraction work-group size
+    int ins_line_len = 0;  // sites of every charge-axis line of every ensemble where they are all the same, else 0
     uint32_t* d_upd = nullptr;
     unsigned long long* d_count = nullptr;
     double* static_partials = nullptr;  // the library's static scratch on this context's device
@@ -999,7 +1000,7 @@ hipError_t enq_levels(u1ml_ctx* c, const Lane& L, hipStream_t st, bool store_o, 
         if (e == hipSuccess && ins_hist)
             e = launch_contract_ins(L.d_ens, L.tab_dev(kTabIns), n, L.tab_total(kTabIns), c->ins_block, c->ins_lds,
                                     c->d_obs, c->d_r, c->d_comp, c->d_pblk, P.ins_ks, c->hc, c->ho, c->ato, P.n_i,
-                                    P.precision, L.max_s_in, P.n_dirs, st);
+                                    P.precision, L.max_s_in, P.n_dirs, c->ins_line_len, st);
         if (e == hipSuccess && P.two && !spec_acc)
             e = launch_combine(L.d_ens, L.tab_dev(kTabComb), n, L.tab_total(kTabComb), c->d_obs, c->at,
                                ins_hist ? c->ato : nullptr, c->ot, ins_hist ? c->oto : nullptr, P.tau_o / P.tau_i, st);
@@ -1401,6 +1402,12 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
         const size_t fit = (size_t)kConLds / ((size_t)E.con_lpb * nmax * per);
         E.con_mc = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)P.n_i));
         c->con_lds = std::max(c->con_lds, (size_t)E.con_lpb * E.con_mc * nmax * per);
+        {
+            const int len0 = n3[P.dirs[0]];
+            bool same = e == 0 || c->ins_line_len == len0;
+            for (int i = 0; i < P.n_dirs; ++i) same = same && n3[P.dirs[i]] == len0;
+            c->ins_line_len = same ? len0 : 0;
+        }
         if (!P.probes.empty() && !P.spectral && P.ins_ks == kMfSlots) {
             // matrix-core kernel: kMfThreads work-items, (slot block, y, 8
             // separations) tiles, up to 4 kMfTiles per pass over the

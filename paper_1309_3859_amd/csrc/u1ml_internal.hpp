@@ -156,11 +156,13 @@ hipError_t launch_contract(const EnsDesc* d_ens, const int* d_bstart, int n_ens,
                            double2* avg_t, int n_meas, int max_slabs, int n_dirs, hipStream_t st);
 // insertion averages [TO] of the inner level from the stored measurements
 // work-groups of `block` threads; slots_per_block selects the kernel's tile (KS, ins_kr(KS)),
-// kMfSlots the matrix-core kernel
+// kMfSlots the matrix-core kernel; line_len: the sites of every line of the launch where they
+// are all the same (24 selects a build with constant LDS offsets), else 0
 hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, int block,
                                size_t lds_bytes, const ObsDesc* d_obs, const int* d_r, const int* d_comp,
                                const int* d_sblk, int slots_per_block, const double2* hist_c, const void* hist_o,
-                               double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, hipStream_t st);
+                               double2* avg_to, int n_meas, int precision, int max_slabs, int n_dirs, int line_len,
+                               hipStream_t st);
 hipError_t launch_combine(const EnsDesc* d_ens, const int* d_bstart, int n_ens, int total_blocks, const ObsDesc* d_obs,
                           const double2* avg_t, const double2* avg_to, double2* out_t, double2* out_to, int q,
                           hipStream_t st);
