@@ -167,9 +167,15 @@ template <typename real, bool MULTIHIT>
 __global__ void __launch_bounds__(256) k_measure(const EnsDesc* __restrict__ ens, const int2* __restrict__ bmap,
                                                  const real* __restrict__ links, double2* __restrict__ hist_c,
                                                  real* __restrict__ hist_o, double* __restrict__ vac_part, int m_in,
-                                                 int m, int tau, int store_o)
+                                                 int m, int tau, int store_o, int n_blocks)
 {
-    const int2 be = bmap[blockIdx.x];
+    // XCD-aware order: the hardware deals consecutive work-groups to the eight
+    // XCDs in turn, so work-group b takes block (b mod 8) G/8 + b/8 of the map
+    // (G, a multiple of 8, launched): each XCD measures a contiguous run of
+    // sites and finds the neighbours' links in its own L2
+    const int bid = (int)(blockIdx.x & 7u) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3);
+    if (bid >= n_blocks) return;  // uniform: padding of the launch to a multiple of 8
+    const int2 be = bmap[bid];
     const EnsDesc& E = ens[be.x];
     const int nsig = E.nsig, S = E.s_in;
     const int item = be.y * 256 + (int)threadIdx.x;
@@ -277,23 +283,24 @@ hipError_t launch_measure(const EnsDesc* d_ens, const int2* d_bmap, int total_bl
                           double2* hist_c, void* hist_o, double* vac_part, int m_in, int m, int tau, int store_o,
                           int multihit, hipStream_t st)
 {
-    const dim3 g(total_blocks), b(256);
+    if (total_blocks <= 0) return hipSuccess;
+    const dim3 g((total_blocks + 7) / 8 * 8), b(256);
     if (precision == 0) {
         const double* l = (const double*)links;
         if (multihit)
             hipLaunchKernelGGL((k_measure<double, true>), g, b, 0, st, d_ens, d_bmap, l, hist_c, (double*)hist_o,
-                               vac_part, m_in, m, tau, store_o);
+                               vac_part, m_in, m, tau, store_o, total_blocks);
         else
             hipLaunchKernelGGL((k_measure<double, false>), g, b, 0, st, d_ens, d_bmap, l, hist_c, (double*)hist_o,
-                               vac_part, m_in, m, tau, store_o);
+                               vac_part, m_in, m, tau, store_o, total_blocks);
     } else {
         const float* l = (const float*)links;
         if (multihit)
             hipLaunchKernelGGL((k_measure<float, true>), g, b, 0, st, d_ens, d_bmap, l, hist_c, (float*)hist_o,
-                               vac_part, m_in, m, tau, store_o);
+                               vac_part, m_in, m, tau, store_o, total_blocks);
         else
             hipLaunchKernelGGL((k_measure<float, false>), g, b, 0, st, d_ens, d_bmap, l, hist_c, (float*)hist_o,
-                               vac_part, m_in, m, tau, store_o);
+                               vac_part, m_in, m, tau, store_o, total_blocks);
     }
     return hipGetLastError();
 }
