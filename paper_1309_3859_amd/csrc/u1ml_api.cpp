@@ -332,7 +332,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     //   history:  contraction 6.6e12 FMA/s (the inner level's [TO] sums,
     //             vector kernel) or 0.18 of the FP64 matrix-core peak per
     //             16 x 16 x 4 step, padding included (matrix-core kernel:
-    //             3.25 ms on the 24^3x8 workload below against 1.97 for the
+    //             3.3 ms per launch on the 24^3x8 workload below against 1.8 for the
     //             vector kernel; a plain stream of these steps runs at 46
     //             TFLOP/s on MI355X, FP64 vector FMA at 61);
     //             two levels: the inner averages folded into the outer sums,
@@ -342,7 +342,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     //             flop of the spectral sums; two levels: the replay repeats
     //             every update (5e10 link updates/s).
     // Measured per configuration (history / spectral, ms): 24^3x8, 9 probes,
-    // 100 updates 11.9 / 18.0; 24^3x8 in-plane map 18.1 / 19.4; 48^3x12 two
+    // 100 updates 11.7 / 18.0; 24^3x8 in-plane map 18.1 / 19.4; 48^3x12 two
     // levels 2 x 10, 1 probe 8.8 / 21.5, 8 probes 39.9 / 21.6.
     {
         bool plane_ok = true;
