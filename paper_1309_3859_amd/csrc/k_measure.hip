@@ -722,7 +722,7 @@ __global__ void __launch_bounds__(kInsThreads, 2) k_contract_ins(
 }
 
 // ---------------------------------------------------------------------------
-// The insertion averages of k_contract_ins on the matrix cores.  For one slot
+// The insertion averages of k_contract_ins (Sec. II.C.3) on the matrix cores.  For one slot
 // block (kMfSlots slots sharing (l, mode, spans)) and one position y of the
 // displaced lines,
 //   S[(r, c)][(k, kind)] = sum_m T_m^c(y - sh(r), r) O_m(y + ..., k, kind)
