@@ -423,21 +423,24 @@ def test_c1_statistical_parity_with_overrelaxation(env, precision):
     assert ok
 
 
-def test_results_independent_of_tile_batch_and_graphs(env):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_results_independent_of_tile_batch_and_graphs(env, kernel):
     """Same ensemble alone or inside a batch of uneven ensembles, any work-group
-    size, graphs on or off: bit-identical links and estimates."""
+    size, graphs on or off: bit-identical links and estimates, with either
+    insertion kernel (vector, matrix cores)."""
     u1, O, torch = env
     A = u1.Ens((6, 4, 4), 8, 1.0, seed=3, key_id=7)
     B = u1.Ens((4, 4, 8), 4, 0.9, seed=3, key_id=1)
     Cc = u1.Ens((8, 8, 4), 4, 1.05, seed=9, key_id=2)
     kw = dict(levels=[(4, 2, 1), (2, 2, 1)], r=[1, 2, 3], dirs=[0], probes=[(0, 0, 0, 1), (0, 1, 1, 1)],
-              comps=[0, 1, 5], precision=1, n_or=3, max_configs=2)
+              comps=[0, 1, 5], precision=1, n_or=3, max_configs=2, ins_kernel=kernel)
     runs = []
     for ens_list, idx, block, graphs in [([A], 0, 256, True), ([B, A, Cc], 1, 64, False), ([Cc, B, A], 2, 1024, True),
                                          ([A, B], 0, 128, False)]:
-        say("determinism", len(ens_list), block, graphs)
+        say("determinism", len(ens_list), block, graphs, kernel)
         spec = u1.Spec(ensembles=ens_list, **kw)
         ctx = u1.Context(spec)
+        assert (ctx.plan["ins_slots"] == 8) == (kernel == 2)
         ctx.set_block(block)
         ctx.set_graphs(graphs)
         ctx.init_links(1)
