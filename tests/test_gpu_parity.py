@@ -318,13 +318,18 @@ def test_insertion_contraction_slot_blocks_match_oracle(env, case, ns, dirs, pre
 #   between the 13 measurements (FP64 O rows: chunks of 4, the last one ragged);
 #   a strided 32-site axis with 9 separations (64 tiles: two passes; FP32 O
 #   rows, as FP64 rows of 32 sites exceed the chunk buffer);
-#   FP32 O rows on the 24-site line (9 identical measurements: chunks of 8)
+#   FP32 O rows on the 24-site line (9 identical measurements: chunks of 8);
+#   a strided 24-site axis (the vector kernel's build for 24-site lines with
+#   rows staged through registers; the matrix-core kernel's word copies, FP32
+#   and FP64 O rows)
 MFMA_CASES = {
     "octets_x": ((24, 6, 6), [0], list(range(1, 12)), [(2, 13, 1)], 0),
     "octets_x_still": ((24, 6, 6), [0], list(range(1, 12)), [(2, 5, 0)], 0),
     "passes_y": ((4, 32, 6), [1], list(range(1, 10)), [(2, 6, 1)], 1),
     "fp32_o": ((24, 6, 6), [0], list(range(1, 12)), [(2, 9, 0)], 1),
     "two_levels": ((24, 6, 4), [0], list(range(1, 12)), [(4, 2, 1), (2, 5, 1)], 0),
+    "strided_24_fp32": ((6, 24, 6), [1], list(range(1, 9)), [(2, 5, 0)], 1),
+    "strided_24_fp64": ((6, 24, 6), [1], list(range(1, 9)), [(2, 5, 0)], 0),
 }
 
 
