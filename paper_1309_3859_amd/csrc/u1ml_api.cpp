@@ -255,9 +255,10 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
     // slot keys of the insertion contraction: the (probe, component) pairs
     // of each probe group whose plaquettes span the axis, then those whose
     // plaquettes do not (probes, then components, in problem order); blocks
-    // of KS slots of one key, KS in {9, 6, 3, 1} leaving the fewest empty
-    // slots (the larger on a tie), or kMfSlots for the matrix-core kernel
-    // (the planner's choice, pack_slot_blocks)
+    // of KS slots of one key, KS in {9, 6, 3, 1} (FP64 O rows) or {3, 1}
+    // (FP32) leaving the fewest empty slots (the larger on a tie), or
+    // kMfSlots for the matrix-core kernel (the planner's choice,
+    // pack_slot_blocks)
     P->skeys.clear();
     P->skey_l.clear();
     P->skey_mode.clear();
@@ -275,9 +276,15 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
             P->skey_mode.push_back(P->gdesc[2 * g + 1]);
             P->skey_spans.push_back(sp);
         }
+    // FP32 O rows: blocks of 3 or 1 (each O value is converted to FP64 where
+    // it is read, once per slot and measurement for KR = 4 separations
+    // instead of 2; C2 FP32 11.51 against 11.72 ms per configuration with
+    // blocks of 9, while FP64 O rows keep 9: 16.80 against 17.05 ms)
     size_t best = ~(size_t)0;
     int best_ks = 1;
+    const bool fp32_o = P->precision == U1ML_FP32;
     for (int ks : {9, 6, 3, 1}) {
+        if (fp32_o && ks > 3) continue;
         size_t padded = 0;
         for (const auto& k : P->skeys) padded += (k.size() + ks - 1) / ks * ks;
         if (padded < best) {
@@ -332,7 +339,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     //   history:  contraction 6.6e12 FMA/s (the inner level's [TO] sums,
     //             vector kernel) or 0.18 of the FP64 matrix-core peak per
     //             16 x 16 x 4 step, padding included (matrix-core kernel:
-    //             3.3 ms per launch on the 24^3x8 workload below against 1.8 for the
+    //             3.3 ms per launch on the 24^3x8 workload below against 1.5 for the
     //             vector kernel; a plain stream of these steps runs at 46
     //             TFLOP/s on MI355X, FP64 vector FMA at 61);
     //             two levels: the inner averages folded into the outer sums,
@@ -342,7 +349,7 @@ bool compute_sizes(Problem& P, Sizes* S, u1ml_plan_info* info, Layout* Lo, std::
     //             flop of the spectral sums; two levels: the replay repeats
     //             every update (5e10 link updates/s).
     // Measured per configuration (history / spectral, ms): 24^3x8, 9 probes,
-    // 100 updates 11.7 / 18.0; 24^3x8 in-plane map 18.1 / 19.4; 48^3x12 two
+    // 100 updates 11.5 / 18.0; 24^3x8 in-plane map 18.1 / 19.4; 48^3x12 two
     // levels 2 x 10, 1 probe 8.8 / 21.5, 8 probes 39.9 / 21.6.
     {
         bool plane_ok = true;

@@ -164,7 +164,7 @@ def test_contraction_form_selection(u1):
 def test_contraction_form_follows_the_cost_estimates(u1):
     """AUTO takes the form with the smaller estimated device time.  The
     estimates order the forms as measured on MI355X (ms per configuration,
-    history / spectral): 24^3x8 with 9 probes 11.7 / 18.0, the in-plane map
+    history / spectral): 24^3x8 with 9 probes 11.5 / 18.0, the in-plane map
     18.1 / 19.4, 48^3x12 at 2 x 10 updates with 1 probe 8.8 / 21.5 and with
     8 probes 39.9 / 21.6; without probes there is nothing to estimate."""
     from paper_1309_3859_amd import configs
@@ -210,21 +210,25 @@ def test_large_bodies_are_launched_directly(u1):
 
 def test_insertion_kernel_choice(u1):
     """The history form's insertion sums run on the vector kernel (slot blocks
-    of 9, 6, 3 or 1) or on the matrix cores (blocks of 8), whichever is
-    estimated faster: on the 24^3x8 workload with 9 probes x 6 components x
-    11 separations the vector kernel (1.8 ms per launch on MI355X
-    against 3.3 ms); either can be asked for, and the matrix-core kernel only
-    where its chunk fits LDS (the estimate does not take it otherwise)."""
+    of 9, 6, 3 or 1 for FP64 O rows, 3 or 1 for FP32 ones, the fewest empty
+    slots) or on the matrix cores (blocks of 8), whichever is estimated
+    faster: on the 24^3x8 workload with 9 probes x 6 components x 11
+    separations the vector kernel (1.5 ms per launch on MI355X against 3.3
+    ms); either can be asked for, and the matrix-core kernel only where its
+    chunk fits LDS (the estimate does not take it otherwise)."""
     from paper_1309_3859_amd import configs
 
     spec, _ = configs.c2_fp32_profiles()
     auto = u1.plan(spec)
-    assert auto["ins_slots"] == 9
+    assert auto["ins_slots"] == 3
+    spec.precision = u1.FP64
+    assert u1.plan(spec)["ins_slots"] == 9
+    spec.precision = u1.FP32
     spec.ins_kernel = 2
     mf = u1.plan(spec)
     assert mf["ins_slots"] == 8 and mf["est_history_ms"] > auto["est_history_ms"]
     spec.ins_kernel = 1
-    assert u1.plan(spec)["ins_slots"] == 9
+    assert u1.plan(spec)["ins_slots"] == 3
     spec.ins_kernel = 3
     with pytest.raises(u1.U1MLError, match="EINVAL"):
         u1.plan(spec)

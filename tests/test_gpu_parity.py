@@ -298,7 +298,8 @@ SLOT_CASES = {
 @pytest.mark.parametrize("kernel", [1, 2])
 def test_insertion_contraction_slot_blocks_match_oracle(env, case, ns, dirs, precision, kernel):
     """The history-form insertion averages for every slot-block size of the
-    vector kernel (kernel 1) and the matrix-core kernel's blocks of 8 slots
+    vector kernel (kernel 1: 9, 6, 3, 1 with FP64 O rows, 3 and 1 with FP32
+    ones) and the matrix-core kernel's blocks of 8 slots
     (kernel 2, several blocks per work-group on these short lines), along a
     contiguous axis (x: chunks copied straight into LDS) and strided ones
     (y, z), against the oracle on the same links (no updates)."""
