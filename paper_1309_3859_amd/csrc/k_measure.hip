@@ -1065,11 +1065,11 @@ hipError_t launch_contract_ins(const EnsDesc* d_ens, const int* d_bstart, int n_
         default: U1ML_INS(double, ins_kr(1), 1); break;
         }
     } else {
-        // FP32 O rows come in blocks of 3 or 1 (the planner's rule)
         switch (slots_per_block) {
+        case 9: U1ML_INS(float, ins_kr(9), 9); break;
+        case 6: U1ML_INS(float, ins_kr(6), 6); break;
         case 3: U1ML_INS(float, ins_kr(3), 3); break;
-        case 1: U1ML_INS(float, ins_kr(1), 1); break;
-        default: return hipErrorInvalidValue;
+        default: U1ML_INS(float, ins_kr(1), 1); break;
         }
     }
 #undef U1ML_INS

@@ -255,10 +255,8 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
     // slot keys of the insertion contraction: the (probe, component) pairs
     // of each probe group whose plaquettes span the axis, then those whose
     // plaquettes do not (probes, then components, in problem order); blocks
-    // of KS slots of one key, KS in {9, 6, 3, 1} (FP64 O rows) or {3, 1}
-    // (FP32) leaving the fewest empty slots (the larger on a tie), or
-    // kMfSlots for the matrix-core kernel (the planner's choice,
-    // pack_slot_blocks)
+    // of KS slots of one key, KS in {9, 6, 3, 1}, or kMfSlots for the
+    // matrix-core kernel (the planner's choice, pack_slot_blocks)
     P->skeys.clear();
     P->skey_l.clear();
     P->skey_mode.clear();
@@ -276,19 +274,24 @@ bool read_problem(const u1ml_problem* p, Problem* P, std::string* err)
             P->skey_mode.push_back(P->gdesc[2 * g + 1]);
             P->skey_spans.push_back(sp);
         }
-    // FP32 O rows: blocks of 3 or 1 (each O value is converted to FP64 where
-    // it is read, once per slot and measurement for KR = 4 separations
-    // instead of 2; C2 FP32 11.51 against 11.72 ms per configuration with
-    // blocks of 9, while FP64 O rows keep 9: 16.80 against 17.05 ms)
-    size_t best = ~(size_t)0;
+    // the block size whose padded work (slots rounded up to whole blocks,
+    // separations to whole groups of ins_kr(KS)) is least; on a tie FP32 O
+    // rows take the smaller block (each O value is converted to FP64 where it
+    // is read, once per ins_kr(KS) separations: C2 FP32 11.51 ms per
+    // configuration with blocks of 3 against 11.72 with 9) and FP64 rows the
+    // larger (C2 FP64 16.80 ms with 9 against 17.05 with 3); blocks of 1 only
+    // where they pad least (eight separations per work-item form more T)
+    const size_t R_ = P->r.size();
+    double best = 1e300;
     int best_ks = 1;
     const bool fp32_o = P->precision == U1ML_FP32;
     for (int ks : {9, 6, 3, 1}) {
-        if (fp32_o && ks > 3) continue;
         size_t padded = 0;
         for (const auto& k : P->skeys) padded += (k.size() + ks - 1) / ks * ks;
-        if (padded < best) {
-            best = padded;
+        const int kr = ins_kr(ks);
+        const double work = (double)padded * (double)((R_ + kr - 1) / kr * kr);
+        if (work < best || (fp32_o && work == best && ks >= 3)) {
+            best = work;
             best_ks = ks;
         }
     }

@@ -286,6 +286,7 @@ def test_measurement_and_estimators_match_oracle(env, levels, precision):
 # x 3; 1: one slot)
 SLOT_CASES = {
     "blocks_of_9": ([(0, p1, p2, 1) for p1 in (-1, 0, 1) for p2 in (-1, 0, 1)], [0, 1, 2, 3, 4, 5]),
+    "blocks_of_9_one_r": ([(0, p1, p2, 1) for p1 in (-1, 0, 1) for p2 in (-1, 0, 1)], [0, 1, 2, 3, 4, 5], [2]),
     "blocks_of_6": ([(1, 0, 0, 1), (1, 1, 1, 1)], [0, 1, 2, 3, 4, 5]),
     "blocks_of_3": ([(-1, 1, 0, 0)], [0, 1, 2, 3, 4, 5]),
     "block_of_1": ([(0, 1, 1, 1)], [4]),
@@ -298,14 +299,16 @@ SLOT_CASES = {
 @pytest.mark.parametrize("kernel", [1, 2])
 def test_insertion_contraction_slot_blocks_match_oracle(env, case, ns, dirs, precision, kernel):
     """The history-form insertion averages for every slot-block size of the
-    vector kernel (kernel 1: 9, 6, 3, 1 with FP64 O rows, 3 and 1 with FP32
-    ones) and the matrix-core kernel's blocks of 8 slots
+    vector kernel (kernel 1: 9, 6, 3 and 1 with FP64 and FP32 O rows, the
+    planner's choice for each case) and the matrix-core kernel's blocks of 8
+    slots
     (kernel 2, several blocks per work-group on these short lines), along a
     contiguous axis (x: chunks copied straight into LDS) and strided ones
     (y, z), against the oracle on the same links (no updates)."""
-    probes, comps = SLOT_CASES[case]
+    probes, comps = SLOT_CASES[case][:2]
+    r = SLOT_CASES[case][2] if len(SLOT_CASES[case]) > 2 else [1, 2, 3]
     say("slot blocks", case, ns, dirs, precision, kernel)
-    got, want, ctx, _ = _multilevel_pair(env, ns, 8, [(2, 5, 0)], 3, [1, 2, 3], dirs, probes, comps,
+    got, want, ctx, _ = _multilevel_pair(env, ns, 8, [(2, 5, 0)], 3, r, dirs, probes, comps,
                                          precision=precision, ins_kernel=kernel)
     assert ctx.plan["form"] == env[0].FORM_HISTORY
     assert (ctx.plan["ins_slots"] == 8) == (kernel == 2), ctx.plan["ins_slots"]
