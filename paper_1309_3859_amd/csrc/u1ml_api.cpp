@@ -1433,7 +1433,9 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
                 while (mc > 4 && !mf_chunk_fits(mc, (int)nmax, (int)R, bpw * 2 * kMfSlots, (int)word)) mc -= 4;
                 return mc;
             };
-            while (E.ins_pbw > 1 && fit_mc(E.ins_pbw) < std::min(8, (P.n_i + 3) / 4 * 4)) --E.ins_pbw;
+            while (E.ins_pbw > 1 && (!mf_chunk_fits(4, (int)nmax, (int)R, E.ins_pbw * 2 * kMfSlots, (int)word) ||
+                                     fit_mc(E.ins_pbw) < std::min(8, (P.n_i + 3) / 4 * 4)))
+                --E.ins_pbw;
             const int mc = fit_mc(E.ins_pbw);
             if (!mf_chunk_fits(mc, (int)nmax, (int)R, E.ins_pbw * 2 * kMfSlots, (int)word)) {
                 release(c);
@@ -1453,7 +1455,10 @@ u1ml_status u1ml_create(const u1ml_problem* problem, void* d_ws, size_t ws_bytes
                 while (mc > 1 && !ins_chunk_fits(mc, (int)nmax, bpw * ks * 2, (int)word)) --mc;
                 return mc;
             };
-            while (E.ins_pbw > 1 && fit_mc(E.ins_pbw) < std::min(8, P.n_i)) --E.ins_pbw;
+            // (fewer also while not even one measurement fits)
+            while (E.ins_pbw > 1 && (!ins_chunk_fits(1, (int)nmax, E.ins_pbw * ks * 2, (int)word) ||
+                                     fit_mc(E.ins_pbw) < std::min(8, P.n_i)))
+                --E.ins_pbw;
             c->ins_block = std::max(c->ins_block, std::min(kInsThreads, (E.ins_pbw * unit + 63) / 64 * 64));
             const int nrows = E.ins_pbw * ks * 2;
             const int mc = fit_mc(E.ins_pbw);
